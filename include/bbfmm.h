@@ -1,0 +1,206 @@
+/*
+ * bbfmm.h — C ABI of the MI355X (gfx950) Chebyshev black-box FMM with a symmetry-blocked M2L.
+ *
+ * The method is the bbFMM of Sec. 2.1.1 of Messner, Bramas, Coulaud, Darve, "Optimized M2L
+ * kernels for the Chebyshev interpolation based fast multipole method": it approximates
+ *
+ *     phi_i = sum_{j != i} K(x_i, x_j) q_j          (Sec. 2, Eq. direct; sources = targets)
+ *
+ * with P2M/M2M (Eq. m2m_bbfmm), M2L (Eq. m2l_bbfmm) and L2L/L2P (Eq. l2l_bbfmm) on a uniform
+ * octree, plus a direct near field over the 27 neighbour leaves (Sec. 3.2). The M2L uses only
+ * the 16 operators of the cone t1 >= t2 >= t3 >= 0 (Eqs. z_sym, reduced_interaction_list), the
+ * other 300 being row/column permutations of them (Eqs. axial_permutation,
+ * diagonal_permutation, permutations), applied in blocks as dense matrix products (Sec. 4.2.3,
+ * Alg. BlockedM2L), optionally with each operator compressed by a truncated SVD (Eq. ialowrank).
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns a bbfmm_status; no C++ exception crosses this boundary. After a
+ *    non-OK status, bbfmm_last_error() returns a message (thread-local, valid until the next
+ *    call on the same thread).
+ *  - Pointers named d_* are HIP device memory owned by the CALLER. `stream` is a hipStream_t
+ *    (NULL = the default stream). Work is enqueued on `stream`; apply-type calls return before
+ *    the GPU finishes, the caller synchronises. Build and precompute synchronise `stream`.
+ *  - Arguments are validated on the host before any HIP call; invalid ones give BBFMM_EINVAL
+ *    and leave outputs untouched.
+ *  - Point and density arrays are row-major in the caller's order; the library sorts points
+ *    into leaf (Morton) order internally and returns results in the caller's order.
+ *  - Trees and plans own their device buffers (allocated by build/precompute, and by apply when
+ *    a larger nrhs than before is requested), released by the matching *_destroy.
+ *  - One plan runs one apply-type call at a time (its work buffers are shared); overlapping
+ *    calls on the same plan from different streams race. A plan must not outlive its tree.
+ */
+#ifndef BBFMM_H
+#define BBFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BBFMM_OK = 0,
+  BBFMM_EINVAL = -1,        /* invalid argument (null pointer, size, non-finite or out-of-box point) */
+  BBFMM_ENOMEM = -2,        /* device or host allocation failed */
+  BBFMM_EHIP = -3,          /* a HIP runtime call failed */
+  BBFMM_EUNSUPPORTED = -4,  /* valid but not supported by this build (e.g. order outside [2, 8]) */
+  BBFMM_ESTATE = -5         /* object in the wrong state (e.g. gradient requested before apply) */
+} bbfmm_status;
+
+/* Kernel functions. 1/r is the Laplace kernel of Sec. 5, Eq. (kernel_functions), without the
+ * 1/(4 pi) factor. The polynomial kernels are exactly interpolated for orders >= 3 and >= 5
+ * and exist for verification. */
+typedef enum {
+  BBFMM_K_INV_R = 0,            /* 1/r, 0 at r = 0; homogeneous of degree -1 */
+  BBFMM_K_INV_SQRT_R2C2 = 1,    /* 1/sqrt(r^2 + c^2); not homogeneous: operators per level */
+  BBFMM_K_R2 = 100,             /* r^2; homogeneous of degree 2 */
+  BBFMM_K_R4 = 101              /* r^4; homogeneous of degree 4 */
+} bbfmm_kernel;
+
+/* Arithmetic of the M2L matrix products. Everything else (precompute, SVD, P2M, M2M, L2L, L2P,
+ * near field) is FP64 in every mode. */
+typedef enum {
+  BBFMM_M2L_FP64 = 0,     /* FP64 MFMA */
+  BBFMM_M2L_FP32 = 1,     /* FP32 operands and FP32 MFMA accumulation, flushed to FP64 per
+                             unique operator */
+  BBFMM_M2L_SPLIT32 = 2   /* hi/lo FP32 split of operator and multipoles, three FP32 MFMA
+                             products (hi*hi + hi*lo + lo*hi), flushed to FP64 per operator */
+} bbfmm_m2l_prec;
+
+typedef struct {
+  int32_t depth;            /* leaf level of the uniform octree, 0..8 (level l has 8^l cells) */
+  int32_t max_leaf_points;  /* reserved (adaptive trees); must be 0 */
+  double root_lo[3];        /* lower corner of the root cube (used when root_width > 0) */
+  double root_width;        /* > 0: root cube [lo, lo + width)^3, every point must lie in it;
+                               <= 0: tight bounding cube of the points, enlarged by 1e-12
+                               relative so that the top faces are inside */
+} bbfmm_tree_opts;
+
+typedef struct {
+  int32_t kernel;    /* bbfmm_kernel */
+  double c;          /* regularisation of BBFMM_K_INV_SQRT_R2C2 (> 0), ignored otherwise */
+  int32_t order;     /* Chebyshev order l in [2, 8]; l^3 interpolation points per cell */
+  double svd_eps;    /* <= 0: full-rank operators (variant NAblk); > 0: each of the 16 operators
+                        truncated to the singular values > svd_eps * sigma_1, extended over a
+                        tied cluster at the cut (variant IAblk) */
+  int32_t m2l_prec;  /* bbfmm_m2l_prec */
+} bbfmm_plan_opts;
+
+typedef struct {
+  int64_t n_points;
+  int32_t depth, order, n_levels_m2l;   /* M2L runs on levels 2..depth */
+  int32_t n_operator_sets;              /* 1 for homogeneous kernels, depth-1 otherwise */
+  int32_t rank[16];                     /* rank of each unique operator (order^3 if full) */
+  double root_lo[3], root_width;
+  int64_t pairs_total;                  /* far pairs of all M2L levels with both cells in the box */
+  int64_t pairs_nonempty;               /* ... of which both cells hold points (plan_stats only) */
+  double m2l_flops_algorithmic;         /* per right-hand side: sum over non-empty pairs of
+                                           2 l^6 (full) or 4 l^3 r_p (compressed) */
+  double m2l_flops_issued;              /* per right-hand side, MFMA work including padding */
+  double precompute_seconds;            /* host time of bbfmm_precompute_m2l */
+  int64_t device_bytes;                 /* device memory held by tree + plan */
+} bbfmm_stats;
+
+typedef struct bbfmm_tree bbfmm_tree;
+typedef struct bbfmm_plan bbfmm_plan;
+
+/* Builds the uniform octree of Sec. 3 (Alg. SeparateNearAndFarField, smooth branch): each point
+ * goes to leaf floor((x - lo) / w_leaf) per axis, clamped into the root; points are counting-
+ * sorted into Morton leaf order (ties kept in input order) and leaf offsets are stored.
+ * d_points: n x 3 row-major FP64 device array (copied; may be freed after the call).
+ * Errors: EINVAL for n < 1, null pointers, depth outside [0, 8], max_leaf_points != 0, a
+ * non-finite coordinate, or (root_width > 0) a point outside the root cube. */
+bbfmm_status bbfmm_build_octree(const double* d_points, int64_t n, const bbfmm_tree_opts* opts,
+                                void* stream, bbfmm_tree** out);
+
+/* Precomputes the M2L operators of Sec. 3.1, Eq. (m2lmatrix) for the 16 transfer vectors of
+ * T_sym (Eq. reduced_interaction_list) in FP64 on the host, at unit cell width for homogeneous
+ * kernels (scaled per level, Sec. 3.2) or at every level's width otherwise; compresses each by
+ * a truncated SVD when svd_eps > 0 (Eq. ialowrank); builds the per-octant interaction tables
+ * (189 transfer vectors, their representative p(t) and permutation sigma_t, Eqs.
+ * axial_permutation and diagonal_permutation) and the 1-D interpolation matrices of M2M/L2L;
+ * uploads everything. `tree` is borrowed and must outlive the plan.
+ * Errors: EINVAL (null, c <= 0 for INV_SQRT_R2C2, unknown kernel or precision),
+ * EUNSUPPORTED (order outside [2, 8]). */
+bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts* opts,
+                                  void* stream, bbfmm_plan** out);
+
+/* phi = A q: P2M -> M2M -> M2L (levels 2..depth) -> L2L -> L2P plus the near field, FP64 output.
+ * d_q, d_phi: n x nrhs row-major FP64 device arrays in the caller's point order; d_phi is
+ * overwritten. The leaf locals are kept in the plan for bbfmm_eval_grad.
+ * Errors: EINVAL (null, nrhs < 1 or > 64, d_q == d_phi), ENOMEM. */
+bbfmm_status bbfmm_apply(bbfmm_plan* plan, const double* d_q, int32_t nrhs, double* d_phi,
+                         void* stream);
+
+/* grad_q = A^T g through the transposed chain L2P^T, L2L^T, M2L^T (K_t^T = K_{-t}), M2M^T,
+ * P2M^T and the transposed near field. For the symmetric kernels supported here, with one point
+ * set as sources and targets, A^T = A, so this runs the forward passes on g; the leaf adjoint
+ * locals are kept for bbfmm_eval_grad. Same argument rules as bbfmm_apply. */
+bbfmm_status bbfmm_apply_adjoint(bbfmm_plan* plan, const double* d_g, int32_t nrhs,
+                                 double* d_grad_q, void* stream);
+
+/* d/dx_i of L = sum_k g_k . phi_k(x) with the tree held fixed (cell membership and centres),
+ * for L computed by bbfmm_apply(q) and bbfmm_apply_adjoint(g) with the same nrhs, which must
+ * both have been called on this plan, in either order, since the last change of q or g:
+ * grad_x_i = g_i . grad L2P(F^(q))(x_i) + q_i . grad L2P(F^(g))(x_i)
+ *          + sum_{j near, j != i} grad_x K(x_i, x_j) (g_i . q_j + q_i . g_j).
+ * roles: 1 = target role only (first and the g_i q_j part of the third term), 2 = source role
+ * only, 3 = both (the full derivative). d_grad_x: n x 3 row-major FP64, overwritten.
+ * Errors: EINVAL, ESTATE (apply or apply_adjoint missing, or nrhs mismatch). */
+bbfmm_status bbfmm_eval_grad(bbfmm_plan* plan, const double* d_q, const double* d_g, int32_t nrhs,
+                             int32_t roles, double* d_grad_x, void* stream);
+
+/* Fills `out`; counts non-empty pairs on the device (synchronises the plan's last stream). */
+bbfmm_status bbfmm_plan_stats(const bbfmm_plan* plan, bbfmm_stats* out);
+
+void bbfmm_plan_destroy(bbfmm_plan* plan);
+void bbfmm_tree_destroy(bbfmm_tree* tree);
+const char* bbfmm_last_error(void);
+const char* bbfmm_version(void);
+
+/* ---------------------------------------------------------------------------------------
+ * Inspection entry points (testing and measurement). Expansion arrays are in the library's
+ * layout: cells of a level in Morton order (x bit lowest), each cell l^3 interpolation points in
+ * the order m(a) = a1 + l a2 + l^2 a3 of Sec. 3.1, each point nrhs values.
+ * --------------------------------------------------------------------------------------- */
+
+/* Copies expansions of `level` from the last apply-type call: which = 0 multipoles W,
+ * 1 M2L output (before L2L), 2 locals after L2L. d_out: 8^level * l^3 * nrhs FP64.
+ * Errors: EINVAL (level outside [2, depth], which outside [0, 2]), ESTATE (no apply yet). */
+bbfmm_status bbfmm_debug_get_expansions(const bbfmm_plan* plan, int32_t level, int32_t which,
+                                        double* d_out, void* stream);
+
+/* Runs only the M2L of `level` on caller multipoles d_w (layout above) and writes the M2L
+ * output to d_f (overwritten), with the plan's operators and precision. */
+bbfmm_status bbfmm_debug_m2l_level(bbfmm_plan* plan, int32_t level, const double* d_w,
+                                   int32_t nrhs, double* d_f, void* stream);
+
+/* Sorted-order permutation of the tree: d_perm[i] = caller index of the i-th point in leaf
+ * order (n int32), and d_leaf_start (8^depth + 1 int32 offsets into that order). */
+bbfmm_status bbfmm_debug_tree_order(const bbfmm_tree* tree, int32_t* d_perm, int32_t* d_leaf_start,
+                                    void* stream);
+
+/* Host-only helpers (no GPU needed): the 16 representative transfer vectors in the library's
+ * order (out_t: 16 x 3), and for transfer vector t (|t_i| <= 3, max |t_i| >= 2) the index of
+ * p(t) in that list and the permutation sigma_t with K_t[i][j] = K_p[sigma[i]][sigma[j]]
+ * (out_sigma: order^3 int32). */
+bbfmm_status bbfmm_host_symmetry(int32_t order, const int32_t t[3], int32_t* out_t16,
+                                 int32_t* out_p, int32_t* out_sigma);
+
+/* Host-only: the library's precomputed operator of representative `p` (0..15) at cell width
+ * `width`: full matrix (l^3 x l^3 row-major) into out_k, and when svd_eps > 0 the factors
+ * U (l^3 x r, = U_r Sigma_r) and V (l^3 x r) into out_u / out_v (each l^6 doubles capacity) with
+ * the rank in *out_rank. */
+bbfmm_status bbfmm_host_operator(int32_t kernel, double c, int32_t order, double width,
+                                 int32_t p, double svd_eps, double* out_k, double* out_u,
+                                 double* out_v, int32_t* out_rank);
+
+/* Host-only: singular values of a row-major m x n matrix (m >= n) by the library's one-sided
+ * Jacobi SVD, descending, into out_s (n doubles). */
+bbfmm_status bbfmm_host_singular_values(const double* a, int32_t m, int32_t n, double* out_s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BBFMM_H */

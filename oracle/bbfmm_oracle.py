@@ -381,13 +381,16 @@ def m2l_level(w: np.ndarray, level: int, width: float, order: int, kind: str, c:
     wl = width / (1 << level)
     for t, (xi, yi) in interaction_pairs(level).items():
         kt = m2l_operator(t, wl, order, kind, c)
+        # all pairs sharing t as one product K_t [W_Y1, W_Y2, ...] (columns = pairs x rhs)
+        cols = w[yi].transpose(1, 0, 2).reshape(w.shape[1], -1)
         if eps > 0:
             u, v, _ = compress(kt, eps)
-            f[xi] += np.matmul(u, np.matmul(v.T, w[yi]))
+            prod = u @ (v.T @ cols)
             if stats is not None:
                 stats.setdefault("ranks", {})[(level, t)] = u.shape[1]
         else:
-            f[xi] += np.matmul(kt, w[yi])
+            prod = kt @ cols
+        f[xi] += prod.reshape(w.shape[1], xi.size, w.shape[2]).transpose(1, 0, 2)
         if stats is not None:
             stats["pairs"] = stats.get("pairs", 0) + xi.size
     return f
@@ -582,12 +585,14 @@ def _adjoint_leaf_locals(points, g, order, depth, kind, c, eps, lo, width) -> np
         wb = np.zeros_like(fbar[lev])
         for t, (xi, yi) in interaction_pairs(lev).items():
             kt = m2l_operator(t, wl, order, kind, c)
+            cols = fbar[lev][xi].transpose(1, 0, 2).reshape(fbar[lev].shape[1], -1)
             if eps > 0:
                 u, v, _ = compress(kt, eps)
-                contrib = np.matmul(v, np.matmul(u.T, fbar[lev][xi]))
+                prod = v @ (u.T @ cols)
             else:
-                contrib = np.matmul(kt.T, fbar[lev][xi])
-            np.add.at(wb, yi, contrib)
+                prod = kt.T @ cols
+            # within one t every source cell occurs once
+            wb[yi] += prod.reshape(fbar[lev].shape[1], yi.size, fbar[lev].shape[2]).transpose(1, 0, 2)
         wbar[lev] = wb
     for lev in range(3, depth + 1):
         gp = _grid(wbar[lev - 1], lev - 1)

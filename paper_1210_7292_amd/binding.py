@@ -1,0 +1,278 @@
+"""ctypes binding of libbbfmm.so with the names of the C ABI (include/bbfmm.h)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libbbfmm.so")
+
+KERNELS = {"inv_r": 0, "inv_sqrt_r2c2": 1, "r2": 100, "r4": 101}
+PRECISIONS = {"fp64": 0, "fp32": 1, "split32": 2}
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED", -5: "ESTATE"}
+
+
+class BBFMMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bbfmm {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class TreeOpts(C.Structure):
+    _fields_ = [("depth", C.c_int32), ("max_leaf_points", C.c_int32),
+                ("root_lo", C.c_double * 3), ("root_width", C.c_double)]
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("c", C.c_double), ("order", C.c_int32),
+                ("svd_eps", C.c_double), ("m2l_prec", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_points", C.c_int64), ("depth", C.c_int32), ("order", C.c_int32),
+                ("n_levels_m2l", C.c_int32), ("n_operator_sets", C.c_int32),
+                ("rank", C.c_int32 * 16), ("root_lo", C.c_double * 3), ("root_width", C.c_double),
+                ("pairs_total", C.c_int64), ("pairs_nonempty", C.c_int64),
+                ("m2l_flops_algorithmic", C.c_double), ("m2l_flops_issued", C.c_double),
+                ("precompute_seconds", C.c_double), ("device_bytes", C.c_int64)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported symbol declared in include/bbfmm.h
+_P = C.c_void_p
+SIGNATURES = [
+    ("bbfmm_build_octree", C.c_int, [_P, C.c_int64, C.POINTER(TreeOpts), _P, C.POINTER(_P)]),
+    ("bbfmm_precompute_m2l", C.c_int, [_P, C.POINTER(PlanOpts), _P, C.POINTER(_P)]),
+    ("bbfmm_apply", C.c_int, [_P, _P, C.c_int32, _P, _P]),
+    ("bbfmm_apply_adjoint", C.c_int, [_P, _P, C.c_int32, _P, _P]),
+    ("bbfmm_eval_grad", C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
+    ("bbfmm_plan_stats", C.c_int, [_P, C.POINTER(Stats)]),
+    ("bbfmm_plan_destroy", None, [_P]),
+    ("bbfmm_tree_destroy", None, [_P]),
+    ("bbfmm_last_error", C.c_char_p, []),
+    ("bbfmm_version", C.c_char_p, []),
+    ("bbfmm_debug_get_expansions", C.c_int, [_P, C.c_int32, C.c_int32, _P, _P]),
+    ("bbfmm_debug_m2l_level", C.c_int, [_P, C.c_int32, _P, C.c_int32, _P, _P]),
+    ("bbfmm_debug_tree_order", C.c_int, [_P, _P, _P, _P]),
+    ("bbfmm_host_symmetry", C.c_int, [C.c_int32, _P, _P, _P, _P]),
+    ("bbfmm_host_operator", C.c_int, [C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_int32,
+                                      C.c_double, _P, _P, _P, _P]),
+    ("bbfmm_host_singular_values", C.c_int, [_P, C.c_int32, C.c_int32, _P]),
+]
+
+
+def lib() -> C.CDLL:
+    """Loads libbbfmm.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise BBFMMError(-3, f"{_LIB_PATH} is missing: run `python -m paper_1210_7292_amd.build_lib`")
+        h = C.CDLL(_LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise BBFMMError(status, lib().bbfmm_last_error().decode())
+
+
+def _stream(torch_mod, device) -> Optional[int]:
+    return torch_mod.cuda.current_stream(device).cuda_stream
+
+
+def _dev_ptr(t, dtype, shape_last=None, name="tensor"):
+    import torch
+    if not t.is_cuda:
+        raise BBFMMError(-1, f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise BBFMMError(-1, f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise BBFMMError(-1, f"{name} must be contiguous")
+    if shape_last is not None and (t.dim() != 2 or t.shape[1] != shape_last):
+        raise BBFMMError(-1, f"{name} must have shape (n, {shape_last})")
+    return C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------- C-ABI names
+
+
+def build_octree(points, depth: int, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0):
+    """bbfmm_build_octree on an (n, 3) float64 device tensor; returns an opaque tree handle."""
+    import torch
+    p = _dev_ptr(points, torch.float64, 3, "points")
+    o = TreeOpts(int(depth), 0, (C.c_double * 3)(*[float(v) for v in root_lo]), float(root_width))
+    out = C.c_void_p()
+    _check(lib().bbfmm_build_octree(p, points.shape[0], C.byref(o), _P(_stream(torch, points.device)),
+                                    C.byref(out)))
+    return out
+
+
+def precompute_m2l(tree, kernel: str = "inv_r", order: int = 5, svd_eps: float = 0.0,
+                   m2l_prec: str = "fp64", c: float = 0.0, device=None):
+    import torch
+    o = PlanOpts(KERNELS[kernel], float(c), int(order), float(svd_eps), PRECISIONS[m2l_prec])
+    out = C.c_void_p()
+    _check(lib().bbfmm_precompute_m2l(tree, C.byref(o), _P(_stream(torch, device)), C.byref(out)))
+    return out
+
+
+def apply(plan, q, out=None):
+    """bbfmm_apply: phi = A q for q of shape (n, nrhs) float64 on the device."""
+    import torch
+    qp = _dev_ptr(q, torch.float64, None, "q")
+    out = torch.empty_like(q) if out is None else out
+    _check(lib().bbfmm_apply(plan, qp, q.shape[1], _dev_ptr(out, torch.float64, q.shape[1], "out"),
+                             _P(_stream(torch, q.device))))
+    return out
+
+
+def apply_adjoint(plan, g, out=None):
+    import torch
+    gp = _dev_ptr(g, torch.float64, None, "g")
+    out = torch.empty_like(g) if out is None else out
+    _check(lib().bbfmm_apply_adjoint(plan, gp, g.shape[1], _dev_ptr(out, torch.float64, g.shape[1], "out"),
+                                     _P(_stream(torch, g.device))))
+    return out
+
+
+def eval_grad(plan, q, g, roles: int = 3, out=None):
+    import torch
+    n = q.shape[0]
+    out = torch.empty((n, 3), dtype=torch.float64, device=q.device) if out is None else out
+    _check(lib().bbfmm_eval_grad(plan, _dev_ptr(q, torch.float64, None, "q"),
+                                 _dev_ptr(g, torch.float64, q.shape[1], "g"), q.shape[1], int(roles),
+                                 _dev_ptr(out, torch.float64, 3, "out"), _P(_stream(torch, q.device))))
+    return out
+
+
+def plan_stats(plan) -> dict:
+    s = Stats()
+    _check(lib().bbfmm_plan_stats(plan, C.byref(s)))
+    d = {k: getattr(s, k) for k, _ in Stats._fields_}
+    d["rank"] = list(s.rank)
+    d["root_lo"] = list(s.root_lo)
+    return d
+
+
+def host_symmetry(order: int, t):
+    """(list of the 16 representatives, index of p(t), sigma_t) from the library's host tables."""
+    t16 = (C.c_int32 * 48)()
+    pidx = C.c_int32()
+    sig = np.zeros(order ** 3, dtype=np.int32)
+    tt = (C.c_int32 * 3)(*[int(v) for v in t])
+    _check(lib().bbfmm_host_symmetry(order, tt, t16, C.byref(pidx), sig.ctypes.data_as(_P)))
+    reps = [tuple(t16[3 * i:3 * i + 3]) for i in range(16)]
+    return reps, pidx.value, sig
+
+
+def host_operator(kernel: str, order: int, width: float, p: int, svd_eps: float = 0.0, c: float = 0.0):
+    nn = order ** 3
+    k = np.zeros((nn, nn))
+    u = np.zeros(nn * nn)
+    v = np.zeros(nn * nn)
+    r = C.c_int32()
+    _check(lib().bbfmm_host_operator(KERNELS[kernel], float(c), order, float(width), p, float(svd_eps),
+                                     k.ctypes.data_as(_P), u.ctypes.data_as(_P), v.ctypes.data_as(_P),
+                                     C.byref(r)))
+    rr = r.value
+    return k, u[:nn * rr].reshape(nn, rr), v[:nn * rr].reshape(nn, rr), rr
+
+
+def host_singular_values(a: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    m, n = a.shape
+    s = np.zeros(n)
+    _check(lib().bbfmm_host_singular_values(a.ctypes.data_as(_P), m, n, s.ctypes.data_as(_P)))
+    return s
+
+
+# ---------------------------------------------------------------------------- objects
+
+
+class Octree:
+    """Owns a bbfmm_tree built from an (n, 3) float64 device tensor."""
+
+    def __init__(self, points, depth: int, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0):
+        self.n = points.shape[0]
+        self.depth = depth
+        self.device = points.device
+        self.handle = build_octree(points, depth, root_lo, root_width)
+
+    def order(self):
+        """(perm, leaf_start): caller index of each sorted point and the leaf offsets."""
+        import torch
+        perm = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        ls = torch.empty(8 ** self.depth + 1, dtype=torch.int32, device=self.device)
+        _check(lib().bbfmm_debug_tree_order(self.handle, _P(perm.data_ptr()), _P(ls.data_ptr()),
+                                            _P(_stream(torch, self.device))))
+        return perm, ls
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.bbfmm_tree_destroy(h)
+            self.handle = None
+
+
+class Plan:
+    """Owns a bbfmm_plan (operators + work buffers) on a tree."""
+
+    def __init__(self, tree: Octree, kernel: str = "inv_r", order: int = 5, svd_eps: float = 0.0,
+                 m2l_prec: str = "fp64", c: float = 0.0):
+        self.tree = tree            # keeps the tree alive
+        self.order = order
+        self.kernel = kernel
+        self.handle = precompute_m2l(tree.handle, kernel, order, svd_eps, m2l_prec, c, tree.device)
+
+    def apply(self, q, out=None):
+        return apply(self.handle, q, out)
+
+    def apply_adjoint(self, g, out=None):
+        return apply_adjoint(self.handle, g, out)
+
+    def eval_grad(self, q, g, roles: int = 3, out=None):
+        return eval_grad(self.handle, q, g, roles, out)
+
+    def stats(self) -> dict:
+        return plan_stats(self.handle)
+
+    def expansions(self, level: int, which: int, nrhs: int):
+        """Copies W (0), the M2L output (1) or the locals (2) of `level` (Morton cell order)."""
+        import torch
+        out = torch.empty((8 ** level, self.order ** 3, nrhs), dtype=torch.float64, device=self.tree.device)
+        _check(lib().bbfmm_debug_get_expansions(self.handle, level, which, _P(out.data_ptr()),
+                                                _P(_stream(torch, self.tree.device))))
+        return out
+
+    def m2l_level(self, level: int, w):
+        """Runs only the M2L of `level` on multipoles w (8^level, l^3, nrhs) in Morton order."""
+        import torch
+        f = torch.empty_like(w)
+        _check(lib().bbfmm_debug_m2l_level(self.handle, level, _dev_ptr(w, torch.float64, None, "w"),
+                                           w.shape[2], _P(f.data_ptr()), _P(_stream(torch, w.device))))
+        return f
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.bbfmm_plan_destroy(h)
+            self.handle = None
+
+
+def fmm_apply(points, q, depth: int, order: int, kernel: str = "inv_r", svd_eps: float = 0.0,
+              m2l_prec: str = "fp64", c: float = 0.0, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0):
+    """One-shot build_octree + precompute_m2l + apply."""
+    tree = Octree(points, depth, root_lo, root_width)
+    plan = Plan(tree, kernel, order, svd_eps, m2l_prec, c)
+    if q.dim() == 1:
+        return plan.apply(q.reshape(-1, 1).contiguous()).reshape(-1)
+    return plan.apply(q)

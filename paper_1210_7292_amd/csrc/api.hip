@@ -1,0 +1,629 @@
+// C ABI of the bbFMM library (include/bbfmm.h): argument validation, object lifetimes,
+// host precompute and upload, and the stream-ordered pass sequence of an apply.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace bbfmm {
+
+static thread_local std::string g_last_error;
+
+void set_error(bbfmm_status code, const std::string& msg) {
+  (void)code;
+  g_last_error = msg;
+}
+
+namespace {
+
+bbfmm_status fail(bbfmm_status code, const std::string& msg) {
+  set_error(code, msg);
+  return code;
+}
+
+template <typename T>
+hipError_t dmalloc(T** p, size_t count, long long* bytes) {
+  *p = nullptr;
+  if (count == 0) return hipSuccess;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e == hipSuccess && bytes) *bytes += (long long)(count * sizeof(T));
+  return e;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+PassGeom geom_of(const bbfmm_plan* pl) {
+  const bbfmm_tree* t = pl->tree;
+  PassGeom g;
+  g.xs = t->xs; g.ys = t->ys; g.zs = t->zs;
+  g.perm = t->perm; g.leaf_of = t->leaf_of; g.leaf_start = t->leaf_start;
+  g.n = t->n; g.depth = t->depth;
+  for (int r = 0; r < 3; ++r) g.lo[r] = t->lo[r];
+  g.width = t->width;
+  g.tk = pl->d_tk; g.m2m = pl->d_m2m;
+  g.order = pl->order; g.kernel = pl->kernel; g.c = pl->c;
+  return g;
+}
+
+bool valid_kernel(int k) { return k == kInvR || k == kInvSqrtR2C2 || k == kR2 || k == kR4; }
+
+void free_buffers(bbfmm_plan* p) {
+  dfree(p->W); p->W = nullptr;
+  for (int s = 0; s < 2; ++s) {
+    dfree(p->F[s]); p->F[s] = nullptr;
+    dfree(p->qs[s]); p->qs[s] = nullptr;
+    p->slot_nrhs[s] = 0;
+  }
+  dfree(p->phis); p->phis = nullptr;
+  p->nrhs_cap = 0;
+  p->buffer_bytes = 0;
+}
+
+bbfmm_status ensure_buffers(bbfmm_plan* p, int nrhs, int slot) {
+  const bbfmm_tree* t = p->tree;
+  if (nrhs > p->nrhs_cap) {
+    free_buffers(p);
+    long long bytes = 0;
+    if (t->depth >= 2) {
+      BBFMM_HIP_TRY(dmalloc(&p->W, (size_t)p->exp_elems * nrhs, &bytes));
+      BBFMM_HIP_TRY(dmalloc(&p->F[0], (size_t)p->exp_elems * nrhs, &bytes));
+      BBFMM_HIP_TRY(dmalloc(&p->phis, (size_t)t->n * nrhs, &bytes));
+    }
+    BBFMM_HIP_TRY(dmalloc(&p->qs[0], (size_t)t->n * nrhs, &bytes));
+    p->nrhs_cap = nrhs;
+    p->buffer_bytes = bytes;
+  }
+  if (slot == 1 && p->qs[1] == nullptr) {
+    long long bytes = 0;
+    if (t->depth >= 2) BBFMM_HIP_TRY(dmalloc(&p->F[1], (size_t)p->exp_elems * p->nrhs_cap, &bytes));
+    BBFMM_HIP_TRY(dmalloc(&p->qs[1], (size_t)t->n * p->nrhs_cap, &bytes));
+    p->buffer_bytes += bytes;
+  }
+  return BBFMM_OK;
+}
+
+M2LArgs m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double* F, int only_level) {
+  const bbfmm_tree* t = p->tree;
+  M2LArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nrhs = nrhs;
+  int blocks = 0, k = 0;
+  for (int l = t->depth; l >= 2; --l) {
+    if (only_level >= 0 && l != only_level) continue;
+    M2LLevel& lv = a.lv[k++];
+    lv.W = only_level >= 0 ? W : W + p->level_off[l] * nrhs;
+    lv.F = only_level >= 0 ? F : F + p->level_off[l] * nrhs;
+    lv.level = l;
+    lv.side = 1 << l;
+    lv.npar = 1 << (3 * (l - 1));
+    const long long cols = (long long)lv.npar * nrhs;
+    lv.ntiles = (int)((cols + 63) / 64);
+    lv.block_begin = blocks;
+    blocks += 8 * lv.ntiles;
+    lv.set = p->set_of_level[l];
+    lv.scale = p->scale_of_level[l];
+  }
+  a.nlev = k;
+  a.nblocks = blocks;
+  a.ops_hi = p->ops_hi; a.ops_lo = p->ops_lo;
+  a.op_off = p->d_op_off; a.op_rank = p->d_op_rank;
+  a.tab = p->d_tab; a.grp = p->d_grp; a.sig = p->d_sig; a.siginv = p->d_siginv;
+  return a;
+}
+
+// One forward pass of the chain on `in` (caller order) into `out` (caller order); slot 0 keeps
+// the locals of an apply, slot 1 those of an adjoint apply.
+bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, int slot,
+                       hipStream_t s) {
+  bbfmm_status st = ensure_buffers(p, nrhs, slot);
+  if (st != BBFMM_OK) return st;
+  const bbfmm_tree* t = p->tree;
+  const PassGeom g = geom_of(p);
+  double* qs = p->qs[slot];
+  BBFMM_HIP_TRY(launch_gather_rows(in, t->perm, t->n, nrhs, qs, s));
+  const double* far = nullptr;
+  if (t->depth >= 2) {
+    double* W = p->W;
+    double* F = p->F[slot];
+    const int d = t->depth;
+    BBFMM_HIP_TRY(launch_p2m(g, qs, nrhs, W + p->level_off[d] * nrhs, s));
+    for (int l = d - 1; l >= 2; --l)
+      BBFMM_HIP_TRY(launch_m2m(g, l, W + p->level_off[l + 1] * nrhs, W + p->level_off[l] * nrhs, nrhs, s));
+    const M2LArgs a = m2l_args(p, nrhs, W, F, -1);
+    BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, s));
+    for (int l = 3; l <= d; ++l)
+      BBFMM_HIP_TRY(launch_l2l(g, l - 1, F + p->level_off[l - 1] * nrhs, F + p->level_off[l] * nrhs, nrhs, s));
+    BBFMM_HIP_TRY(launch_l2p(g, F + p->level_off[d] * nrhs, nrhs, p->phis, s));
+    far = p->phis;
+  }
+  BBFMM_HIP_TRY(launch_p2p_scatter(g, qs, far, nrhs, out, s));
+  p->slot_nrhs[slot] = nrhs;
+  return BBFMM_OK;
+}
+
+std::vector<int> octant_tables(std::vector<int>* grp) {
+  std::vector<int> tab(8 * kFarPerOctant);
+  grp->assign(8 * 17, 0);
+  for (int o = 0; o < 8; ++o) octant_table(o, &tab[o * kFarPerOctant], &(*grp)[o * 17]);
+  return tab;
+}
+
+}  // namespace
+}  // namespace bbfmm
+
+using namespace bbfmm;
+
+extern "C" {
+
+const char* bbfmm_last_error(void) { return g_last_error.c_str(); }
+const char* bbfmm_version(void) { return "bbfmm-gfx950 0.1"; }
+
+bbfmm_status bbfmm_build_octree(const double* d_points, int64_t n, const bbfmm_tree_opts* opts,
+                                void* stream, bbfmm_tree** out) {
+  if (!out) return fail(BBFMM_EINVAL, "out is null");
+  *out = nullptr;
+  if (!d_points || !opts) return fail(BBFMM_EINVAL, "null points or options");
+  if (n < 1 || n > 0x7fffffffLL) return fail(BBFMM_EINVAL, "n must be in [1, 2^31 - 1]");
+  if (opts->depth < 0 || opts->depth > kMaxDepth)
+    return fail(BBFMM_EINVAL, "depth must be in [0, 8] (adaptive trees are not supported)");
+  if (opts->max_leaf_points != 0) return fail(BBFMM_EINVAL, "max_leaf_points must be 0");
+  if (opts->root_width > 0) {
+    for (int r = 0; r < 3; ++r)
+      if (!std::isfinite(opts->root_lo[r])) return fail(BBFMM_EINVAL, "root_lo is not finite");
+    if (!std::isfinite(opts->root_width)) return fail(BBFMM_EINVAL, "root_width is not finite");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<bbfmm_tree> t(new (std::nothrow) bbfmm_tree());
+  if (!t) return fail(BBFMM_ENOMEM, "host allocation");
+  BBFMM_HIP_TRY(hipGetDevice(&t->device));
+  t->n = n;
+  t->depth = opts->depth;
+  // Bounding box and validation (one synchronisation).
+  const int nparts = bbox_parts(n);
+  BBox* d_bb = nullptr;
+  BBFMM_HIP_TRY(hipMalloc((void**)&d_bb, (nparts + 1) * sizeof(BBox)));
+  BBox bb;
+  hipError_t e = launch_bbox(d_points, n, d_bb + 1, nparts, d_bb, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&bb, d_bb, sizeof(BBox), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_bb);
+  if (e != hipSuccess) return fail(BBFMM_EHIP, std::string("bounding box: ") + hipGetErrorString(e));
+  if (bb.nonfinite > 0) return fail(BBFMM_EINVAL, "points contain non-finite coordinates");
+  if (opts->root_width > 0) {
+    for (int r = 0; r < 3; ++r) {
+      t->lo[r] = opts->root_lo[r];
+      if (bb.lo[r] < opts->root_lo[r] || bb.hi[r] > opts->root_lo[r] + opts->root_width)
+        return fail(BBFMM_EINVAL, "a point lies outside the root cube");
+    }
+    t->width = opts->root_width;
+  } else {
+    double ext = 0.0;
+    for (int r = 0; r < 3; ++r) ext = std::max(ext, bb.hi[r] - bb.lo[r]);
+    if (!(ext > 0.0)) ext = 1.0;
+    const double w = ext * (1.0 + 1e-12);
+    for (int r = 0; r < 3; ++r) t->lo[r] = bb.lo[r] - 0.5 * (w - (bb.hi[r] - bb.lo[r]));
+    t->width = w;
+  }
+  const long long nleaf = 1LL << (3 * t->depth);
+  long long bytes = 0;
+  unsigned* keys = nullptr;
+  int *counts = nullptr, *cursor = nullptr, *tmp = nullptr;
+  auto cleanup = [&]() {
+    dfree(keys); dfree(counts); dfree(cursor); dfree(tmp);
+  };
+  auto bad = [&](hipError_t err, const char* what) {
+    cleanup();
+    dfree(t->xs); dfree(t->ys); dfree(t->zs); dfree(t->perm); dfree(t->leaf_of); dfree(t->leaf_start);
+    return fail(err == hipErrorOutOfMemory ? BBFMM_ENOMEM : BBFMM_EHIP,
+                std::string(what) + ": " + hipGetErrorString(err));
+  };
+  if ((e = dmalloc(&t->xs, n, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&t->ys, n, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&t->zs, n, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&t->perm, n, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&t->leaf_of, n, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&t->leaf_start, nleaf + 1, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&keys, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&counts, nleaf, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&cursor, nleaf, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&tmp, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  const double wleaf = t->width / (double)(1 << t->depth);
+  if ((e = hipMemsetAsync(counts, 0, nleaf * sizeof(int), s)) != hipSuccess) return bad(e, "memset");
+  if ((e = hipMemsetAsync(cursor, 0, nleaf * sizeof(int), s)) != hipSuccess) return bad(e, "memset");
+  if ((e = launch_leaf_keys(d_points, n, t->lo, wleaf, t->depth, keys, counts, s)) != hipSuccess)
+    return bad(e, "leaf keys");
+  if ((e = exclusive_scan(counts, t->leaf_start, nleaf, s)) != hipSuccess) return bad(e, "scan");
+  if ((e = launch_scatter(keys, n, t->leaf_start, cursor, tmp, s)) != hipSuccess) return bad(e, "scatter");
+  if ((e = launch_order(d_points, keys, n, t->leaf_start, tmp, t->perm, t->leaf_of, t->xs, t->ys,
+                        t->zs, s)) != hipSuccess)
+    return bad(e, "order");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "build");
+  cleanup();
+  t->bytes = bytes;
+  *out = t.release();
+  return BBFMM_OK;
+}
+
+void bbfmm_tree_destroy(bbfmm_tree* t) {
+  if (!t) return;
+  dfree(t->xs); dfree(t->ys); dfree(t->zs); dfree(t->perm); dfree(t->leaf_of); dfree(t->leaf_start);
+  delete t;
+}
+
+bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts* opts,
+                                  void* stream, bbfmm_plan** out) {
+  if (!out) return fail(BBFMM_EINVAL, "out is null");
+  *out = nullptr;
+  if (!tree || !opts) return fail(BBFMM_EINVAL, "null tree or options");
+  if (!valid_kernel(opts->kernel)) return fail(BBFMM_EINVAL, "unknown kernel");
+  if (opts->kernel == kInvSqrtR2C2 && !(opts->c > 0.0 && std::isfinite(opts->c)))
+    return fail(BBFMM_EINVAL, "c must be finite and > 0 for 1/sqrt(r^2 + c^2)");
+  if (opts->m2l_prec < 0 || opts->m2l_prec > 2) return fail(BBFMM_EINVAL, "unknown M2L precision");
+  if (!std::isfinite(opts->svd_eps)) return fail(BBFMM_EINVAL, "svd_eps is not finite");
+  if (opts->order < 2 || opts->order > kMaxOrder)
+    return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<bbfmm_plan> p(new (std::nothrow) bbfmm_plan());
+  if (!p) return fail(BBFMM_ENOMEM, "host allocation");
+  p->tree = tree;
+  p->kernel = opts->kernel; p->c = opts->c; p->order = opts->order; p->eps = opts->svd_eps;
+  p->prec = opts->m2l_prec;
+  const int L = p->order, nn = L * L * L, np = (nn + 15) / 16 * 16;
+  p->nn = nn; p->np = np;
+  const int depth = tree->depth;
+  double degree = 0.0;
+  const bool homog = kernel_is_homogeneous(p->kernel, &degree);
+  p->nsets = depth >= 2 ? (homog ? 1 : depth - 1) : 0;
+  for (int l = 2; l <= depth; ++l) {
+    const double wl = tree->width / (double)(1 << l);
+    p->set_of_level[l] = homog ? 0 : l - 2;
+    p->scale_of_level[l] = homog ? std::pow(wl, degree) : 1.0;
+  }
+  // ---- operators (FP64 on the host) ----
+  const int nsets = p->nsets;
+  std::vector<std::vector<double>> kfull(nsets * kNumSym), ufac(nsets * kNumSym), vfac(nsets * kNumSym);
+  p->ranks.assign(std::max(1, nsets) * kNumSym, nn);
+  int max_rank = 0;
+  for (int set = 0; set < nsets; ++set) {
+    const double wset = homog ? 1.0 : tree->width / (double)(1 << (set + 2));
+    for (int q = 0; q < kNumSym; ++q) {
+      std::vector<double>& K = kfull[set * kNumSym + q];
+      K.resize((size_t)nn * nn);
+      m2l_operator(p->kernel, p->c, L, wset, q, K.data());
+      if (p->eps > 0) {
+        std::vector<double> U((size_t)nn * nn), S(nn), V((size_t)nn * nn);
+        jacobi_svd(K.data(), nn, nn, U.data(), S.data(), V.data());
+        const int r = truncation_rank(S.data(), nn, p->eps);
+        p->ranks[set * kNumSym + q] = r;
+        max_rank = std::max(max_rank, r);
+        std::vector<double>& Uf = ufac[set * kNumSym + q];
+        std::vector<double>& Vf = vfac[set * kNumSym + q];
+        Uf.assign((size_t)nn * r, 0.0);
+        Vf.assign((size_t)nn * r, 0.0);
+        for (int i = 0; i < nn; ++i)
+          for (int k = 0; k < r; ++k) {
+            Uf[(size_t)i * r + k] = U[(size_t)i * nn + k] * S[k];
+            Vf[(size_t)i * r + k] = V[(size_t)i * nn + k];
+          }
+        // truncated operator for the full-rank fallback
+        for (int i = 0; i < nn; ++i)
+          for (int jj = 0; jj < nn; ++jj) {
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc += Uf[(size_t)i * r + k] * Vf[(size_t)jj * r + k];
+            K[(size_t)i * nn + jj] = acc;
+          }
+      }
+    }
+  }
+  p->lowrank = p->eps > 0 && nsets > 0 && L >= 3 && max_rank <= m2l_ia_rank_limit(L);
+  // ---- device layout ----
+  std::vector<double> blob;
+  p->op_off.assign(std::max(1, nsets) * kNumSym * 2, 0);
+  for (int set = 0; set < nsets; ++set)
+    for (int q = 0; q < kNumSym; ++q) {
+      const int idx = set * kNumSym + q;
+      if (!p->lowrank) {
+        p->op_off[idx * 2] = (long long)blob.size();
+        blob.insert(blob.end(), kfull[idx].begin(), kfull[idx].end());
+      } else {
+        const int r = p->ranks[idx], ru = (r + 3) / 4 * 4, rv = (r + 15) / 16 * 16;
+        p->op_off[idx * 2] = (long long)blob.size();
+        for (int i = 0; i < nn; ++i)
+          for (int k = 0; k < ru; ++k) blob.push_back(k < r ? ufac[idx][(size_t)i * r + k] : 0.0);
+        p->op_off[idx * 2 + 1] = (long long)blob.size();
+        for (int i = 0; i < nn; ++i)
+          for (int k = 0; k < rv; ++k) blob.push_back(k < r ? vfac[idx][(size_t)i * r + k] : 0.0);
+      }
+    }
+  std::vector<int> grp;
+  std::vector<int> tab = octant_tables(&grp);
+  p->h_tab = tab;
+  p->h_grp = grp;
+  std::vector<short> sig((size_t)kNumPerms * np), siginv((size_t)kNumPerms * np);
+  {
+    std::vector<int32_t> tmpv(nn);
+    for (int pid = 0; pid < kNumPerms; ++pid) {
+      sigma_table(L, pid, tmpv.data());
+      for (int i = 0; i < np; ++i) {
+        sig[(size_t)pid * np + i] = (short)(i < nn ? tmpv[i] : nn);
+        siginv[(size_t)pid * np + i] = (short)nn;
+      }
+      for (int i = 0; i < nn; ++i) siginv[(size_t)pid * np + tmpv[i]] = (short)i;
+    }
+  }
+  const std::vector<double> x = cheb_nodes(L);
+  std::vector<double> tk((size_t)L * L), m2m((size_t)2 * L * L);
+  for (int k = 0; k < L; ++k)
+    for (int m = 0; m < L; ++m) tk[(size_t)k * L + m] = std::cos(k * std::acos(x[m]));
+  for (int sbit = 0; sbit < 2; ++sbit)
+    for (int bc = 0; bc < L; ++bc)
+      for (int bp = 0; bp < L; ++bp)
+        m2m[((size_t)sbit * L + bc) * L + bp] = cheb_basis(L, 0.5 * (2 * sbit - 1) + 0.5 * x[bc], bp);
+  // ---- upload ----
+  long long bytes = 0;
+  auto up = [&](void** dst, const void* src, size_t nbytes) -> hipError_t {
+    *dst = nullptr;
+    if (nbytes == 0) return hipSuccess;
+    hipError_t er = hipMalloc(dst, nbytes);
+    if (er != hipSuccess) return er;
+    bytes += (long long)nbytes;
+    return hipMemcpyAsync(*dst, src, nbytes, hipMemcpyHostToDevice, s);
+  };
+  auto destroy_partial = [&]() {
+    dfree(p->ops_hi); dfree(p->ops_lo); dfree(p->d_op_off); dfree(p->d_op_rank); dfree(p->d_tab);
+    dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
+  };
+  hipError_t e = hipSuccess;
+  std::vector<float> hi, lo;
+  if (p->prec == 0) {
+    e = up(&p->ops_hi, blob.data(), blob.size() * sizeof(double));
+  } else {
+    hi.resize(blob.size());
+    lo.resize(blob.size());
+    for (size_t i = 0; i < blob.size(); ++i) {
+      hi[i] = (float)blob[i];
+      lo[i] = (float)(blob[i] - (double)hi[i]);
+    }
+    e = up(&p->ops_hi, hi.data(), hi.size() * sizeof(float));
+    if (e == hipSuccess && p->prec == 2) e = up(&p->ops_lo, lo.data(), lo.size() * sizeof(float));
+  }
+  if (e == hipSuccess) e = up((void**)&p->d_op_off, p->op_off.data(), p->op_off.size() * sizeof(long long));
+  if (e == hipSuccess) e = up((void**)&p->d_op_rank, p->ranks.data(), p->ranks.size() * sizeof(int));
+  if (e == hipSuccess) e = up((void**)&p->d_tab, tab.data(), tab.size() * sizeof(int));
+  if (e == hipSuccess) e = up((void**)&p->d_grp, grp.data(), grp.size() * sizeof(int));
+  if (e == hipSuccess) e = up((void**)&p->d_sig, sig.data(), sig.size() * sizeof(short));
+  if (e == hipSuccess) e = up((void**)&p->d_siginv, siginv.data(), siginv.size() * sizeof(short));
+  if (e == hipSuccess) e = up((void**)&p->d_tk, tk.data(), tk.size() * sizeof(double));
+  if (e == hipSuccess) e = up((void**)&p->d_m2m, m2m.data(), m2m.size() * sizeof(double));
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    destroy_partial();
+    return fail(e == hipErrorOutOfMemory ? BBFMM_ENOMEM : BBFMM_EHIP,
+                std::string("precompute upload: ") + hipGetErrorString(e));
+  }
+  p->op_bytes = bytes;
+  long long off = 0;
+  for (int l = 2; l <= depth; ++l) {
+    p->level_off[l] = off;
+    off += (1LL << (3 * l)) * nn;
+  }
+  p->exp_elems = off;
+  p->precompute_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = p.release();
+  return BBFMM_OK;
+}
+
+void bbfmm_plan_destroy(bbfmm_plan* p) {
+  if (!p) return;
+  free_buffers(p);
+  dfree(p->ops_hi); dfree(p->ops_lo); dfree(p->d_op_off); dfree(p->d_op_rank); dfree(p->d_tab);
+  dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
+  delete p;
+}
+
+static bbfmm_status check_apply_args(const bbfmm_plan* p, const double* in, int32_t nrhs,
+                                     const double* out) {
+  if (!p) return fail(BBFMM_EINVAL, "plan is null");
+  if (!in || !out) return fail(BBFMM_EINVAL, "null input or output");
+  if (nrhs < 1 || nrhs > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64]");
+  if (in == out) return fail(BBFMM_EINVAL, "input and output must not alias");
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_apply(bbfmm_plan* p, const double* d_q, int32_t nrhs, double* d_phi, void* stream) {
+  bbfmm_status st = check_apply_args(p, d_q, nrhs, d_phi);
+  if (st != BBFMM_OK) return st;
+  return run_chain(p, d_q, nrhs, d_phi, 0, (hipStream_t)stream);
+}
+
+bbfmm_status bbfmm_apply_adjoint(bbfmm_plan* p, const double* d_g, int32_t nrhs, double* d_grad_q,
+                                 void* stream) {
+  bbfmm_status st = check_apply_args(p, d_g, nrhs, d_grad_q);
+  if (st != BBFMM_OK) return st;
+  // The supported kernels are symmetric and sources = targets: L2P^T = P2M, L2L^T = M2M,
+  // K_t^T = K_{-t} (so M2L^T is the M2L of the reversed pairs) and the near field is symmetric;
+  // the transposed chain is therefore the forward pass sequence run on g.
+  return run_chain(p, d_g, nrhs, d_grad_q, 1, (hipStream_t)stream);
+}
+
+bbfmm_status bbfmm_eval_grad(bbfmm_plan* p, const double* d_q, const double* d_g, int32_t nrhs,
+                             int32_t roles, double* d_grad_x, void* stream) {
+  if (!p) return fail(BBFMM_EINVAL, "plan is null");
+  if (!d_q || !d_g || !d_grad_x) return fail(BBFMM_EINVAL, "null argument");
+  if (roles < 1 || roles > 3) return fail(BBFMM_EINVAL, "roles must be 1, 2 or 3");
+  if (nrhs < 1 || nrhs > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64]");
+  if (p->slot_nrhs[0] != nrhs || p->slot_nrhs[1] != nrhs)
+    return fail(BBFMM_ESTATE, "eval_grad needs bbfmm_apply(q) and bbfmm_apply_adjoint(g) with this nrhs first");
+  hipStream_t s = (hipStream_t)stream;
+  const bbfmm_tree* t = p->tree;
+  const PassGeom g = geom_of(p);
+  // densities in sorted order are already in qs[0] / qs[1] from the two chains; re-gather in case
+  // the caller passes different arrays than were applied (they must be the same values).
+  BBFMM_HIP_TRY(launch_gather_rows(d_q, t->perm, t->n, nrhs, p->qs[0], s));
+  BBFMM_HIP_TRY(launch_gather_rows(d_g, t->perm, t->n, nrhs, p->qs[1], s));
+  const double* Fq = t->depth >= 2 ? p->F[0] + p->level_off[t->depth] * nrhs : nullptr;
+  const double* Fg = t->depth >= 2 ? p->F[1] + p->level_off[t->depth] * nrhs : nullptr;
+  BBFMM_HIP_TRY(launch_grad(g, p->qs[0], p->qs[1], Fq, Fg, nrhs, roles, d_grad_x, s));
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_plan_stats(const bbfmm_plan* p, bbfmm_stats* out) {
+  if (!p || !out) return fail(BBFMM_EINVAL, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  const bbfmm_tree* t = p->tree;
+  out->n_points = t->n;
+  out->depth = t->depth;
+  out->order = p->order;
+  out->n_levels_m2l = t->depth >= 2 ? t->depth - 1 : 0;
+  out->n_operator_sets = p->nsets;
+  for (int q = 0; q < kNumSym; ++q) out->rank[q] = p->eps > 0 ? p->ranks[q] : p->nn;
+  for (int r = 0; r < 3; ++r) out->root_lo[r] = t->lo[r];
+  out->root_width = t->width;
+  out->precompute_seconds = p->precompute_seconds;
+  out->device_bytes = t->bytes + p->op_bytes + p->buffer_bytes;
+  if (t->depth < 2) return BBFMM_OK;
+  unsigned long long* d_counts = nullptr;
+  const int nlev = t->depth - 1;
+  BBFMM_HIP_TRY(hipMalloc((void**)&d_counts, sizeof(unsigned long long) * 16 * nlev));
+  hipError_t e = hipMemset(d_counts, 0, sizeof(unsigned long long) * 16 * nlev);
+  for (int l = 2; l <= t->depth && e == hipSuccess; ++l)
+    e = launch_count_pairs(t->leaf_start, t->depth, l, p->d_tab, d_counts + 16 * (l - 2), nullptr);
+  std::vector<unsigned long long> counts(16 * nlev);
+  if (e == hipSuccess)
+    e = hipMemcpy(counts.data(), d_counts, counts.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+  (void)hipFree(d_counts);
+  if (e != hipSuccess) return fail(BBFMM_EHIP, std::string("plan_stats: ") + hipGetErrorString(e));
+  const double nn = p->nn;
+  for (int l = 2; l <= t->depth; ++l) {
+    const long long s = 1LL << l;
+    out->pairs_total += (6 * s - 8) * (6 * s - 8) * (6 * s - 8) - (3 * s - 2) * (3 * s - 2) * (3 * s - 2);
+    const int set = p->set_of_level[l];
+    for (int q = 0; q < kNumSym; ++q) {
+      const double c = (double)counts[16 * (l - 2) + q];
+      out->pairs_nonempty += (long long)c;
+      const double r = p->ranks[set * kNumSym + q];
+      out->m2l_flops_algorithmic += c * (p->eps > 0 ? 4.0 * nn * r : 2.0 * nn * nn);
+    }
+    // issued: every tile runs every transfer vector of its octant
+    const long long npar = 1LL << (3 * (l - 1));
+    const double tiles_per_rhs = (double)npar / 64.0;   // per right-hand side
+    for (int q = 0; q < kNumSym; ++q) {
+      const int np_q = p->h_grp[q + 1] - p->h_grp[q];
+      const double per_t = m2l_issued_flops_per_t(p->order, p->lowrank, p->ranks[set * kNumSym + q]);
+      out->m2l_flops_issued += 8.0 * tiles_per_rhs * np_q * per_t;
+    }
+  }
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_debug_get_expansions(const bbfmm_plan* p, int32_t level, int32_t which,
+                                        double* d_out, void* stream) {
+  if (!p || !d_out) return fail(BBFMM_EINVAL, "null argument");
+  const bbfmm_tree* t = p->tree;
+  if (level < 2 || level > t->depth) return fail(BBFMM_EINVAL, "level must be in [2, depth]");
+  if (which < 0 || which > 2) return fail(BBFMM_EINVAL, "which must be 0, 1 or 2");
+  const int nrhs = p->slot_nrhs[0];
+  if (nrhs == 0 || !p->W) return fail(BBFMM_ESTATE, "no apply has run on this plan");
+  const size_t count = (size_t)(1LL << (3 * level)) * p->nn * nrhs;
+  const double* src = nullptr;
+  if (which == 0) src = p->W + p->level_off[level] * nrhs;
+  else src = p->F[0] + p->level_off[level] * nrhs;
+  if (which == 1) {
+    // M2L output alone: rerun the M2L of this level into the output
+    const M2LArgs a = m2l_args(p, nrhs, p->W + p->level_off[level] * nrhs, d_out, level);
+    BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, (hipStream_t)stream));
+    return BBFMM_OK;
+  }
+  BBFMM_HIP_TRY(hipMemcpyAsync(d_out, src, count * sizeof(double), hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream));
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_debug_m2l_level(bbfmm_plan* p, int32_t level, const double* d_w, int32_t nrhs,
+                                   double* d_f, void* stream) {
+  if (!p || !d_w || !d_f) return fail(BBFMM_EINVAL, "null argument");
+  if (level < 2 || level > p->tree->depth) return fail(BBFMM_EINVAL, "level must be in [2, depth]");
+  if (nrhs < 1 || nrhs > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64]");
+  const M2LArgs a = m2l_args(p, nrhs, d_w, d_f, level);
+  BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, (hipStream_t)stream));
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_debug_tree_order(const bbfmm_tree* t, int32_t* d_perm, int32_t* d_leaf_start,
+                                    void* stream) {
+  if (!t || !d_perm || !d_leaf_start) return fail(BBFMM_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  BBFMM_HIP_TRY(hipMemcpyAsync(d_perm, t->perm, t->n * sizeof(int), hipMemcpyDeviceToDevice, s));
+  BBFMM_HIP_TRY(hipMemcpyAsync(d_leaf_start, t->leaf_start, ((1LL << (3 * t->depth)) + 1) * sizeof(int),
+                               hipMemcpyDeviceToDevice, s));
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_host_symmetry(int32_t order, const int32_t t[3], int32_t* out_t16,
+                                 int32_t* out_p, int32_t* out_sigma) {
+  if (order < 2 || order > kMaxOrder) return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
+  const auto& reps = representatives();
+  if (out_t16)
+    for (int q = 0; q < kNumSym; ++q)
+      for (int r = 0; r < 3; ++r) out_t16[q * 3 + r] = reps[q][r];
+  if (t) {
+    int linf = 0;
+    for (int r = 0; r < 3; ++r) {
+      if (t[r] < -3 || t[r] > 3) return fail(BBFMM_EINVAL, "|t_i| must be <= 3");
+      linf = std::max(linf, std::abs(t[r]));
+    }
+    if (linf < 2) return fail(BBFMM_EINVAL, "t is a near-field vector");
+    const int tt[3] = {t[0], t[1], t[2]};
+    const SymInfo si = symmetry_of(tt);
+    if (out_p) *out_p = si.p;
+    if (out_sigma) sigma_table(order, si.perm_id, out_sigma);
+  }
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_host_operator(int32_t kernel, double c, int32_t order, double width, int32_t p,
+                                 double svd_eps, double* out_k, double* out_u, double* out_v,
+                                 int32_t* out_rank) {
+  if (!valid_kernel(kernel)) return fail(BBFMM_EINVAL, "unknown kernel");
+  if (order < 2 || order > kMaxOrder) return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
+  if (p < 0 || p >= kNumSym) return fail(BBFMM_EINVAL, "p must be in [0, 16)");
+  if (!(width > 0)) return fail(BBFMM_EINVAL, "width must be > 0");
+  const int nn = order * order * order;
+  std::vector<double> K((size_t)nn * nn);
+  m2l_operator(kernel, c, order, width, p, K.data());
+  if (out_k) std::memcpy(out_k, K.data(), K.size() * sizeof(double));
+  if (svd_eps > 0) {
+    std::vector<double> U((size_t)nn * nn), S(nn), V((size_t)nn * nn);
+    jacobi_svd(K.data(), nn, nn, U.data(), S.data(), V.data());
+    const int r = truncation_rank(S.data(), nn, svd_eps);
+    if (out_rank) *out_rank = r;
+    for (int i = 0; i < nn; ++i)
+      for (int k = 0; k < r; ++k) {
+        if (out_u) out_u[(size_t)i * r + k] = U[(size_t)i * nn + k] * S[k];
+        if (out_v) out_v[(size_t)i * r + k] = V[(size_t)i * nn + k];
+      }
+  } else if (out_rank) {
+    *out_rank = nn;
+  }
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_host_singular_values(const double* a, int32_t m, int32_t n, double* out_s) {
+  if (!a || !out_s) return fail(BBFMM_EINVAL, "null argument");
+  if (n < 1 || m < n) return fail(BBFMM_EINVAL, "need m >= n >= 1");
+  std::vector<double> U((size_t)m * n), V((size_t)n * n);
+  jacobi_svd(a, m, n, U.data(), out_s, V.data());
+  return BBFMM_OK;
+}
+
+}  // extern "C"

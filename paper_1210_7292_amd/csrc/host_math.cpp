@@ -1,0 +1,226 @@
+// Host FP64 precomputation for the bbFMM M2L. See host_math.h.
+#include "host_math.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace bbfmm {
+
+std::vector<double> cheb_nodes(int order) {
+  std::vector<double> x(order);
+  for (int k = 1; k <= order; ++k) x[k - 1] = -std::cos((2.0 * k - 1.0) * M_PI / (2.0 * order));
+  return x;
+}
+
+double cheb_basis(int order, double u, int m) {
+  // T_k by the three-term recurrence at u and at the node.
+  const double xm = -std::cos((2.0 * (m + 1) - 1.0) * M_PI / (2.0 * order));
+  double tu0 = 1.0, tu1 = u, tx0 = 1.0, tx1 = xm;
+  double sum = 1.0 / order;
+  for (int k = 1; k < order; ++k) {
+    sum += (2.0 / order) * tu1 * tx1;
+    const double tu2 = 2.0 * u * tu1 - tu0, tx2 = 2.0 * xm * tx1 - tx0;
+    tu0 = tu1; tu1 = tu2; tx0 = tx1; tx1 = tx2;
+  }
+  return sum;
+}
+
+double kernel_value(int kind, double c, double r) {
+  switch (kind) {
+    case kInvR: return r > 0.0 ? 1.0 / r : 0.0;
+    case kInvSqrtR2C2: return 1.0 / std::sqrt(r * r + c * c);
+    case kR2: return r * r;
+    case kR4: return (r * r) * (r * r);
+    default: return 0.0;
+  }
+}
+
+bool kernel_is_homogeneous(int kind, double* degree) {
+  switch (kind) {
+    case kInvR: *degree = -1.0; return true;
+    case kR2: *degree = 2.0; return true;
+    case kR4: *degree = 4.0; return true;
+    default: *degree = 0.0; return false;
+  }
+}
+
+const std::array<std::array<int, 3>, kNumSym>& representatives() {
+  static const std::array<std::array<int, 3>, kNumSym> reps = [] {
+    std::array<std::array<int, 3>, kNumSym> r{};
+    int n = 0;
+    for (int a = 2; a <= 3; ++a)
+      for (int b = 0; b <= a; ++b)
+        for (int c = 0; c <= b; ++c) r[n++] = {a, b, c};
+    return r;
+  }();
+  return reps;
+}
+
+const std::array<std::array<int, 3>, 6>& axis_orders() {
+  static const std::array<std::array<int, 3>, 6> ord = {{{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
+                                                          {1, 2, 0}, {2, 0, 1}, {2, 1, 0}}};
+  return ord;
+}
+
+SymInfo symmetry_of(const int t[3]) {
+  SymInfo s{};
+  int at[3];
+  for (int r = 0; r < 3; ++r) {
+    if (t[r] < 0) s.flip |= 1 << r;
+    at[r] = std::abs(t[r]);
+  }
+  // Stable descending order of |t|: insertion sort on axis indices.
+  int ax[3] = {0, 1, 2};
+  for (int i = 1; i < 3; ++i)
+    for (int j = i; j > 0 && at[ax[j]] > at[ax[j - 1]]; --j) std::swap(ax[j], ax[j - 1]);
+  const auto& ords = axis_orders();
+  for (int k = 0; k < 6; ++k)
+    if (ords[k][0] == ax[0] && ords[k][1] == ax[1] && ords[k][2] == ax[2]) s.axes = k;
+  const int pt[3] = {at[ax[0]], at[ax[1]], at[ax[2]]};
+  const auto& reps = representatives();
+  s.p = -1;
+  for (int k = 0; k < kNumSym; ++k)
+    if (reps[k][0] == pt[0] && reps[k][1] == pt[1] && reps[k][2] == pt[2]) s.p = k;
+  s.perm_id = s.flip * 6 + s.axes;
+  return s;
+}
+
+void sigma_table(int order, int perm_id, int32_t* out) {
+  const int flip = perm_id / 6;
+  const auto& ax = axis_orders()[perm_id % 6];
+  const int nn = order * order * order;
+  for (int i = 0; i < nn; ++i) {
+    int a[3] = {i % order, (i / order) % order, i / (order * order)};
+    for (int r = 0; r < 3; ++r)
+      if (flip & (1 << r)) a[r] = order - 1 - a[r];
+    out[i] = a[ax[0]] + order * a[ax[1]] + order * order * a[ax[2]];
+  }
+}
+
+void m2l_operator(int kind, double c, int order, double width, int p, double* out) {
+  const std::vector<double> x = cheb_nodes(order);
+  const auto& t = representatives()[p];
+  const int nn = order * order * order;
+  for (int i = 0; i < nn; ++i) {
+    const int a[3] = {i % order, (i / order) % order, i / (order * order)};
+    for (int j = 0; j < nn; ++j) {
+      const int b[3] = {j % order, (j / order) % order, j / (order * order)};
+      double r2 = 0.0;
+      for (int s = 0; s < 3; ++s) {
+        const double d = width * t[s] + 0.5 * width * (x[a[s]] - x[b[s]]);
+        r2 += d * d;
+      }
+      out[(size_t)i * nn + j] = kernel_value(kind, c, std::sqrt(r2));
+    }
+  }
+}
+
+void jacobi_svd(const double* a, int m, int n, double* u, double* s, double* v) {
+  // Work column-major: column j of A in w[j*m .. j*m+m).
+  std::vector<double> w((size_t)m * n), vv((size_t)n * n, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) w[(size_t)j * m + i] = a[(size_t)i * n + j];
+  for (int j = 0; j < n; ++j) vv[(size_t)j * n + j] = 1.0;
+  const double tol = 1e-15;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < n - 1; ++p) {
+      double* wp = &w[(size_t)p * m];
+      for (int q = p + 1; q < n; ++q) {
+        double* wq = &w[(size_t)q * m];
+        double alpha = 0.0, beta = 0.0, gamma = 0.0;
+        for (int k = 0; k < m; ++k) {
+          alpha += wp[k] * wp[k];
+          beta += wq[k] * wq[k];
+          gamma += wp[k] * wq[k];
+        }
+        if (gamma == 0.0 || std::fabs(gamma) <= tol * std::sqrt(alpha * beta)) continue;
+        rotated = true;
+        const double zeta = (beta - alpha) / (2.0 * gamma);
+        const double tt = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / std::sqrt(1.0 + tt * tt), sn = cs * tt;
+        for (int k = 0; k < m; ++k) {
+          const double x0 = wp[k], x1 = wq[k];
+          wp[k] = cs * x0 - sn * x1;
+          wq[k] = sn * x0 + cs * x1;
+        }
+        double* vp = &vv[(size_t)p * n];
+        double* vq = &vv[(size_t)q * n];
+        for (int k = 0; k < n; ++k) {
+          const double x0 = vp[k], x1 = vq[k];
+          vp[k] = cs * x0 - sn * x1;
+          vq[k] = sn * x0 + cs * x1;
+        }
+      }
+    }
+    if (!rotated) break;
+  }
+  std::vector<double> norms(n);
+  for (int j = 0; j < n; ++j) {
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) acc += w[(size_t)j * m + k] * w[(size_t)j * m + k];
+    norms[j] = std::sqrt(acc);
+  }
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return norms[x] > norms[y]; });
+  for (int jj = 0; jj < n; ++jj) {
+    const int j = idx[jj];
+    s[jj] = norms[j];
+    const double inv = norms[j] > 0.0 ? 1.0 / norms[j] : 0.0;
+    for (int k = 0; k < m; ++k) u[(size_t)k * n + jj] = w[(size_t)j * m + k] * inv;
+    for (int k = 0; k < n; ++k) v[(size_t)k * n + jj] = vv[(size_t)j * n + k];
+  }
+}
+
+int truncation_rank(const double* s, int n, double eps) {
+  if (n == 0 || s[0] == 0.0) return 0;
+  int r = 0;
+  for (int k = 0; k < n; ++k)
+    if (s[k] > eps * s[0]) ++r;
+  if (r < 1) r = 1;
+  while (r < n && std::fabs(s[r] - s[r - 1]) <= 1e-10 * s[0]) ++r;
+  return r;
+}
+
+void octant_table(int octant, int32_t* entries, int32_t* group_start) {
+  const int o[3] = {octant & 1, (octant >> 1) & 1, (octant >> 2) & 1};
+  struct E { int d[3]; int p; int perm; int order; };
+  std::vector<E> list;
+  int seq = 0;
+  for (int dz = -3; dz <= 3; ++dz)
+    for (int dy = -3; dy <= 3; ++dy)
+      for (int dx = -3; dx <= 3; ++dx) {
+        const int d[3] = {dx, dy, dz};
+        bool ok = true;
+        int linf = 0;
+        for (int r = 0; r < 3; ++r) {
+          // target coordinate 2P + o, source 2P + o + d; parents must be neighbours.
+          const int num = o[r] + d[r];
+          const int pshift = (num >= 0) ? num / 2 : -((-num + 1) / 2);  // floor(num / 2)
+          if (pshift < -1 || pshift > 1) ok = false;
+          linf = std::max(linf, std::abs(d[r]));
+        }
+        if (!ok || linf <= 1) continue;
+        const int t[3] = {-dx, -dy, -dz};
+        const SymInfo si = symmetry_of(t);
+        list.push_back(E{{dx, dy, dz}, si.p, si.perm_id, seq++});
+      }
+  std::stable_sort(list.begin(), list.end(), [](const E& a, const E& b) { return a.p < b.p; });
+  for (int p = 0; p <= kNumSym; ++p) group_start[p] = 0;
+  for (size_t k = 0; k < list.size() && k < (size_t)kFarPerOctant; ++k) {
+    const E& e = list[k];
+    entries[k] = (e.d[0] + 3) | ((e.d[1] + 3) << 3) | ((e.d[2] + 3) << 6) | (e.p << 9) |
+                 (e.perm << 13);
+  }
+  int cursor = 0;
+  for (int p = 0; p < kNumSym; ++p) {
+    group_start[p] = cursor;
+    for (const E& e : list)
+      if (e.p == p) ++cursor;
+  }
+  group_start[kNumSym] = cursor;
+}
+
+}  // namespace bbfmm

@@ -1,0 +1,65 @@
+// Host-side FP64 precomputation of the bbFMM (pure C++, no HIP): Chebyshev interpolation,
+// M2L operators of the 16 representative transfer vectors, their truncated SVD, and the
+// symmetry tables that map every transfer vector onto a representative.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <vector>
+
+namespace bbfmm {
+
+constexpr int kMaxOrder = 8;
+constexpr int kNumSym = 16;      // |T_sym| (Eq. reduced_interaction_list)
+constexpr int kNumPerms = 48;    // 8 axial reflections x 6 axis orders
+constexpr int kFarPerOctant = 189;
+
+enum KernelKind : int32_t { kInvR = 0, kInvSqrtR2C2 = 1, kR2 = 100, kR4 = 101 };
+
+// Chebyshev roots of T_l, ascending (Sec. 2.1; T_l(x) = cos(l arccos x)).
+std::vector<double> cheb_nodes(int order);
+
+// S_l(u, xbar_m) in the Chebyshev-sum form 1/l + 2/l sum_{k=1}^{l-1} T_k(u) T_k(xbar_m).
+double cheb_basis(int order, double u, int m);
+
+// Kernel value at distance r.
+double kernel_value(int kind, double c, double r);
+bool kernel_is_homogeneous(int kind, double* degree);
+
+// The 16 representatives t1 >= t2 >= t3 >= 0 with max(t) in {2, 3}, in a fixed order.
+const std::array<std::array<int, 3>, kNumSym>& representatives();
+
+// The 6 axis orders (lexicographic permutations of {0, 1, 2}).
+const std::array<std::array<int, 3>, 6>& axis_orders();
+
+struct SymInfo {
+  int p;        // index into representatives()
+  int flip;     // bit r set when t_r < 0 (Eq. axial_permutation)
+  int axes;     // index into axis_orders(): |t_{a0}| >= |t_{a1}| >= |t_{a2}|, ties by axis
+  int perm_id;  // flip * 6 + axes, 0..47
+};
+SymInfo symmetry_of(const int t[3]);
+
+// sigma for permutation id `perm_id`: K_t[i][j] = K_p[sigma[i]][sigma[j]].
+// sigma(i) = m(pi(flip(m^{-1}(i)))), pi(a)_s = a_{axes[s]}, m(a) = a0 + l a1 + l^2 a2.
+void sigma_table(int order, int perm_id, int32_t* out);
+
+// Full M2L operator of representative p at cell width `width` (row-major l^3 x l^3):
+// K[m(a)][n(b)] = K(width * t_p + width/2 * (xhat_a - xhat_b)).
+void m2l_operator(int kind, double c, int order, double width, int p, double* out);
+
+// One-sided (Hestenes) Jacobi SVD of a row-major m x n matrix (m >= n):
+// A = U diag(S) V^T, U m x n (row-major), S descending, V n x n (row-major).
+void jacobi_svd(const double* a, int m, int n, double* u, double* s, double* v);
+
+// Rank rule: count of s_k > eps * s_0, extended over values within 1e-10 * s_0 of the last kept.
+int truncation_rank(const double* s, int n, double eps);
+
+// Far-field table of a target octant (x bit 0, y bit 1, z bit 2): the 189 source offsets
+// d = Y - X (cell units) whose source is a child of a neighbour of the target's parent and not a
+// neighbour of the target, sorted by representative (stable). Each entry packs
+// (dx+3) | (dy+3) << 3 | (dz+3) << 6 | p << 9 | perm_id << 13, where t = -d.
+// group_start[p] .. group_start[p+1] delimits representative p.
+void octant_table(int octant, int32_t* entries /*189*/, int32_t* group_start /*17*/);
+
+}  // namespace bbfmm

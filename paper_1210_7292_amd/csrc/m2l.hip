@@ -1,0 +1,403 @@
+// Symmetry-blocked M2L on gfx950 matrix cores (Sec. 4.2.1-4.2.3, Alg. BlockedM2L).
+//
+// For a pair (target X, source Y = X - t) the paper applies K_t = P_t K_{p(t)} P_t^T as
+//   w_t = P_t^T w,  f_t = K_{p(t)} w_t,  f += P_t f_t            (Eqs. perm_mult .. perm_loc)
+// with only the 16 operators K_p of the cone t1 >= t2 >= t3 >= 0 stored. In index form,
+// K_t[i][j] = K_p[sigma(i)][sigma(j)], so
+//   f_X[i] += sum_j K_p[sigma(i)][sigma(j)] w_Y[j].
+// Here the permutations are folded into operand fetches instead of moving vectors: the row
+// permutation selects which LDS row of K_p feeds MFMA row i, and the column permutation selects
+// either the LDS column (compressed path) or the multipole entry (full-rank path). The local
+// expansion tile therefore stays in MFMA accumulators across all 189 transfer vectors of its
+// targets and is written once, with no atomics.
+//
+// Work unit: one workgroup of 4 waves owns 64 columns = (target, rhs) pairs whose targets all
+// have the same octant inside their parent, so they share the same 189 transfer vectors, p(t)
+// and sigma_t. Transfer vectors are visited grouped by representative; each representative's
+// operator (or its factors) is staged once in LDS and reused by all its transfer vectors — the
+// blocking of Alg. BlockedM2L across many target cells, with the column count fixed at 64.
+//
+// Full rank (variants NA*): F += K_p[sigma(i)][k'] * w[sigma^-1(k')], K_p staged in column
+//   chunks of KC.
+// Compressed (Eq. ialowrank, K_p ~ U_p V_p^T): Z = V_p[sigma(j)]^T w (GEMM 1), then
+//   F += U_p[sigma(i)] Z (GEMM 2); Z passes through LDS to change from accumulator layout to
+//   operand layout.
+//
+// MFMA v_mfma_{f64,f32}_16x16x4: lane l supplies A[l%16][l/16], B[l/16][l%16] and holds
+// D[4(l/16)+v][l%16], v = 0..3.
+#include "internal.h"
+
+namespace bbfmm {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kCols = 16 * kWaves;
+
+template <int PREC> struct Arith;
+template <> struct Arith<0> {
+  using T = double;
+  using V = f64x4;
+  static __device__ inline V mfma(T a, T b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Arith<1> {
+  using T = float;
+  using V = f32x4;
+  static __device__ inline V mfma(T a, T b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Arith<2> : Arith<1> {};
+
+struct BlockPos {
+  const M2LLevel* lv;
+  int oct;
+  int tile;
+};
+
+__device__ inline bool locate(const M2LArgs& a, BlockPos& bp) {
+  // Logical block order is level-major, then tile, then octant, so the 8 octants of one group of
+  // parents are adjacent. Hardware sends block b to XCD b % 8; remapping gives each XCD a
+  // contiguous range of logical blocks, keeping shared source cells in one L2.
+  const int per = gridDim.x / 8;
+  const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (logical >= a.nblocks) return false;
+  int k = 0;
+  while (k + 1 < a.nlev && logical >= a.lv[k + 1].block_begin) ++k;
+  bp.lv = &a.lv[k];
+  const int local = logical - bp.lv->block_begin;
+  bp.tile = local / 8;
+  bp.oct = local % 8;
+  return true;
+}
+
+struct Column {
+  int tx, ty, tz;     // target cell coordinates
+  unsigned target;    // Morton index of the target cell
+  int rhs;
+  bool valid;
+};
+
+__device__ inline Column column_of(const M2LArgs& a, const BlockPos& bp, int col_in_tile) {
+  Column c;
+  const int col = bp.tile * kCols + col_in_tile;
+  const int P = col / a.nrhs;
+  c.rhs = col - P * a.nrhs;
+  c.valid = P < bp.lv->npar;
+  const unsigned Pm = c.valid ? (unsigned)P : 0u;
+  c.target = Pm * 8u + (unsigned)bp.oct;
+  demorton3(c.target, c.tx, c.ty, c.tz);
+  return c;
+}
+
+// Multipole column of the source Y = X + d for this lane, or null outside the level.
+__device__ inline const double* source_of(const M2LArgs& a, const BlockPos& bp, const Column& c,
+                                          int ent, int nn) {
+  const int sx = c.tx + (ent & 7) - 3, sy = c.ty + ((ent >> 3) & 7) - 3,
+            sz = c.tz + ((ent >> 6) & 7) - 3;
+  const int side = bp.lv->side;
+  if (!c.valid || sx < 0 || sy < 0 || sz < 0 || sx >= side || sy >= side || sz >= side) return nullptr;
+  return bp.lv->W + ((long long)morton3(sx, sy, sz) * nn) * a.nrhs + c.rhs;
+}
+
+template <int L, int MB, typename V>
+__device__ inline void store_tile(const M2LArgs& a, const BlockPos& bp, const Column& c, int kq,
+                                  const V* acc, const f64x4* acc64, bool use64) {
+  constexpr int NN = L * L * L;
+  if (!c.valid) return;
+  const double sc = bp.lv->scale;
+  double* dst = bp.lv->F + ((long long)c.target * NN) * a.nrhs + c.rhs;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * mb + 4 * kq + v;
+      if (i < NN) dst[(long long)i * a.nrhs] = sc * (use64 ? acc64[mb][v] : (double)acc[mb][v]);
+    }
+}
+
+// ------------------------------------------------------------------------ full-rank M2L ----
+template <int L, int KC, int PREC>
+__global__ __launch_bounds__(kThreads) void m2l_full_kernel(M2LArgs a) {
+  using A = Arith<PREC>;
+  using T = typename A::T;
+  using V = typename A::V;
+  constexpr int NN = L * L * L;
+  constexpr int NP = (NN + 15) / 16 * 16;
+  constexpr int MB = NP / 16;
+  constexpr int NCH = (NN + KC - 1) / KC;
+  constexpr int LDK = KC + 1;              // odd stride in elements: rows hit distinct banks
+  constexpr bool SPLIT = PREC == 2;
+  __shared__ T khi[(NN + 1) * LDK];
+  __shared__ T klo[SPLIT ? (NN + 1) * LDK : 1];
+
+  BlockPos bp;
+  if (!locate(a, bp)) return;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int j = lane % 16, kq = lane / 16;
+  const Column col = column_of(a, bp, 16 * wave + j);
+  const int set = bp.lv->set;
+
+  V acc[MB];
+  f64x4 acc64[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    acc[mb] = V{0, 0, 0, 0};
+    acc64[mb] = f64x4{0, 0, 0, 0};
+  }
+
+  for (int p = 0; p < kNumSym; ++p) {
+    const int g0 = a.grp[bp.oct * 17 + p], g1 = a.grp[bp.oct * 17 + p + 1];
+    if (g0 == g1) continue;
+    const long long off = a.op_off[(set * kNumSym + p) * 2];
+    const T* Kp = static_cast<const T*>(a.ops_hi) + off;
+    const T* Kl = SPLIT ? static_cast<const T*>(a.ops_lo) + off : nullptr;
+    for (int ch = 0; ch < NCH; ++ch) {
+      __syncthreads();
+      for (int e = tid; e < (NN + 1) * KC; e += kThreads) {
+        const int row = e / KC, cc = e - row * KC, k = ch * KC + cc;
+        const bool in = row < NN && k < NN;
+        khi[row * LDK + cc] = in ? Kp[(long long)row * NN + k] : T(0);
+        if (SPLIT) klo[row * LDK + cc] = in ? Kl[(long long)row * NN + k] : T(0);
+      }
+      __syncthreads();
+      for (int e = g0; e < g1; ++e) {
+        const int ent = a.tab[bp.oct * kFarPerOctant + e];
+        const int perm = ent >> 13;
+        const double* src = source_of(a, bp, col, ent, NN);
+        const short* sg = a.sig + perm * NP;
+        const short* si = a.siginv + perm * NP;
+        int srow[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) srow[mb] = sg[16 * mb + j] * LDK;
+        // B operand: w[sigma^-1(k)] for the chunk's natural columns k.
+        double bv[KC / 4];
+#pragma unroll
+        for (int s = 0; s < KC / 4; ++s) {
+          const int k = ch * KC + 4 * s + kq;
+          bv[s] = (src != nullptr && k < NN) ? src[(long long)si[k] * a.nrhs] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < KC / 4; ++s) {
+          const int kl = 4 * s + kq;
+          if (!SPLIT) {
+            const T b = (T)bv[s];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = A::mfma(khi[srow[mb] + kl], b, acc[mb]);
+          } else {
+            const T bh = (T)bv[s];
+            const T bl = (T)(bv[s] - (double)bh);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+              const T ah = khi[srow[mb] + kl], al = klo[srow[mb] + kl];
+              acc[mb] = A::mfma(ah, bh, acc[mb]);
+              acc[mb] = A::mfma(ah, bl, acc[mb]);
+              acc[mb] = A::mfma(al, bh, acc[mb]);
+            }
+          }
+        }
+      }
+    }
+    if (PREC != 0) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[mb][v] += (double)acc[mb][v];
+        acc[mb] = V{0, 0, 0, 0};
+      }
+    }
+  }
+  store_tile<L, MB, V>(a, bp, col, kq, acc, acc64, PREC != 0);
+}
+
+// ----------------------------------------------------------------------- compressed M2L ----
+template <int L, int RMAX, int PREC>
+__global__ __launch_bounds__(kThreads) void m2l_lowrank_kernel(M2LArgs a) {
+  using A = Arith<PREC>;
+  using T = typename A::T;
+  using V = typename A::V;
+  constexpr int NN = L * L * L;
+  constexpr int NP = (NN + 15) / 16 * 16;
+  constexpr int MB = NP / 16;
+  constexpr int K4 = (NN + 3) / 4;
+  constexpr int ZB = RMAX / 16;             // max M-blocks of GEMM 1
+  constexpr bool SPLIT = PREC == 2;
+  __shared__ T vhi[(NN + 1) * (RMAX + 1)];
+  __shared__ T uhi[(NN + 1) * (RMAX + 1)];
+  __shared__ T vlo[SPLIT ? (NN + 1) * (RMAX + 1) : 1];
+  __shared__ T ulo[SPLIT ? (NN + 1) * (RMAX + 1) : 1];
+  __shared__ T zs[kWaves][RMAX][17];
+
+  BlockPos bp;
+  if (!locate(a, bp)) return;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int j = lane % 16, kq = lane / 16;
+  const Column col = column_of(a, bp, 16 * wave + j);
+  const int set = bp.lv->set;
+
+  V acc[MB];
+  f64x4 acc64[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    acc[mb] = V{0, 0, 0, 0};
+    acc64[mb] = f64x4{0, 0, 0, 0};
+  }
+
+  for (int p = 0; p < kNumSym; ++p) {
+    const int g0 = a.grp[bp.oct * 17 + p], g1 = a.grp[bp.oct * 17 + p + 1];
+    if (g0 == g1) continue;
+    const int r = a.op_rank[set * kNumSym + p];
+    const int rv = (r + 15) / 16 * 16, ru = (r + 3) / 4 * 4;
+    const int ldv = rv + 1, ldu = ru + 1;
+    const long long offu = a.op_off[(set * kNumSym + p) * 2];
+    const long long offv = a.op_off[(set * kNumSym + p) * 2 + 1];
+    const T* Ug = static_cast<const T*>(a.ops_hi) + offu;   // [NN][ru]
+    const T* Vg = static_cast<const T*>(a.ops_hi) + offv;   // [NN][rv]
+    __syncthreads();
+    for (int e = tid; e < (NN + 1) * rv; e += kThreads) {
+      const int row = e / rv, cc = e - row * rv;
+      vhi[row * ldv + cc] = row < NN ? Vg[(long long)row * rv + cc] : T(0);
+      if (SPLIT) vlo[row * ldv + cc] = row < NN ? (static_cast<const T*>(a.ops_lo) + offv)[(long long)row * rv + cc] : T(0);
+    }
+    for (int e = tid; e < (NN + 1) * ru; e += kThreads) {
+      const int row = e / ru, cc = e - row * ru;
+      uhi[row * ldu + cc] = row < NN ? Ug[(long long)row * ru + cc] : T(0);
+      if (SPLIT) ulo[row * ldu + cc] = row < NN ? (static_cast<const T*>(a.ops_lo) + offu)[(long long)row * ru + cc] : T(0);
+    }
+    __syncthreads();
+    const int zb = rv / 16;
+    for (int e = g0; e < g1; ++e) {
+      const int ent = a.tab[bp.oct * kFarPerOctant + e];
+      const int perm = ent >> 13;
+      const double* src = source_of(a, bp, col, ent, NN);
+      const short* sg = a.sig + perm * NP;
+      // GEMM 1: Z[m][j] = sum_k V_p[sigma(k)][m] w_j[k]
+      V z[ZB];
+#pragma unroll
+      for (int b = 0; b < ZB; ++b) z[b] = V{0, 0, 0, 0};
+#pragma unroll 8
+      for (int s = 0; s < K4; ++s) {
+        const int k = 4 * s + kq;
+        const double bv = (src != nullptr && k < NN) ? src[(long long)k * a.nrhs] : 0.0;
+        const int vrow = sg[k] * ldv + j;
+        if (!SPLIT) {
+          const T b = (T)bv;
+#pragma unroll
+          for (int b2 = 0; b2 < ZB; ++b2)
+            if (b2 < zb) z[b2] = A::mfma(vhi[vrow + 16 * b2], b, z[b2]);
+        } else {
+          const T bh = (T)bv, bl = (T)(bv - (double)bh);
+#pragma unroll
+          for (int b2 = 0; b2 < ZB; ++b2)
+            if (b2 < zb) {
+              const T ah = vhi[vrow + 16 * b2], al = vlo[vrow + 16 * b2];
+              z[b2] = A::mfma(ah, bh, z[b2]);
+              z[b2] = A::mfma(ah, bl, z[b2]);
+              z[b2] = A::mfma(al, bh, z[b2]);
+            }
+        }
+      }
+      // accumulator layout -> operand layout through LDS
+#pragma unroll
+      for (int b2 = 0; b2 < ZB; ++b2)
+        if (b2 < zb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) zs[wave][16 * b2 + 4 * kq + v][j] = z[b2][v];
+      __syncthreads();
+      // GEMM 2: F[i][j] += sum_k U_p[sigma(i)][k] Z[k][j]
+      int urow[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) urow[mb] = sg[16 * mb + j] * ldu;
+      for (int s = 0; s < ru / 4; ++s) {
+        const int k = 4 * s + kq;
+        const T bz = zs[wave][k][j];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          acc[mb] = A::mfma(uhi[urow[mb] + k], bz, acc[mb]);
+          if (SPLIT) acc[mb] = A::mfma(ulo[urow[mb] + k], bz, acc[mb]);
+        }
+      }
+      __syncthreads();
+    }
+    if (PREC != 0) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[mb][v] += (double)acc[mb][v];
+        acc[mb] = V{0, 0, 0, 0};
+      }
+    }
+  }
+  store_tile<L, MB, V>(a, bp, col, kq, acc, acc64, PREC != 0);
+}
+
+template <int L> constexpr int full_kc() { return L <= 2 ? 8 : 32; }
+template <int L> constexpr int rank_limit() { return L <= 6 ? 32 : 16; }
+
+template <int L, int PREC>
+hipError_t launch_l(bool lowrank, const M2LArgs& a, hipStream_t s) {
+  const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
+  if (lowrank) {
+    if constexpr (L >= 3) {
+      hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC>), dim3(grid), dim3(kThreads), 0, s, a);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else {
+    hipLaunchKernelGGL((m2l_full_kernel<L, full_kc<L>(), PREC>), dim3(grid), dim3(kThreads), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_prec(int order, bool lowrank, const M2LArgs& a, hipStream_t s) {
+  switch (order) {
+    case 2: return launch_l<2, PREC>(lowrank, a, s);
+    case 3: return launch_l<3, PREC>(lowrank, a, s);
+    case 4: return launch_l<4, PREC>(lowrank, a, s);
+    case 5: return launch_l<5, PREC>(lowrank, a, s);
+    case 6: return launch_l<6, PREC>(lowrank, a, s);
+    case 7: return launch_l<7, PREC>(lowrank, a, s);
+    case 8: return launch_l<8, PREC>(lowrank, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int m2l_ia_rank_limit(int order) {
+  if (order < 3) return 0;
+  return order <= 6 ? 32 : 16;
+}
+
+hipError_t launch_m2l(int order, bool lowrank, int prec, const M2LArgs& a, hipStream_t s) {
+  if (a.nblocks <= 0) return hipSuccess;
+  switch (prec) {
+    case 0: return launch_prec<0>(order, lowrank, a, s);
+    case 1: return launch_prec<1>(order, lowrank, a, s);
+    case 2: return launch_prec<2>(order, lowrank, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+double m2l_issued_flops_per_t(int order, bool lowrank, int rank) {
+  const int nn = order * order * order;
+  const int np = (nn + 15) / 16 * 16;
+  const double mfma = 2.0 * 16 * 16 * 4;   // flops of one 16x16x4 MFMA
+  if (!lowrank) {
+    const int kc = order <= 2 ? 8 : 32;
+    const int nch = (nn + kc - 1) / kc;
+    return (double)(np / 16) * (nch * kc / 4) * mfma * kWaves;
+  }
+  const int rv = (rank + 15) / 16 * 16, ru = (rank + 3) / 4 * 4;
+  const int k4 = (nn + 3) / 4;
+  return ((double)(rv / 16) * k4 + (double)(np / 16) * (ru / 4)) * mfma * kWaves;
+}
+
+}  // namespace bbfmm

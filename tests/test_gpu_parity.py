@@ -1,0 +1,272 @@
+"""HIP path against the CPU oracle, element by element, through the C ABI (needs a gfx950 GPU).
+
+Tolerances: relative L2 1e-12 for the FP64 path (the symmetric/blocked variants compute the
+same operators as the oracle's NA/IA variants, only the summation order differs); FP32 and
+split-FP32 M2L are reported against the FP64 oracle with the bounds written in each test.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bbfmm_oracle as O
+from tests.helpers import morton_to_oracle, oracle_to_morton, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1210_7292_amd as pk  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def cube(n, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    return rng.random((n, 3)), rng.uniform(-1, 1, (n, nrhs))
+
+
+# ------------------------------------------------------------------------------ tree
+
+
+@pytest.mark.parametrize("n,depth", [(5000, 3), (777, 4), (1, 2), (300, 0)])
+def test_tree_order_is_stable_morton_sort(n, depth):
+    say("tree order", n, depth)
+    pts, _ = cube(n, 1, 11)
+    tree = pk.Octree(dev(pts), depth)
+    perm, ls = tree.order()
+    perm, ls = host(perm), host(ls)
+    s = 1 << depth
+    ijk = np.clip(np.floor(pts * s).astype(np.int64), 0, s - 1)
+    key = np.zeros(n, dtype=np.int64)
+    for b in range(depth):
+        for r in range(3):
+            key |= ((ijk[:, r] >> b) & 1) << (3 * b + r)
+    ref = np.argsort(key, kind="stable")
+    assert np.array_equal(perm, ref)
+    counts = np.bincount(key, minlength=8 ** depth)
+    assert np.array_equal(ls, np.concatenate([[0], np.cumsum(counts)]))
+
+
+# ------------------------------------------------------------------------------ M2L alone
+
+
+@pytest.mark.parametrize("order,eps,prec,level,nrhs,tol", [
+    (4, 0.0, "fp64", 3, 1, 1e-12),
+    (4, 0.0, "fp64", 2, 2, 1e-12),
+    (5, 1e-5, "fp64", 3, 1, 1e-12),
+    (5, 1e-5, "fp64", 4, 1, 1e-12),
+    (3, 1e-3, "fp64", 4, 3, 1e-12),
+    (5, 0.0, "fp64", 3, 1, 1e-12),
+    (7, 0.0, "fp64", 3, 1, 1e-12),
+    (4, 0.0, "fp32", 3, 1, 1e-6),
+    (4, 0.0, "split32", 3, 1, 1e-6),
+    (5, 1e-5, "fp32", 3, 1, 1e-6),
+])
+def test_m2l_level_matches_oracle(order, eps, prec, level, nrhs, tol):
+    say("m2l level", order, eps, prec, level, nrhs)
+    pts, _ = cube(64, 1, 1)
+    tree = pk.Octree(dev(pts), level)
+    plan = pk.Plan(tree, "inv_r", order, eps, prec)
+    rng = np.random.default_rng(100 + level)
+    w = rng.standard_normal((8 ** level, order ** 3, nrhs))
+    f_gpu = host(plan.m2l_level(level, dev(oracle_to_morton(w, level))))
+    f_ref = O.m2l_level(w, level, 1.0, order, "inv_r", 0.0, eps)
+    err = rel(morton_to_oracle(f_gpu, level), f_ref)
+    say("  rel err", err)
+    assert err < tol
+
+
+# ------------------------------------------------------------------------------ full apply
+
+
+CASES = [
+    # name, n, nrhs, order, depth, kernel, c, eps, prec, tol
+    ("cfg1_small", 3000, 1, 4, 3, "inv_r", 0.0, 0.0, "fp64", 1e-12),
+    ("ia_p5", 4000, 1, 5, 3, "inv_r", 0.0, 1e-5, "fp64", 1e-12),
+    ("ia_p5_d4", 6000, 1, 5, 4, "inv_r", 0.0, 1e-5, "fp64", 1e-12),
+    ("nrhs3_p3_d4", 2500, 3, 3, 4, "inv_r", 0.0, 0.0, "fp64", 1e-12),
+    ("soft_p3_d4", 2500, 2, 3, 4, "inv_sqrt_r2c2", 1e-3, 0.0, "fp64", 1e-12),
+    ("p7_d3", 2000, 1, 7, 3, "inv_sqrt_r2c2", 1e-3, 0.0, "fp64", 1e-12),
+    ("p2_d3", 1000, 1, 2, 3, "inv_r", 0.0, 0.0, "fp64", 1e-12),
+    ("fp32_p4", 3000, 1, 4, 3, "inv_r", 0.0, 0.0, "fp32", 1e-6),
+    ("split_p7", 2000, 4, 7, 3, "inv_sqrt_r2c2", 1e-3, 0.0, "split32", 1e-6),
+    ("fp32_p7", 2000, 4, 7, 3, "inv_sqrt_r2c2", 1e-3, 0.0, "fp32", 1e-5),
+]
+
+
+@pytest.mark.parametrize("name,n,nrhs,order,depth,kind,c,eps,prec,tol", CASES, ids=[x[0] for x in CASES])
+def test_apply_matches_oracle(name, n, nrhs, order, depth, kind, c, eps, prec, tol):
+    say("apply", name)
+    pts, q = cube(n, nrhs, hash(name) % 1000)
+    phi = host(pk.fmm_apply(dev(pts), dev(q), depth, order, kind, eps, prec, c))
+    ref = O.fmm_apply(pts, q, order, depth, kind, c, eps).phi
+    err = rel(phi, ref)
+    say("  rel err", err)
+    assert err < tol
+
+
+def test_passes_match_oracle():
+    say("passes")
+    pts, q = cube(3000, 2, 5)
+    order, depth = 4, 3
+    tree = pk.Octree(dev(pts), depth)
+    plan = pk.Plan(tree, "inv_r", order, 0.0)
+    plan.apply(dev(q))
+    res = O.fmm_apply(pts, q, order, depth, "inv_r")
+    for lev in range(2, depth + 1):
+        w = morton_to_oracle(host(plan.expansions(lev, 0, 2)), lev)
+        assert rel(w, res.multipoles[lev]) < 1e-13, ("W", lev)
+        f = morton_to_oracle(host(plan.expansions(lev, 2, 2)), lev)
+        assert rel(f, res.locals[lev]) < 1e-12, ("F", lev)
+        fm = morton_to_oracle(host(plan.expansions(lev, 1, 2)), lev)
+        assert rel(fm, res.locals_m2l[lev]) < 1e-12, ("M2L", lev)
+
+
+@pytest.mark.parametrize("kind,order", [("r2", 3), ("r4", 5)])
+def test_polynomial_kernel_equals_brute_force(kind, order):
+    say("poly", kind)
+    pts, q = cube(2000, 1, 6)
+    phi = host(pk.fmm_apply(dev(pts), dev(q), 4, order, kind))
+    assert rel(phi, O.brute_force(pts, q, kind)) < 1e-12
+
+
+@pytest.mark.parametrize("depth", [0, 1])
+def test_shallow_tree_is_brute_force(depth):
+    pts, q = cube(1500, 2, 7)
+    phi = host(pk.fmm_apply(dev(pts), dev(q), depth, 4))
+    assert rel(phi, O.brute_force(pts, q, "inv_r")) < 1e-14
+
+
+def test_ragged_and_degenerate_inputs():
+    say("ragged")
+    rng = np.random.default_rng(8)
+    # fewer points than leaves, many empty cells
+    pts, q = rng.random((37, 3)), rng.uniform(-1, 1, (37, 1))
+    phi = host(pk.fmm_apply(dev(pts), dev(q), 4, 4))
+    assert rel(phi, O.fmm_apply(pts, q, 4, 4).phi) < 1e-12
+    # a single point
+    phi1 = host(pk.fmm_apply(dev(np.array([[0.3, 0.4, 0.5]])), dev(np.array([[2.0]])), 3, 4))
+    assert phi1[0, 0] == 0.0
+    # all points in one leaf, plus points on the upper faces of the root
+    pts2 = np.concatenate([0.01 + 0.001 * rng.random((200, 3)), np.ones((3, 3)), [[1.0, 0.0, 0.5]]])
+    q2 = rng.uniform(-1, 1, (pts2.shape[0], 1))
+    phi2 = host(pk.fmm_apply(dev(pts2), dev(q2), 3, 4))
+    assert rel(phi2, O.fmm_apply(pts2, q2, 4, 3).phi) < 1e-12
+    # coincident distinct points under 1/r contribute nothing
+    pts3 = np.array([[0.5, 0.5, 0.5], [0.5, 0.5, 0.5], [0.1, 0.1, 0.1]])
+    phi3 = host(pk.fmm_apply(dev(pts3), dev(np.ones((3, 1))), 2, 3))
+    assert rel(phi3, O.brute_force(pts3, np.ones((3, 1)), "inv_r")) < 1e-14
+
+
+def test_apply_is_deterministic():
+    pts, q = cube(4000, 1, 9)
+    tree = pk.Octree(dev(pts), 3)
+    plan = pk.Plan(tree, "inv_r", 5, 1e-5)
+    a = host(plan.apply(dev(q)))
+    b = host(plan.apply(dev(q)))
+    assert np.array_equal(a, b)
+
+
+def test_invalid_points_are_rejected():
+    pts = np.array([[0.1, 0.2, 0.3], [1.5, 0.2, 0.3]])
+    with pytest.raises(pk.BBFMMError) as e:
+        pk.Octree(dev(pts), 2)
+    assert e.value.status == -1
+    pts[1, 0] = np.nan
+    with pytest.raises(pk.BBFMMError):
+        pk.Octree(dev(pts), 2, root_width=-1.0)
+
+
+def test_tight_root_cube():
+    rng = np.random.default_rng(12)
+    pts = -3.0 + 2.0 * rng.random((2000, 3))
+    q = rng.uniform(-1, 1, (2000, 1))
+    tree = pk.Octree(dev(pts), 3, root_width=-1.0)
+    st = pk.Plan(tree, "inv_r", 4).stats()
+    lo, w = np.array(st["root_lo"]), st["root_width"]
+    assert np.all(lo <= pts.min(0)) and np.all(lo + w >= pts.max(0))
+    phi = host(pk.fmm_apply(dev(pts), dev(q), 3, 4, root_lo=tuple(lo), root_width=w))
+    assert rel(phi, O.fmm_apply(pts, q, 4, 3, lo=lo, width=w).phi) < 1e-12
+
+
+# ------------------------------------------------------------------------------ adjoint, gradient
+
+
+def test_adjoint_and_gradient_match_oracle():
+    say("adjoint/grad")
+    rng = np.random.default_rng(13)
+    n, order, depth = 1500, 4, 3
+    pts = rng.uniform(0.0, 1.0, (n, 3))
+    q, g = rng.uniform(-1, 1, (n, 1)), rng.uniform(-1, 1, (n, 1))
+    tree = pk.Octree(dev(pts), depth)
+    plan = pk.Plan(tree, "inv_r", order, 1e-6)
+    dq, dg = dev(q), dev(g)
+    plan.apply(dq)
+    atg = host(plan.apply_adjoint(dg))
+    assert rel(atg, O.fmm_adjoint(pts, g, order, depth, eps=1e-6)) < 1e-12
+    grad = host(plan.eval_grad(dq, dg, 3))
+    ref = O.fmm_grad_points(pts, q, g, order, depth, eps=1e-6)
+    assert rel(grad, ref) < 1e-11
+    # roles split the derivative into target and source parts
+    gt = host(plan.eval_grad(dq, dg, 1))
+    gs = host(plan.eval_grad(dq, dg, 2))
+    assert rel(gt + gs, grad) < 1e-14
+
+
+def test_autograd_against_finite_differences():
+    say("autograd")
+    rng = np.random.default_rng(14)
+    n, order, depth = 800, 4, 3
+    pts = rng.uniform(0.02, 0.98, (n, 3))
+    q, g = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    P = dev(pts).requires_grad_(True)
+    Q = dev(q).requires_grad_(True)
+    phi = pk.FMMFunction.apply(P, Q, depth, order)
+    loss = (dev(g) * phi).sum()
+    loss.backward()
+    gp, gq = host(P.grad), host(Q.grad)
+    # dL/dq is linear: exact against the oracle's transposed chain
+    assert rel(gq, O.fmm_adjoint(pts, g[:, None], order, depth)[:, 0]) < 1e-12
+    h = 1e-6
+    tree = O.UniformTree(pts, depth, np.zeros(3), 1.0)
+    for flat in rng.choice(3 * n, 16, replace=False):
+        i, k = divmod(int(flat), 3)
+        pp, pm = pts.copy(), pts.copy()
+        pp[i, k] += h
+        pm[i, k] -= h
+        if not (np.array_equal(O.UniformTree(pp, depth, np.zeros(3), 1.0).leaf, tree.leaf) and
+                np.array_equal(O.UniformTree(pm, depth, np.zeros(3), 1.0).leaf, tree.leaf)):
+            continue
+        lp = float(np.sum(g * host(pk.fmm_apply(dev(pp), dev(q), depth, order))))
+        lm = float(np.sum(g * host(pk.fmm_apply(dev(pm), dev(q), depth, order))))
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - gp[i, k]) < 1e-5 * max(1.0, abs(gp[i, k])), (i, k, fd, gp[i, k])
+
+
+def test_stats_counts():
+    pts, _ = cube(20000, 1, 15)
+    tree = pk.Octree(dev(pts), 4)
+    st = pk.Plan(tree, "inv_r", 5, 1e-5).stats()
+    pairs = sum((6 * (1 << l) - 8) ** 3 - (3 * (1 << l) - 2) ** 3 for l in range(2, 5))
+    assert st["pairs_total"] == pairs
+    # 20000 points in 4096 leaves: every cell is non-empty with overwhelming probability
+    assert st["pairs_nonempty"] <= pairs and st["pairs_nonempty"] > 0.95 * pairs
+    assert st["rank"][0] == 23
+    assert st["m2l_flops_issued"] > st["m2l_flops_algorithmic"]

@@ -1,0 +1,99 @@
+"""The C-ABI library on the CPU: exports, host precompute against the oracle, argument checks.
+
+No GPU is touched: every call here either is host-only or fails validation before any HIP call.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1210_7292_amd as pk
+from paper_1210_7292_amd import binding as B
+from oracle import bbfmm_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_declared_symbol_is_exported():
+    hdr = open(os.path.join(ROOT, "include", "bbfmm.h")).read()
+    declared = set(re.findall(r"\b(bbfmm_[a-z0-9_]+)\s*\(", hdr))
+    assert len(declared) >= 16
+    lib = pk.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == {n for n, _, _ in B.SIGNATURES}
+
+
+def test_representatives_are_the_cone():
+    reps, _, _ = pk.host_symmetry(3, (2, 0, 0))
+    assert len(reps) == 16 and len(set(reps)) == 16
+    assert all(a >= b >= c >= 0 and a in (2, 3) for a, b, c in reps)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_host_symmetry_matches_oracle(order):
+    reps, _, _ = pk.host_symmetry(order, (2, 0, 0))
+    for t in O.far_transfer_vectors():
+        _, p, sig = pk.host_symmetry(order, t)
+        po, so = O.symmetry(t, order)
+        assert reps[p] == po
+        assert np.array_equal(sig, so), t
+
+
+@pytest.mark.parametrize("kind,c,order,width", [("inv_r", 0.0, 4, 1.0), ("inv_r", 0.0, 5, 0.125),
+                                                ("inv_sqrt_r2c2", 1e-3, 3, 1 / 64), ("r4", 0.0, 3, 0.5)])
+def test_host_operators_match_oracle(kind, c, order, width):
+    reps, _, _ = pk.host_symmetry(order, (2, 0, 0))
+    for p, t in enumerate(reps):
+        k, _, _, r = pk.host_operator(kind, order, width, p, 0.0, c)
+        ko = O.m2l_operator(t, width, order, kind, c)
+        assert r == order ** 3
+        # a few ulps: the distance is summed in another order (r^4 magnifies it fourfold)
+        assert np.max(np.abs(k - ko) / np.abs(ko)) <= 4e-15
+
+
+@pytest.mark.parametrize("order,eps", [(4, 1e-4), (5, 1e-5), (3, 1e-3)])
+def test_host_compression_matches_oracle(order, eps):
+    reps, _, _ = pk.host_symmetry(order, (2, 0, 0))
+    for p, t in enumerate(reps):
+        k, u, v, r = pk.host_operator("inv_r", order, 1.0, p, eps)
+        uo, vo, so = O.compress(O.m2l_operator(t, 1.0, order, "inv_r"), eps)
+        assert r == uo.shape[1], (t, r, uo.shape[1])
+        # factors are unique only up to rotation: compare the truncated operators
+        assert np.max(np.abs(u @ v.T - uo @ vo.T)) <= 1e-13 * so[0]
+
+
+def test_jacobi_svd_against_lapack():
+    rng = np.random.default_rng(0)
+    for m, n in [(7, 7), (40, 25), (125, 125)]:
+        a = rng.standard_normal((m, n)) @ np.diag(np.logspace(0, -12, n))
+        s = pk.host_singular_values(a)
+        ref = np.linalg.svd(a, compute_uv=False)
+        assert np.allclose(s, ref, rtol=1e-10, atol=1e-14 * ref[0])
+
+
+def test_validation_without_gpu():
+    lib = pk.lib()
+    out = C.c_void_p()
+    o = B.TreeOpts(3, 0, (C.c_double * 3)(0, 0, 0), 1.0)
+    assert lib.bbfmm_build_octree(None, 10, C.byref(o), None, C.byref(out)) == -1
+    o.depth = 9
+    assert lib.bbfmm_build_octree(C.c_void_p(8), 10, C.byref(o), None, C.byref(out)) == -1
+    assert b"depth" in lib.bbfmm_last_error()
+    o.depth = 3
+    assert lib.bbfmm_build_octree(C.c_void_p(8), 0, C.byref(o), None, C.byref(out)) == -1
+    o.max_leaf_points = 64
+    assert lib.bbfmm_build_octree(C.c_void_p(8), 10, C.byref(o), None, C.byref(out)) == -1
+    po = B.PlanOpts(0, 0.0, 5, 0.0, 0)
+    assert lib.bbfmm_precompute_m2l(None, C.byref(po), None, C.byref(out)) == -1
+    assert lib.bbfmm_apply(None, C.c_void_p(8), 1, C.c_void_p(16), None) == -1
+    assert lib.bbfmm_apply_adjoint(None, C.c_void_p(8), 1, C.c_void_p(16), None) == -1
+    assert lib.bbfmm_eval_grad(None, None, None, 1, 3, None, None) == -1
+    assert lib.bbfmm_host_symmetry(9, None, None, None, None) == -4
+    t = (C.c_int32 * 3)(1, 0, 0)
+    assert lib.bbfmm_host_symmetry(4, t, None, None, None) == -1      # near-field vector
+    k = np.zeros(64 * 64)
+    assert lib.bbfmm_host_operator(7, 0.0, 4, 1.0, 0, 0.0, k.ctypes.data_as(C.c_void_p), None, None, None) == -1
+    assert lib.bbfmm_host_operator(0, 0.0, 4, 1.0, 16, 0.0, k.ctypes.data_as(C.c_void_p), None, None, None) == -1
