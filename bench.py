@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X bbFMM: one FMM matvec phi = A q per step.
+
+Default workload (the configuration the headline metric is quoted on): N = 1,000,000 points
+uniform in the unit cube, kernel 1/r, Chebyshev order 5, uniform octree of depth 6, the 16
+unique M2L operators each SVD-compressed at eps = 1e-5 (IAblk), FP64, one density vector.
+
+A step is one apply: gather -> P2M -> M2M -> M2L (levels 2..6) -> L2L -> L2P -> near field ->
+scatter, with points, densities, tree and operators resident in HBM. Tree build and operator
+precompute are timed once and reported beside it. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split32": 157.3}   # MI355X dense matrix peaks
+KERNEL_NAMES = {"inv_r": "1/r", "inv_sqrt_r2c2": "1/sqrt(r^2+c^2)", "r2": "r^2", "r4": "r^4"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def direct_sum_gpu(torch, pts, q, targets, kernel, c, chunk=1 << 16):
+    """phi_i = sum_{j != i} K(x_i, x_j) q_j at the sample targets, FP64 (measurement only)."""
+    x = pts[targets]                                     # (m, 3)
+    out = torch.zeros((targets.numel(), q.shape[1]), dtype=torch.float64, device=pts.device)
+    for s in range(0, pts.shape[0], chunk):
+        y = pts[s:s + chunk]
+        d2 = ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1)
+        if kernel == "inv_r":
+            k = torch.where(d2 > 0, d2.rsqrt(), torch.zeros_like(d2))
+        elif kernel == "inv_sqrt_r2c2":
+            k = (d2 + c * c).rsqrt()
+        elif kernel == "r2":
+            k = d2
+        else:
+            k = d2 * d2
+        idx = torch.arange(s, s + y.shape[0], device=pts.device)
+        k = torch.where(targets[:, None] == idx[None, :], torch.zeros_like(k), k)
+        out += k @ q[s:s + chunk]
+    return out
+
+
+def cpu_baseline(w, inp, sample_n):
+    """The oracle (as it stands) on a bounded sample of the same workload, on the host cores."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import bbfmm_oracle as O
+    n = min(sample_n, inp.points.shape[0])
+    # keep the points per leaf of the full workload: depth reduced by log8 of the size ratio
+    depth = max(2, int(round(w.depth - np.log(inp.points.shape[0] / n) / np.log(8))))
+    pts = inp.points[:n]
+    q = inp.q[:n]
+    t0 = time.perf_counter()
+    O.fmm_apply(pts, q, w.order, depth, w.kernel, w.c, w.svd_eps)
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    return {"value": n / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {n} points of the workload at depth {depth} (same order, kernel, eps), "
+                      f"one oracle fmm_apply in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, help="workload number (1-4)")
+    ap.add_argument("--prec", default=None, help="override M2L precision: fp64 | fp32 | split32")
+    ap.add_argument("--cpu-sample", type=int, default=100_000, help="points in the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1210_7292_amd as pk
+    from workloads import WORKLOADS, make_inputs
+
+    w = WORKLOADS[args.config]
+    if w.depth < 0:
+        print("the adaptive-tree workload is not built", file=sys.stderr)
+        sys.exit(2)
+    prec = args.prec or w.m2l_prec
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload {w.name}: drawing inputs")
+    inp = make_inputs(w)
+    pts = torch.from_numpy(inp.points).to(dev)
+    q = torch.from_numpy(inp.q).to(dev)
+    out = torch.empty_like(q)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    tree = pk.Octree(pts, w.depth)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    plan = pk.Plan(tree, w.kernel, w.order, w.svd_eps, prec, w.c)
+    st = plan.stats()
+    log(f"[bench] tree {build_ms:.1f} ms, precompute {st['precompute_seconds']:.2f} s, ranks {st['rank']}")
+
+    for _ in range(args.warmup):
+        plan.apply(q, out)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup})")
+
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.apply(q, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    passes, calls = plan.pass_times()
+    plan.set_timing(False)
+    ms_per_step = total_ms / args.steps
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step; passes (ms/step): "
+        + ", ".join(f"{k} {v / max(calls, 1):.3f}" for k, v in passes.items()))
+
+    m2l_ms = passes["m2l"] / max(calls, 1)
+    flops = st["m2l_flops_algorithmic"] * w.nrhs
+    achieved = flops / (m2l_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+
+    err = None
+    if not args.no_error:
+        targets = torch.from_numpy(inp.sample_targets.astype(np.int64)).to(dev)
+        ref = direct_sum_gpu(torch, pts, q, targets, w.kernel, w.c)
+        got = out[targets]
+        err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
+        log(f"[bench] rel L2 error vs direct sum at {targets.numel()} targets: {err:.3e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] oracle on {args.cpu_sample} points (host cores)")
+        cpu = cpu_baseline(w, inp, args.cpu_sample)
+        log(f"[bench] oracle: {cpu['value']:.3e} points/s")
+
+    variant = ("IAblk" if w.svd_eps > 0 else "NAblk")
+    line = {
+        "metric": "FMM points/sec of one apply (bbFMM, symmetry-blocked M2L), with M2L TFLOP/s vs "
+                  "MFMA peak and rel. L2 error",
+        "value": w.n / (ms_per_step * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_points": w.n, "kernel": KERNEL_NAMES[w.kernel], "c": w.c,
+                   "order": w.order, "depth": w.depth, "nrhs": w.nrhs, "svd_eps": w.svd_eps,
+                   "m2l_prec": prec, "m2l_variant": variant},
+        "m2l_gflops": achieved * 1e3,
+        "rel_l2_err_vs_direct": err,
+        "passes_ms_per_step": {k: v / max(calls, 1) for k, v in passes.items()},
+        "tree_build_ms": build_ms,
+        "precompute_s": st["precompute_seconds"],
+        "m2l_pairs_nonempty": st["pairs_nonempty"],
+        "m2l_flops_algorithmic_per_apply": flops,
+        "m2l_flops_issued_per_apply": st["m2l_flops_issued"] * w.nrhs,
+        "roofline": {"bound": "mfma", "kernel": "m2l", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

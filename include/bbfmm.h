@@ -150,6 +150,14 @@ bbfmm_status bbfmm_apply_adjoint(bbfmm_plan* plan, const double* d_g, int32_t nr
 bbfmm_status bbfmm_eval_grad(bbfmm_plan* plan, const double* d_q, const double* d_g, int32_t nrhs,
                              int32_t roles, double* d_grad_x, void* stream);
 
+/* Per-pass tracing. While enabled, every apply-type call records HIP events on its stream between
+ * its passes (no synchronisation). bbfmm_plan_pass_times waits for the recorded events and returns
+ * the milliseconds summed over the calls since timing was (re-)enabled, per pass in the order
+ * gather, P2M, M2M, M2L, L2L, L2P, near field + scatter (out_ms: 7 doubles), and the number of
+ * calls. Enabling resets the sums. Errors: EINVAL (null), EHIP. */
+bbfmm_status bbfmm_plan_set_timing(bbfmm_plan* plan, int32_t enable);
+bbfmm_status bbfmm_plan_pass_times(bbfmm_plan* plan, double* out_ms, int32_t* out_calls);
+
 /* Fills `out`; counts non-empty pairs on the device (synchronises the plan's last stream). */
 bbfmm_status bbfmm_plan_stats(const bbfmm_plan* plan, bbfmm_stats* out);
 

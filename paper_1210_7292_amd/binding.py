@@ -12,6 +12,7 @@ _LIB_PATH = os.path.join(_HERE, "libbbfmm.so")
 
 KERNELS = {"inv_r": 0, "inv_sqrt_r2c2": 1, "r2": 100, "r4": 101}
 PRECISIONS = {"fp64": 0, "fp32": 1, "split32": 2}
+PASS_NAMES = ("gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED", -5: "ESTATE"}
 
 
@@ -51,6 +52,8 @@ SIGNATURES = [
     ("bbfmm_apply_adjoint", C.c_int, [_P, _P, C.c_int32, _P, _P]),
     ("bbfmm_eval_grad", C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
     ("bbfmm_plan_stats", C.c_int, [_P, C.POINTER(Stats)]),
+    ("bbfmm_plan_set_timing", C.c_int, [_P, C.c_int32]),
+    ("bbfmm_plan_pass_times", C.c_int, [_P, _P, _P]),
     ("bbfmm_plan_destroy", None, [_P]),
     ("bbfmm_tree_destroy", None, [_P]),
     ("bbfmm_last_error", C.c_char_p, []),
@@ -244,6 +247,16 @@ class Plan:
 
     def stats(self) -> dict:
         return plan_stats(self.handle)
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().bbfmm_plan_set_timing(self.handle, 1 if enable else 0))
+
+    def pass_times(self):
+        """({pass: summed ms}, calls) over the apply-type calls since set_timing(True)."""
+        ms = (C.c_double * 7)()
+        calls = C.c_int32()
+        _check(lib().bbfmm_plan_pass_times(self.handle, ms, C.byref(calls)))
+        return dict(zip(PASS_NAMES, list(ms))), calls.value
 
     def expansions(self, level: int, which: int, nrhs: int):
         """Copies W (0), the M2L output (1) or the locals (2) of `level` (Morton cell order)."""

@@ -119,6 +119,22 @@ M2LArgs m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double* F, int 
   return a;
 }
 
+enum Pass { kPassStart = -1, kGather = 0, kP2M, kM2M, kM2L, kL2L, kL2P, kP2P, kNumPasses };
+
+// Records an event tagged with the pass that just ended (tracing only).
+hipError_t mark(bbfmm_plan* p, int tag, hipStream_t s) {
+  if (!p->timing) return hipSuccess;
+  if (p->ev_used == p->ev_pool.size()) {
+    hipEvent_t e;
+    hipError_t er = hipEventCreate(&e);
+    if (er != hipSuccess) return er;
+    p->ev_pool.push_back(e);
+    p->ev_tag.push_back(0);
+  }
+  p->ev_tag[p->ev_used] = tag;
+  return hipEventRecord(p->ev_pool[p->ev_used++], s);
+}
+
 // One forward pass of the chain on `in` (caller order) into `out` (caller order); slot 0 keeps
 // the locals of an apply, slot 1 those of an adjoint apply.
 bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, int slot,
@@ -128,23 +144,31 @@ bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, i
   const bbfmm_tree* t = p->tree;
   const PassGeom g = geom_of(p);
   double* qs = p->qs[slot];
+  BBFMM_HIP_TRY(mark(p, kPassStart, s));
   BBFMM_HIP_TRY(launch_gather_rows(in, t->perm, t->n, nrhs, qs, s));
+  BBFMM_HIP_TRY(mark(p, kGather, s));
   const double* far = nullptr;
   if (t->depth >= 2) {
     double* W = p->W;
     double* F = p->F[slot];
     const int d = t->depth;
     BBFMM_HIP_TRY(launch_p2m(g, qs, nrhs, W + p->level_off[d] * nrhs, s));
+    BBFMM_HIP_TRY(mark(p, kP2M, s));
     for (int l = d - 1; l >= 2; --l)
       BBFMM_HIP_TRY(launch_m2m(g, l, W + p->level_off[l + 1] * nrhs, W + p->level_off[l] * nrhs, nrhs, s));
+    BBFMM_HIP_TRY(mark(p, kM2M, s));
     const M2LArgs a = m2l_args(p, nrhs, W, F, -1);
     BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, s));
+    BBFMM_HIP_TRY(mark(p, kM2L, s));
     for (int l = 3; l <= d; ++l)
       BBFMM_HIP_TRY(launch_l2l(g, l - 1, F + p->level_off[l - 1] * nrhs, F + p->level_off[l] * nrhs, nrhs, s));
+    BBFMM_HIP_TRY(mark(p, kL2L, s));
     BBFMM_HIP_TRY(launch_l2p(g, F + p->level_off[d] * nrhs, nrhs, p->phis, s));
+    BBFMM_HIP_TRY(mark(p, kL2P, s));
     far = p->phis;
   }
   BBFMM_HIP_TRY(launch_p2p_scatter(g, qs, far, nrhs, out, s));
+  BBFMM_HIP_TRY(mark(p, kP2P, s));
   p->slot_nrhs[slot] = nrhs;
   return BBFMM_OK;
 }
@@ -425,6 +449,7 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
 
 void bbfmm_plan_destroy(bbfmm_plan* p) {
   if (!p) return;
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   free_buffers(p);
   dfree(p->ops_hi); dfree(p->ops_lo); dfree(p->d_op_off); dfree(p->d_op_rank); dfree(p->d_tab);
   dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
@@ -474,6 +499,31 @@ bbfmm_status bbfmm_eval_grad(bbfmm_plan* p, const double* d_q, const double* d_g
   const double* Fq = t->depth >= 2 ? p->F[0] + p->level_off[t->depth] * nrhs : nullptr;
   const double* Fg = t->depth >= 2 ? p->F[1] + p->level_off[t->depth] * nrhs : nullptr;
   BBFMM_HIP_TRY(launch_grad(g, p->qs[0], p->qs[1], Fq, Fg, nrhs, roles, d_grad_x, s));
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_plan_set_timing(bbfmm_plan* p, int32_t enable) {
+  if (!p) return fail(BBFMM_EINVAL, "plan is null");
+  p->timing = enable != 0;
+  p->ev_used = 0;
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_plan_pass_times(bbfmm_plan* p, double* out_ms, int32_t* out_calls) {
+  if (!p || !out_ms) return fail(BBFMM_EINVAL, "null argument");
+  for (int k = 0; k < kNumPasses; ++k) out_ms[k] = 0.0;
+  int calls = 0;
+  if (p->ev_used > 0) BBFMM_HIP_TRY(hipEventSynchronize(p->ev_pool[p->ev_used - 1]));
+  for (size_t k = 0; k < p->ev_used; ++k) {
+    if (p->ev_tag[k] == kPassStart) {
+      ++calls;
+      continue;
+    }
+    float ms = 0.0f;
+    BBFMM_HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[k - 1], p->ev_pool[k]));
+    out_ms[p->ev_tag[k]] += ms;
+  }
+  if (out_calls) *out_calls = calls;
   return BBFMM_OK;
 }
 

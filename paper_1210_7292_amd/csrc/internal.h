@@ -173,4 +173,9 @@ struct bbfmm_plan {
   int slot_nrhs[2] = {0, 0};                       // nrhs of the last forward / adjoint run
   long long buffer_bytes = 0;
   long long op_bytes = 0;
+  // per-pass tracing: events recorded in order, each tagged with the pass it closes (-1 = start)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_tag;
+  size_t ev_used = 0;
 };

@@ -23,8 +23,9 @@
 //   F += U_p[sigma(i)] Z (GEMM 2); Z passes through LDS to change from accumulator layout to
 //   operand layout.
 //
-// MFMA v_mfma_{f64,f32}_16x16x4: lane l supplies A[l%16][l/16], B[l/16][l%16] and holds
-// D[4(l/16)+v][l%16], v = 0..3.
+// MFMA v_mfma_{f64,f32}_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]. It holds
+// D[row][l%16], v = 0..3, with row = l/16 + 4v for f64 and row = 4(l/16) + v for f32 (the two
+// output layouts differ on gfx950).
 #include "internal.h"
 
 namespace bbfmm {
@@ -54,6 +55,12 @@ template <> struct Arith<1> {
   }
 };
 template <> struct Arith<2> : Arith<1> {};
+
+// Row of D held in accumulator element v by lanes of quarter kq = lane / 16.
+template <int PREC>
+__device__ constexpr int out_row(int kq, int v) {
+  return PREC == 0 ? kq + 4 * v : 4 * kq + v;
+}
 
 struct BlockPos {
   const M2LLevel* lv;
@@ -106,7 +113,7 @@ __device__ inline const double* source_of(const M2LArgs& a, const BlockPos& bp, 
   return bp.lv->W + ((long long)morton3(sx, sy, sz) * nn) * a.nrhs + c.rhs;
 }
 
-template <int L, int MB, typename V>
+template <int L, int MB, int PREC, typename V>
 __device__ inline void store_tile(const M2LArgs& a, const BlockPos& bp, const Column& c, int kq,
                                   const V* acc, const f64x4* acc64, bool use64) {
   constexpr int NN = L * L * L;
@@ -117,7 +124,7 @@ __device__ inline void store_tile(const M2LArgs& a, const BlockPos& bp, const Co
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = 16 * mb + 4 * kq + v;
+      const int i = 16 * mb + out_row<PREC>(kq, v);
       if (i < NN) dst[(long long)i * a.nrhs] = sc * (use64 ? acc64[mb][v] : (double)acc[mb][v]);
     }
 }
@@ -213,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void m2l_full_kernel(M2LArgs a) {
       }
     }
   }
-  store_tile<L, MB, V>(a, bp, col, kq, acc, acc64, PREC != 0);
+  store_tile<L, MB, PREC, V>(a, bp, col, kq, acc, acc64, PREC != 0);
 }
 
 // ----------------------------------------------------------------------- compressed M2L ----
@@ -308,7 +315,7 @@ __global__ __launch_bounds__(kThreads) void m2l_lowrank_kernel(M2LArgs a) {
       for (int b2 = 0; b2 < ZB; ++b2)
         if (b2 < zb)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) zs[wave][16 * b2 + 4 * kq + v][j] = z[b2][v];
+          for (int v = 0; v < 4; ++v) zs[wave][16 * b2 + out_row<PREC>(kq, v)][j] = z[b2][v];
       __syncthreads();
       // GEMM 2: F[i][j] += sum_k U_p[sigma(i)][k] Z[k][j]
       int urow[MB];
@@ -334,7 +341,7 @@ __global__ __launch_bounds__(kThreads) void m2l_lowrank_kernel(M2LArgs a) {
       }
     }
   }
-  store_tile<L, MB, V>(a, bp, col, kq, acc, acc64, PREC != 0);
+  store_tile<L, MB, PREC, V>(a, bp, col, kq, acc, acc64, PREC != 0);
 }
 
 template <int L> constexpr int full_kc() { return L <= 2 ? 8 : 32; }

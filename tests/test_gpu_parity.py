@@ -169,10 +169,14 @@ def test_ragged_and_degenerate_inputs():
     q2 = rng.uniform(-1, 1, (pts2.shape[0], 1))
     phi2 = host(pk.fmm_apply(dev(pts2), dev(q2), 3, 4))
     assert rel(phi2, O.fmm_apply(pts2, q2, 4, 3).phi) < 1e-12
-    # coincident distinct points under 1/r contribute nothing
+    # coincident distinct points under 1/r contribute nothing (near field: exact; with a far
+    # field at depth 2: equal to the oracle's FMM)
     pts3 = np.array([[0.5, 0.5, 0.5], [0.5, 0.5, 0.5], [0.1, 0.1, 0.1]])
-    phi3 = host(pk.fmm_apply(dev(pts3), dev(np.ones((3, 1))), 2, 3))
-    assert rel(phi3, O.brute_force(pts3, np.ones((3, 1)), "inv_r")) < 1e-14
+    one = np.ones((3, 1))
+    phi3 = host(pk.fmm_apply(dev(pts3), dev(one), 0, 3))
+    assert rel(phi3, O.brute_force(pts3, one, "inv_r")) < 1e-14
+    phi4 = host(pk.fmm_apply(dev(pts3), dev(one), 2, 3))
+    assert rel(phi4, O.fmm_apply(pts3, one, 3, 2).phi) < 1e-12
 
 
 def test_apply_is_deterministic():
