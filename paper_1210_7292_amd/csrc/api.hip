@@ -95,7 +95,7 @@ M2LArgs m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double* F, int 
   M2LArgs a;
   std::memset(&a, 0, sizeof(a));
   a.nrhs = nrhs;
-  int blocks = 0, k = 0;
+  int k = 0;
   for (int l = t->depth; l >= 2; --l) {
     if (only_level >= 0 && l != only_level) continue;
     M2LLevel& lv = a.lv[k++];
@@ -104,18 +104,14 @@ M2LArgs m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double* F, int 
     lv.level = l;
     lv.side = 1 << l;
     lv.npar = 1 << (3 * (l - 1));
-    const long long cols = (long long)lv.npar * nrhs;
-    lv.ntiles = (int)((cols + 63) / 64);
-    lv.block_begin = blocks;
-    blocks += 8 * lv.ntiles;
     lv.set = p->set_of_level[l];
     lv.scale = p->scale_of_level[l];
   }
   a.nlev = k;
-  a.nblocks = blocks;
   a.ops_hi = p->ops_hi; a.ops_lo = p->ops_lo;
   a.op_off = p->d_op_off; a.op_rank = p->d_op_rank;
   a.tab = p->d_tab; a.grp = p->d_grp; a.sig = p->d_sig; a.siginv = p->d_siginv;
+  a.zeros = p->d_zeros;
   return a;
 }
 
@@ -405,6 +401,7 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
   auto destroy_partial = [&]() {
     dfree(p->ops_hi); dfree(p->ops_lo); dfree(p->d_op_off); dfree(p->d_op_rank); dfree(p->d_tab);
     dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
+    dfree(p->d_zeros);
   };
   hipError_t e = hipSuccess;
   std::vector<float> hi, lo;
@@ -428,6 +425,8 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
   if (e == hipSuccess) e = up((void**)&p->d_siginv, siginv.data(), siginv.size() * sizeof(short));
   if (e == hipSuccess) e = up((void**)&p->d_tk, tk.data(), tk.size() * sizeof(double));
   if (e == hipSuccess) e = up((void**)&p->d_m2m, m2m.data(), m2m.size() * sizeof(double));
+  const std::vector<double> zeros((size_t)nn * kMaxRhs, 0.0);
+  if (e == hipSuccess) e = up((void**)&p->d_zeros, zeros.data(), zeros.size() * sizeof(double));
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     destroy_partial();
@@ -453,6 +452,7 @@ void bbfmm_plan_destroy(bbfmm_plan* p) {
   free_buffers(p);
   dfree(p->ops_hi); dfree(p->ops_lo); dfree(p->d_op_off); dfree(p->d_op_rank); dfree(p->d_tab);
   dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
+  dfree(p->d_zeros);
   delete p;
 }
 

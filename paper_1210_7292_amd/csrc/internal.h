@@ -75,7 +75,9 @@ struct M2LArgs {
   M2LLevel lv[kMaxLevels];
   int nlev;
   int nrhs;
-  int nblocks;                 // logical blocks
+  int nblocks;                 // logical blocks (filled by launch_m2l)
+  int cols;                    // columns per block (filled by launch_m2l)
+  int remap;
   const void* ops_hi;          // operator data (double or float)
   const void* ops_lo;          // low parts (split precision)
   const long long* op_off;     // [set][16][2]: offset of K (or U) and V, in elements
@@ -84,6 +86,7 @@ struct M2LArgs {
   const int* grp;              // [8][17]
   const short* sig;            // [48][NP]; entries >= l^3 map to l^3
   const short* siginv;         // [48][NP]
+  const double* zeros;         // l^3 * 64 zeros: the multipoles of a missing source
 };
 
 // Returns the LDS-capacity rank limit of the compressed M2L kernel for an order.
@@ -161,6 +164,7 @@ struct bbfmm_plan {
   long long* d_op_off = nullptr; int* d_op_rank = nullptr;
   int* d_tab = nullptr; int* d_grp = nullptr; short* d_sig = nullptr; short* d_siginv = nullptr;
   double* d_tk = nullptr; double* d_m2m = nullptr;
+  double* d_zeros = nullptr;
   std::vector<int> h_tab, h_grp;
   // work buffers
   int nrhs_cap = 0;

@@ -27,6 +27,7 @@
 // D[row][l%16], v = 0..3, with row = l/16 + 4v for f64 and row = 4(l/16) + v for f32 (the two
 // output layouts differ on gfx950).
 #include "internal.h"
+#include <cstdlib>
 
 namespace bbfmm {
 
@@ -63,7 +64,7 @@ __device__ constexpr int out_row(int kq, int v) {
 }
 
 struct BlockPos {
-  const M2LLevel* lv;
+  M2LLevel lv;     // the block's level, by value (uniform)
   int oct;
   int tile;
 };
@@ -73,12 +74,14 @@ __device__ inline bool locate(const M2LArgs& a, BlockPos& bp) {
   // parents are adjacent. Hardware sends block b to XCD b % 8; remapping gives each XCD a
   // contiguous range of logical blocks, keeping shared source cells in one L2.
   const int per = gridDim.x / 8;
-  const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int logical = a.remap ? (blockIdx.x % 8) * per + blockIdx.x / 8 : blockIdx.x;  // EXPERIMENT
   if (logical >= a.nblocks) return false;
-  int k = 0;
-  while (k + 1 < a.nlev && logical >= a.lv[k + 1].block_begin) ++k;
-  bp.lv = &a.lv[k];
-  const int local = logical - bp.lv->block_begin;
+  // static indices only: a dynamic index would copy the argument struct to scratch memory
+  bp.lv = a.lv[0];
+#pragma unroll
+  for (int k = 1; k < kMaxLevels; ++k)
+    if (k < a.nlev && logical >= a.lv[k].block_begin) bp.lv = a.lv[k];
+  const int local = logical - bp.lv.block_begin;
   bp.tile = local / 8;
   bp.oct = local % 8;
   return true;
@@ -93,10 +96,10 @@ struct Column {
 
 __device__ inline Column column_of(const M2LArgs& a, const BlockPos& bp, int col_in_tile) {
   Column c;
-  const int col = bp.tile * kCols + col_in_tile;
+  const int col = bp.tile * a.cols + col_in_tile;
   const int P = col / a.nrhs;
   c.rhs = col - P * a.nrhs;
-  c.valid = P < bp.lv->npar;
+  c.valid = P < bp.lv.npar;
   const unsigned Pm = c.valid ? (unsigned)P : 0u;
   c.target = Pm * 8u + (unsigned)bp.oct;
   demorton3(c.target, c.tx, c.ty, c.tz);
@@ -108,9 +111,9 @@ __device__ inline const double* source_of(const M2LArgs& a, const BlockPos& bp, 
                                           int ent, int nn) {
   const int sx = c.tx + (ent & 7) - 3, sy = c.ty + ((ent >> 3) & 7) - 3,
             sz = c.tz + ((ent >> 6) & 7) - 3;
-  const int side = bp.lv->side;
+  const int side = bp.lv.side;
   if (!c.valid || sx < 0 || sy < 0 || sz < 0 || sx >= side || sy >= side || sz >= side) return nullptr;
-  return bp.lv->W + ((long long)morton3(sx, sy, sz) * nn) * a.nrhs + c.rhs;
+  return bp.lv.W + ((long long)morton3(sx, sy, sz) * nn) * a.nrhs + c.rhs;
 }
 
 template <int L, int MB, int PREC, typename V>
@@ -118,8 +121,8 @@ __device__ inline void store_tile(const M2LArgs& a, const BlockPos& bp, const Co
                                   const V* acc, const f64x4* acc64, bool use64) {
   constexpr int NN = L * L * L;
   if (!c.valid) return;
-  const double sc = bp.lv->scale;
-  double* dst = bp.lv->F + ((long long)c.target * NN) * a.nrhs + c.rhs;
+  const double sc = bp.lv.scale;
+  double* dst = bp.lv.F + ((long long)c.target * NN) * a.nrhs + c.rhs;
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(kThreads) void m2l_full_kernel(M2LArgs a) {
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int j = lane % 16, kq = lane / 16;
   const Column col = column_of(a, bp, 16 * wave + j);
-  const int set = bp.lv->set;
+  const int set = bp.lv.set;
 
   V acc[MB];
   f64x4 acc64[MB];
@@ -224,29 +227,125 @@ __global__ __launch_bounds__(kThreads) void m2l_full_kernel(M2LArgs a) {
 }
 
 // ----------------------------------------------------------------------- compressed M2L ----
-template <int L, int RMAX, int PREC>
-__global__ __launch_bounds__(kThreads) void m2l_lowrank_kernel(M2LArgs a) {
+// One workgroup of W8 waves owns 16 * W8 columns. The 189 transfer vectors of the block's octant
+// are visited in representative order; the factors U_p, V_p of the current representative and
+// the 48 permutation tables live in LDS. Per transfer vector and wave:
+//   GEMM 1: Z = V_p[sigma(k)]^T w over k = 0..l^3, B operand from registers loaded one transfer
+//           vector ahead; super-step c covers k = 16 c + 4 kq + u (u = 0..3 in turn), the order
+//           in which each lane loads its column;
+//   GEMM 2: F += U_p[sigma(i)] Z, with B taken straight from GEMM 1's accumulators: element v
+//           of quarter kq holds Z row 16 b + out_row(kq, v), and GEMM 2 runs its k in that
+//           order, so nothing moves between the two products.
+// Invalid columns and sources outside the level read a zero buffer; k >= l^3 reads a real entry
+// that meets the zero row l^3 of V in LDS. The loads therefore need no branches.
+typedef __attribute__((address_space(1))) const double gdouble;
+
+template <int L, int RMAX, int PREC, int W8>
+struct Lowrank {
   using A = Arith<PREC>;
   using T = typename A::T;
   using V = typename A::V;
-  constexpr int NN = L * L * L;
-  constexpr int NP = (NN + 15) / 16 * 16;
-  constexpr int MB = NP / 16;
-  constexpr int K4 = (NN + 3) / 4;
-  constexpr int ZB = RMAX / 16;             // max M-blocks of GEMM 1
-  constexpr bool SPLIT = PREC == 2;
-  __shared__ T vhi[(NN + 1) * (RMAX + 1)];
-  __shared__ T uhi[(NN + 1) * (RMAX + 1)];
-  __shared__ T vlo[SPLIT ? (NN + 1) * (RMAX + 1) : 1];
-  __shared__ T ulo[SPLIT ? (NN + 1) * (RMAX + 1) : 1];
-  __shared__ T zs[kWaves][RMAX][17];
+  static constexpr int NN = L * L * L;
+  static constexpr int NP = (NN + 15) / 16 * 16;
+  static constexpr int MB = NP / 16;
+  static constexpr int K16 = NP / 16;
+  static constexpr int LD = RMAX + 1;
+  static constexpr bool SPLIT = PREC == 2;
+  static constexpr bool PREFETCH = K16 <= 8;
+  // chunk of super-steps held in registers: the whole column with 4 waves; half of it with 8
+  // waves (2 waves per SIMD halve the register budget; the other wave covers the second load)
+  static constexpr int CH = PREFETCH ? (W8 == 4 ? K16 : (K16 + 1) / 2) : 4;
+  static constexpr int NCHUNK = (K16 + CH - 1) / CH;
+
+  static __device__ inline void load(gdouble* src, int nrhs, int kq, int c0, double (&w)[CH][4]) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int k = 16 * (c0 + c) + 4 * kq + u;
+        k = k < NN ? k : NN - 1;
+        w[c][u] = src[(long long)k * nrhs];
+      }
+  }
+
+  template <int ZB>
+  static __device__ inline void gemm1(const T* vhi, const T* vlo, const short* sg, int j, int kq,
+                                      int c0, const double (&w)[CH][4], V (&z)[2]) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (c0 + c >= K16) break;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 16 * (c0 + c) + 4 * kq + u;
+        const int vrow = sg[k] * LD + j;
+        const double bv = w[c][u];
+        if (!SPLIT) {
+          const T b = (T)bv;
+#pragma unroll
+          for (int b2 = 0; b2 < ZB; ++b2) z[b2] = A::mfma(vhi[vrow + 16 * b2], b, z[b2]);
+        } else {
+          const T bh = (T)bv, bl = (T)(bv - (double)bh);
+#pragma unroll
+          for (int b2 = 0; b2 < ZB; ++b2) {
+            const T ah = vhi[vrow + 16 * b2], al = vlo[vrow + 16 * b2];
+            z[b2] = A::mfma(ah, bh, z[b2]);
+            z[b2] = A::mfma(ah, bl, z[b2]);
+            z[b2] = A::mfma(al, bh, z[b2]);
+          }
+        }
+      }
+    }
+  }
+
+  template <int ZB>
+  static __device__ inline void gemm2(const T* uhi, const T* ulo, const int (&urow)[MB], int kq, int r,
+                                      const V (&z)[2], V (&acc)[MB]) {
+#pragma unroll
+    for (int b2 = 0; b2 < ZB; ++b2)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (16 * b2 + (PREC == 0 ? 4 * v : v) >= r) continue;   // uniform: columns beyond the rank
+        const int kcol = 16 * b2 + out_row<PREC>(kq, v);
+        const T bz = z[b2][v];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          acc[mb] = A::mfma(uhi[urow[mb] + kcol], bz, acc[mb]);
+          if (SPLIT) acc[mb] = A::mfma(ulo[urow[mb] + kcol], bz, acc[mb]);
+        }
+      }
+  }
+};
+
+template <int L, int RMAX, int PREC, int W8>
+__global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
+  using K = Lowrank<L, RMAX, PREC, W8>;
+  using T = typename K::T;
+  using V = typename K::V;
+  constexpr int NT = 64 * W8;
+  constexpr int NN = K::NN, NP = K::NP, MB = K::MB, K16 = K::K16, LD = K::LD, CH = K::CH;
+  constexpr bool SPLIT = K::SPLIT, PREFETCH = K::PREFETCH;
+  static_assert(RMAX == 16 || RMAX == 32, "GEMM 1 has one or two row blocks");
+  __shared__ T vhi[(NN + 1) * LD];
+  __shared__ T uhi[(NN + 1) * LD];
+  __shared__ T vlo[SPLIT ? (NN + 1) * LD : 1];
+  __shared__ T ulo[SPLIT ? (NN + 1) * LD : 1];
+  // permutation tables in LDS when they fit beside the factors
+  constexpr bool SIGLDS = (2 * (SPLIT ? 2 : 1) * (NN + 1) * LD * (int)sizeof(T) + kNumPerms * NP * 2) <= 160 * 1024;
+  __shared__ short sgs[SIGLDS ? kNumPerms * NP : 1];
 
   BlockPos bp;
   if (!locate(a, bp)) return;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int j = lane % 16, kq = lane / 16;
   const Column col = column_of(a, bp, 16 * wave + j);
-  const int set = bp.lv->set;
+  const int set = bp.lv.set;
+  const int nrhs = a.nrhs;
+  const int* tab = a.tab + bp.oct * kFarPerOctant;
+  gdouble* zero_src = (gdouble*)a.zeros + col.rhs;
+
+  if (SIGLDS)
+    for (int e = tid; e < kNumPerms * NP; e += NT) sgs[e] = a.sig[e];
+  const short* sgbase = SIGLDS ? sgs : a.sig;
 
   V acc[MB];
   f64x4 acc64[MB];
@@ -256,83 +355,64 @@ __global__ __launch_bounds__(kThreads) void m2l_lowrank_kernel(M2LArgs a) {
     acc64[mb] = f64x4{0, 0, 0, 0};
   }
 
-  for (int p = 0; p < kNumSym; ++p) {
-    const int g0 = a.grp[bp.oct * 17 + p], g1 = a.grp[bp.oct * 17 + p + 1];
-    if (g0 == g1) continue;
-    const int r = a.op_rank[set * kNumSym + p];
-    const int rv = (r + 15) / 16 * 16, ru = (r + 3) / 4 * 4;
-    const int ldv = rv + 1, ldu = ru + 1;
-    const long long offu = a.op_off[(set * kNumSym + p) * 2];
-    const long long offv = a.op_off[(set * kNumSym + p) * 2 + 1];
-    const T* Ug = static_cast<const T*>(a.ops_hi) + offu;   // [NN][ru]
-    const T* Vg = static_cast<const T*>(a.ops_hi) + offv;   // [NN][rv]
-    __syncthreads();
-    for (int e = tid; e < (NN + 1) * rv; e += kThreads) {
-      const int row = e / rv, cc = e - row * rv;
-      vhi[row * ldv + cc] = row < NN ? Vg[(long long)row * rv + cc] : T(0);
-      if (SPLIT) vlo[row * ldv + cc] = row < NN ? (static_cast<const T*>(a.ops_lo) + offv)[(long long)row * rv + cc] : T(0);
-    }
-    for (int e = tid; e < (NN + 1) * ru; e += kThreads) {
-      const int row = e / ru, cc = e - row * ru;
-      uhi[row * ldu + cc] = row < NN ? Ug[(long long)row * ru + cc] : T(0);
-      if (SPLIT) ulo[row * ldu + cc] = row < NN ? (static_cast<const T*>(a.ops_lo) + offu)[(long long)row * ru + cc] : T(0);
-    }
-    __syncthreads();
-    const int zb = rv / 16;
-    for (int e = g0; e < g1; ++e) {
-      const int ent = a.tab[bp.oct * kFarPerOctant + e];
-      const int perm = ent >> 13;
-      const double* src = source_of(a, bp, col, ent, NN);
-      const short* sg = a.sig + perm * NP;
-      // GEMM 1: Z[m][j] = sum_k V_p[sigma(k)][m] w_j[k]
-      V z[ZB];
-#pragma unroll
-      for (int b = 0; b < ZB; ++b) z[b] = V{0, 0, 0, 0};
-#pragma unroll 8
-      for (int s = 0; s < K4; ++s) {
-        const int k = 4 * s + kq;
-        const double bv = (src != nullptr && k < NN) ? src[(long long)k * a.nrhs] : 0.0;
-        const int vrow = sg[k] * ldv + j;
-        if (!SPLIT) {
-          const T b = (T)bv;
-#pragma unroll
-          for (int b2 = 0; b2 < ZB; ++b2)
-            if (b2 < zb) z[b2] = A::mfma(vhi[vrow + 16 * b2], b, z[b2]);
-        } else {
-          const T bh = (T)bv, bl = (T)(bv - (double)bh);
-#pragma unroll
-          for (int b2 = 0; b2 < ZB; ++b2)
-            if (b2 < zb) {
-              const T ah = vhi[vrow + 16 * b2], al = vlo[vrow + 16 * b2];
-              z[b2] = A::mfma(ah, bh, z[b2]);
-              z[b2] = A::mfma(ah, bl, z[b2]);
-              z[b2] = A::mfma(al, bh, z[b2]);
-            }
-        }
-      }
-      // accumulator layout -> operand layout through LDS
-#pragma unroll
-      for (int b2 = 0; b2 < ZB; ++b2)
-        if (b2 < zb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) zs[wave][16 * b2 + out_row<PREC>(kq, v)][j] = z[b2][v];
+  auto source = [&](int ent) -> gdouble* {
+    const double* s = source_of(a, bp, col, ent, NN);
+    return s ? (gdouble*)s : zero_src;
+  };
+
+  double w[CH][4];
+  int cur_p = -1, r = 0, zb = 0;
+  gdouble* src = source(tab[0]);
+  if (PREFETCH) K::load(src, nrhs, kq, 0, w);
+  for (int e = 0; e < kFarPerOctant; ++e) {
+    const int ent = tab[e];
+    const int p = (ent >> 9) & 15;
+    if (p != cur_p) {
       __syncthreads();
-      // GEMM 2: F[i][j] += sum_k U_p[sigma(i)][k] Z[k][j]
-      int urow[MB];
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) urow[mb] = sg[16 * mb + j] * ldu;
-      for (int s = 0; s < ru / 4; ++s) {
-        const int k = 4 * s + kq;
-        const T bz = zs[wave][k][j];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          acc[mb] = A::mfma(uhi[urow[mb] + k], bz, acc[mb]);
-          if (SPLIT) acc[mb] = A::mfma(ulo[urow[mb] + k], bz, acc[mb]);
+      cur_p = p;
+      r = a.op_rank[set * kNumSym + p];
+      zb = (r + 15) / 16;
+      const int rv = 16 * zb, ru = (r + 3) / 4 * 4;
+      const long long offu = a.op_off[(set * kNumSym + p) * 2];
+      const long long offv = a.op_off[(set * kNumSym + p) * 2 + 1];
+      const T* Ug = static_cast<const T*>(a.ops_hi) + offu;   // [NN][ru]
+      const T* Vg = static_cast<const T*>(a.ops_hi) + offv;   // [NN][rv]
+      const T* Ul = SPLIT ? static_cast<const T*>(a.ops_lo) + offu : nullptr;
+      const T* Vl = SPLIT ? static_cast<const T*>(a.ops_lo) + offv : nullptr;
+      for (int x = tid; x < (NN + 1) * rv; x += NT) {
+        const int row = x / rv, cc = x - row * rv;
+        const bool in = row < NN;
+        vhi[row * LD + cc] = in ? Vg[(long long)row * rv + cc] : T(0);
+        uhi[row * LD + cc] = (in && cc < ru) ? Ug[(long long)row * ru + cc] : T(0);
+        if (SPLIT) {
+          vlo[row * LD + cc] = in ? Vl[(long long)row * rv + cc] : T(0);
+          ulo[row * LD + cc] = (in && cc < ru) ? Ul[(long long)row * ru + cc] : T(0);
         }
       }
       __syncthreads();
     }
-    if (PREC != 0) {
+    const short* sg = sgbase + (ent >> 13) * NP;
+    // ---- GEMM 1 ----
+    V z[2] = {V{0, 0, 0, 0}, V{0, 0, 0, 0}};
+#pragma unroll
+    for (int c0 = 0; c0 < K16; c0 += CH) {
+      if (!PREFETCH || c0 > 0) K::load(src, nrhs, kq, c0, w);
+      if (zb == 1) K::template gemm1<1>(vhi, vlo, sg, j, kq, c0, w, z);
+      else K::template gemm1<RMAX / 16>(vhi, vlo, sg, j, kq, c0, w, z);
+    }
+    // ---- next transfer vector's multipoles, in flight during GEMM 2 ----
+    if (e + 1 < kFarPerOctant) {
+      src = source(tab[e + 1]);
+      if (PREFETCH) K::load(src, nrhs, kq, 0, w);
+    }
+    // ---- GEMM 2 ----
+    int urow[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) urow[mb] = sg[16 * mb + j] * LD;
+    if (zb == 1) K::template gemm2<1>(uhi, ulo, urow, kq, r, z, acc);
+    else K::template gemm2<RMAX / 16>(uhi, ulo, urow, kq, r, z, acc);
+    // flush the FP32 accumulators into FP64 at the end of each representative's group
+    if (PREC != 0 && (e + 1 == kFarPerOctant || ((tab[e + 1] >> 9) & 15) != p)) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
@@ -346,17 +426,43 @@ __global__ __launch_bounds__(kThreads) void m2l_lowrank_kernel(M2LArgs a) {
 
 template <int L> constexpr int full_kc() { return L <= 2 ? 8 : 32; }
 template <int L> constexpr int rank_limit() { return L <= 6 ? 32 : 16; }
+constexpr int kLowrankWaves = 8;
+
+// Fills the per-level tiling for `cols` columns per block.
+void tile(M2LArgs& a, int cols) {
+  int blocks = 0;
+  a.cols = cols;
+  for (int k = 0; k < a.nlev; ++k) {
+    M2LLevel& lv = a.lv[k];
+    const long long c = (long long)lv.npar * a.nrhs;
+    lv.ntiles = (int)((c + cols - 1) / cols);
+    lv.block_begin = blocks;
+    blocks += 8 * lv.ntiles;
+  }
+  a.nblocks = blocks;
+}
 
 template <int L, int PREC>
-hipError_t launch_l(bool lowrank, const M2LArgs& a, hipStream_t s) {
-  const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
+hipError_t launch_l(bool lowrank, M2LArgs a, hipStream_t s) {
   if (lowrank) {
     if constexpr (L >= 3) {
-      hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC>), dim3(grid), dim3(kThreads), 0, s, a);
+      static const int waves = getenv("BBFMM_EXP_WAVES") ? atoi(getenv("BBFMM_EXP_WAVES")) : kLowrankWaves;  // EXPERIMENT
+      if (waves == 4) {
+        tile(a, 16 * 4);
+        const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
+        hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, 4>), dim3(grid), dim3(64 * 4), 0, s, a);
+        return hipGetLastError();
+      }
+      tile(a, 16 * kLowrankWaves);
+      const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
+      hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves>), dim3(grid),
+                         dim3(64 * kLowrankWaves), 0, s, a);
     } else {
       return hipErrorInvalidValue;
     }
   } else {
+    tile(a, kCols);
+    const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
     hipLaunchKernelGGL((m2l_full_kernel<L, full_kc<L>(), PREC>), dim3(grid), dim3(kThreads), 0, s, a);
   }
   return hipGetLastError();
@@ -383,8 +489,10 @@ int m2l_ia_rank_limit(int order) {
   return order <= 6 ? 32 : 16;
 }
 
-hipError_t launch_m2l(int order, bool lowrank, int prec, const M2LArgs& a, hipStream_t s) {
-  if (a.nblocks <= 0) return hipSuccess;
+hipError_t launch_m2l(int order, bool lowrank, int prec, const M2LArgs& a0, hipStream_t s) {
+  if (a0.nlev <= 0) return hipSuccess;
+  M2LArgs a = a0;
+  a.remap = getenv("BBFMM_EXP_REMAP") ? atoi(getenv("BBFMM_EXP_REMAP")) : 1;  // EXPERIMENT
   switch (prec) {
     case 0: return launch_prec<0>(order, lowrank, a, s);
     case 1: return launch_prec<1>(order, lowrank, a, s);
@@ -394,17 +502,18 @@ hipError_t launch_m2l(int order, bool lowrank, int prec, const M2LArgs& a, hipSt
 }
 
 double m2l_issued_flops_per_t(int order, bool lowrank, int rank) {
+  // per 64 columns
   const int nn = order * order * order;
   const int np = (nn + 15) / 16 * 16;
   const double mfma = 2.0 * 16 * 16 * 4;   // flops of one 16x16x4 MFMA
   if (!lowrank) {
     const int kc = order <= 2 ? 8 : 32;
     const int nch = (nn + kc - 1) / kc;
-    return (double)(np / 16) * (nch * kc / 4) * mfma * kWaves;
+    return (double)(np / 16) * (nch * kc / 4) * mfma * 4;
   }
-  const int rv = (rank + 15) / 16 * 16, ru = (rank + 3) / 4 * 4;
-  const int k4 = (nn + 3) / 4;
-  return ((double)(rv / 16) * k4 + (double)(np / 16) * (ru / 4)) * mfma * kWaves;
+  const int zb = (rank + 15) / 16;
+  const int steps2 = (rank + 3) / 4;
+  return ((double)zb * (np / 4) + (double)(np / 16) * steps2) * mfma * 4;
 }
 
 }  // namespace bbfmm
