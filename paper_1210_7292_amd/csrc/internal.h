@@ -77,7 +77,6 @@ struct M2LArgs {
   int nrhs;
   int nblocks;                 // logical blocks (filled by launch_m2l)
   int cols;                    // columns per block (filled by launch_m2l)
-  int remap;
   const void* ops_hi;          // operator data (double or float)
   const void* ops_lo;          // low parts (split precision)
   const long long* op_off;     // [set][16][2]: offset of K (or U) and V, in elements

@@ -27,7 +27,6 @@
 // D[row][l%16], v = 0..3, with row = l/16 + 4v for f64 and row = 4(l/16) + v for f32 (the two
 // output layouts differ on gfx950).
 #include "internal.h"
-#include <cstdlib>
 
 namespace bbfmm {
 
@@ -74,7 +73,7 @@ __device__ inline bool locate(const M2LArgs& a, BlockPos& bp) {
   // parents are adjacent. Hardware sends block b to XCD b % 8; remapping gives each XCD a
   // contiguous range of logical blocks, keeping shared source cells in one L2.
   const int per = gridDim.x / 8;
-  const int logical = a.remap ? (blockIdx.x % 8) * per + blockIdx.x / 8 : blockIdx.x;  // EXPERIMENT
+  const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= a.nblocks) return false;
   // static indices only: a dynamic index would copy the argument struct to scratch memory
   bp.lv = a.lv[0];
@@ -446,13 +445,6 @@ template <int L, int PREC>
 hipError_t launch_l(bool lowrank, M2LArgs a, hipStream_t s) {
   if (lowrank) {
     if constexpr (L >= 3) {
-      static const int waves = getenv("BBFMM_EXP_WAVES") ? atoi(getenv("BBFMM_EXP_WAVES")) : kLowrankWaves;  // EXPERIMENT
-      if (waves == 4) {
-        tile(a, 16 * 4);
-        const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
-        hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, 4>), dim3(grid), dim3(64 * 4), 0, s, a);
-        return hipGetLastError();
-      }
       tile(a, 16 * kLowrankWaves);
       const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
       hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves>), dim3(grid),
@@ -491,8 +483,7 @@ int m2l_ia_rank_limit(int order) {
 
 hipError_t launch_m2l(int order, bool lowrank, int prec, const M2LArgs& a0, hipStream_t s) {
   if (a0.nlev <= 0) return hipSuccess;
-  M2LArgs a = a0;
-  a.remap = getenv("BBFMM_EXP_REMAP") ? atoi(getenv("BBFMM_EXP_REMAP")) : 1;  // EXPERIMENT
+  const M2LArgs& a = a0;
   switch (prec) {
     case 0: return launch_prec<0>(order, lowrank, a, s);
     case 1: return launch_prec<1>(order, lowrank, a, s);
