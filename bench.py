@@ -50,7 +50,7 @@ def direct_sum_gpu(torch, pts, q, targets, kernel, c, chunk=1 << 16):
     return out
 
 
-def cpu_baseline(w, inp, sample_n):
+def cpu_baseline(w, inp, sample_n, grad_mode=False):
     """The oracle (as it stands) on a bounded sample of the same workload, on the host cores."""
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -63,11 +63,14 @@ def cpu_baseline(w, inp, sample_n):
     q = inp.q[:n]
     t0 = time.perf_counter()
     O.fmm_apply(pts, q, w.order, depth, w.kernel, w.c, w.svd_eps)
+    if grad_mode:
+        O.fmm_adjoint(pts, inp.g[:n], w.order, depth, w.kernel, w.c, w.svd_eps)
+        O.fmm_grad_points(pts, q, inp.g[:n], w.order, depth, w.kernel, w.c, w.svd_eps)
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     return {"value": n / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
             "sample": f"first {n} points of the workload at depth {depth} (same order, kernel, eps), "
-                      f"one oracle fmm_apply in {dt:.2f} s"}
+                      f"one oracle {'apply + adjoint + gradient' if grad_mode else 'fmm_apply'} in {dt:.2f} s"}
 
 
 def main():
@@ -77,7 +80,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, help="workload number (1-4)")
     ap.add_argument("--prec", default=None, help="override M2L precision: fp64 | fp32 | split32")
-    ap.add_argument("--cpu-sample", type=int, default=100_000, help="points in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="points in the oracle sample (default: 100000; 20000 for order 7)")
+    ap.add_argument("--variants", action="store_true",
+                    help="also time the other M2L precisions and report their errors vs this one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -125,8 +131,20 @@ def main():
     st = plan.stats()
     log(f"[bench] tree {build_ms:.1f} ms, precompute {st['precompute_seconds']:.2f} s, ranks {st['rank']}")
 
-    for _ in range(args.warmup):
+    # config 4 differentiates: a step is forward, adjoint and position gradient
+    grad_mode = args.config == 4
+    g = torch.from_numpy(inp.g).to(dev) if grad_mode else None
+    grad_x = torch.empty((w.n, 3), dtype=torch.float64, device=dev) if grad_mode else None
+    gq = torch.empty_like(q) if grad_mode else None
+
+    def step():
         plan.apply(q, out)
+        if grad_mode:
+            plan.apply_adjoint(g, gq)
+            plan.eval_grad(q, g, 3, grad_x)
+
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     log(f"[bench] warmup done ({args.warmup})")
 
@@ -136,22 +154,25 @@ def main():
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
-        plan.apply(q, out)
+        step()
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
     passes, calls = plan.pass_times()
     plan.set_timing(False)
     ms_per_step = total_ms / args.steps
-    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step; passes (ms/step): "
+    # per-launch averages: an apply-type call runs every pass once
+    calls = max(calls, 1)
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step; passes (ms per apply-type call): "
         + ", ".join(f"{k} {v / max(calls, 1):.3f}" for k, v in passes.items()))
 
-    m2l_ms = passes["m2l"] / max(calls, 1)
+    m2l_ms = passes["m2l"] / calls
     flops = st["m2l_flops_algorithmic"] * w.nrhs
     achieved = flops / (m2l_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
 
     err = None
+    targets = ref = None
     if not args.no_error:
         targets = torch.from_numpy(inp.sample_targets.astype(np.int64)).to(dev)
         ref = direct_sum_gpu(torch, pts, q, targets, w.kernel, w.c)
@@ -159,10 +180,40 @@ def main():
         err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
         log(f"[bench] rel L2 error vs direct sum at {targets.numel()} targets: {err:.3e}")
 
+    variants = None
+    if args.variants:
+        variants = []
+        for other in ("fp64", "fp32", "split32"):
+            if other == prec:
+                continue
+            p2 = pk.Plan(tree, w.kernel, w.order, w.svd_eps, other, w.c)
+            o2 = torch.empty_like(q)
+            p2.apply(q, o2)
+            torch.cuda.synchronize()
+            p2.set_timing(True)
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            for _ in range(args.steps):
+                p2.apply(q, o2)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            pt, pc = p2.pass_times()
+            v = {"m2l_prec": other, "ms_per_step": a0.elapsed_time(a1) / args.steps,
+                 "m2l_ms": pt["m2l"] / max(pc, 1),
+                 "rel_l2_vs_" + prec: float(torch.linalg.norm(o2 - out) / torch.linalg.norm(out))}
+            v["m2l_tflops"] = flops / (v["m2l_ms"] * 1e-3) / 1e12
+            if err is not None:
+                got2 = o2[targets]
+                v["rel_l2_err_vs_direct"] = float(torch.linalg.norm(got2 - ref) / torch.linalg.norm(ref))
+            log(f"[bench] variant {v}")
+            variants.append(v)
+            del p2, o2
+
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"[bench] oracle on {args.cpu_sample} points (host cores)")
-        cpu = cpu_baseline(w, inp, args.cpu_sample)
+        n_cpu = args.cpu_sample or (20_000 if w.order >= 7 else 100_000)
+        log(f"[bench] oracle on {n_cpu} points (host cores)")
+        cpu = cpu_baseline(w, inp, n_cpu, grad_mode)
         log(f"[bench] oracle: {cpu['value']:.3e} points/s")
 
     # HBM traffic of the M2L launch from the committed rocprofv3 counters, only while the kernel
@@ -198,7 +249,7 @@ def main():
                    "m2l_prec": prec, "m2l_variant": variant},
         "m2l_gflops": achieved * 1e3,
         "rel_l2_err_vs_direct": err,
-        "passes_ms_per_step": {k: v / max(calls, 1) for k, v in passes.items()},
+        "passes_ms_per_call": {k: v / calls for k, v in passes.items()},
         "tree_build_ms": build_ms,
         "precompute_s": st["precompute_seconds"],
         "m2l_pairs_nonempty": st["pairs_nonempty"],
@@ -209,6 +260,12 @@ def main():
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)"},
         "cpu_baseline": cpu,
     }
+    if grad_mode:
+        line["metric"] = ("FMM points/sec of one forward + adjoint + position-gradient step (bbFMM, "
+                          "symmetry-blocked M2L), with M2L TFLOP/s vs MFMA peak")
+        line["config"]["step"] = "apply(q) + apply_adjoint(g) + eval_grad(q, g)"
+    if variants is not None:
+        line["precision_variants"] = variants
     print(json.dumps(line), flush=True)
 
 

@@ -211,14 +211,16 @@ __global__ __launch_bounds__(kThreads) void m2l_full_kernel(M2LArgs a) {
             }
           }
         }
-      }
-    }
-    if (PREC != 0) {
+        // FP32 modes: each (transfer vector, k chunk) product of KC terms is accumulated in FP32
+        // by the MFMA and then added into FP64
+        if (PREC != 0) {
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
+          for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc64[mb][v] += (double)acc[mb][v];
-        acc[mb] = V{0, 0, 0, 0};
+            for (int v = 0; v < 4; ++v) acc64[mb][v] += (double)acc[mb][v];
+            acc[mb] = V{0, 0, 0, 0};
+          }
+        }
       }
     }
   }
@@ -410,8 +412,8 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
     for (int mb = 0; mb < MB; ++mb) urow[mb] = sg[16 * mb + j] * LD;
     if (zb == 1) K::template gemm2<1>(uhi, ulo, urow, kq, r, z, acc);
     else K::template gemm2<RMAX / 16>(uhi, ulo, urow, kq, r, z, acc);
-    // flush the FP32 accumulators into FP64 at the end of each representative's group
-    if (PREC != 0 && (e + 1 == kFarPerOctant || ((tab[e + 1] >> 9) & 15) != p)) {
+    // FP32 modes: each transfer vector's product is accumulated in FP32 and then added into FP64
+    if (PREC != 0) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll

@@ -274,3 +274,60 @@ def test_stats_counts():
     assert st["pairs_nonempty"] <= pairs and st["pairs_nonempty"] > 0.95 * pairs
     assert st["rank"][0] == 23
     assert st["m2l_flops_issued"] > st["m2l_flops_algorithmic"]
+
+
+# ------------------------------------------------------------------------------ full sizes
+
+
+def test_full_size_cfg2_matches_stored_oracle_samples():
+    """The 1M-point order-5 depth-6 compressed workload, as bench.py runs it, against the CPU
+    oracle's potentials at 1024 seeded targets (tests/golden/make_cfg2_samples.py)."""
+    import json
+    import os
+    from workloads import WORKLOADS, make_inputs
+    say("full size cfg2")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cfg2_samples.json")))
+    w = WORKLOADS[2]
+    inp = make_inputs(w)
+    assert gold["targets"] == [int(i) for i in inp.sample_targets]
+    tree = pk.Octree(dev(inp.points), w.depth)
+    plan = pk.Plan(tree, w.kernel, w.order, w.svd_eps, "fp64", w.c)
+    phi = host(plan.apply(dev(inp.q)))[inp.sample_targets, 0]
+    err = rel(phi, np.array(gold["phi_oracle"]))
+    say("  rel err vs oracle", err)
+    assert err < 1e-12
+    assert rel(phi, np.array(gold["phi_direct"])) < 1e-4
+
+
+def test_full_size_cfg3_properties():
+    """4M points, 1/sqrt(r^2+c^2), order 7, depth 7, 4 right-hand sides (the oracle is too slow
+    at this size): the FP64 operator is symmetric, the FP32 and split-FP32 M2L stay within 1e-6 of
+    FP64, and all three match the direct sum at sampled targets to the interpolation error."""
+    from workloads import WORKLOADS, make_inputs
+    say("full size cfg3")
+    w = WORKLOADS[3]
+    inp = make_inputs(w)
+    P = dev(inp.points)
+    tree = pk.Octree(P, w.depth)
+    q = dev(inp.q)
+    g = dev(inp.g)
+    tg = inp.sample_targets[:32]
+    direct = O.brute_force(inp.points, inp.q, w.kernel, w.c, targets=tg)
+    out = {}
+    for prec in ("fp64", "fp32", "split32"):
+        plan = pk.Plan(tree, w.kernel, w.order, 0.0, prec, w.c)
+        out[prec] = host(plan.apply(q))
+        if prec == "fp64":
+            ag = host(plan.apply(g))
+            lhs, rhs = float(np.sum(inp.g * out[prec])), float(np.sum(inp.q * ag))
+            say("  symmetry", lhs, rhs)
+            assert abs(lhs - rhs) < 1e-12 * abs(lhs) * 10
+        del plan
+        torch.cuda.empty_cache()
+        e_direct = rel(out[prec][tg], direct)
+        say("  ", prec, "vs direct", e_direct)
+        assert e_direct < 1e-5
+    for prec in ("fp32", "split32"):
+        e = rel(out[prec], out["fp64"])
+        say("  ", prec, "vs fp64", e)
+        assert e < 1e-6
