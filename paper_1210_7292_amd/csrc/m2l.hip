@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void m2l_full_kernel(M2LArgs a) {
 // that meets the zero row l^3 of V in LDS. The loads therefore need no branches.
 typedef __attribute__((address_space(1))) const double gdouble;
 
-template <int L, int RMAX, int PREC, int W8>
+template <int L, int RMAX, int PREC, int W8, bool ONE_RHS>
 struct Lowrank {
   using A = Arith<PREC>;
   using T = typename A::T;
@@ -265,7 +265,8 @@ struct Lowrank {
       for (int u = 0; u < 4; ++u) {
         int k = 16 * (c0 + c) + 4 * kq + u;
         k = k < NN ? k : NN - 1;
-        w[c][u] = src[(long long)k * nrhs];
+        // one right-hand side: the column is contiguous and k folds into immediate offsets
+        w[c][u] = ONE_RHS ? src[k] : src[(long long)k * nrhs];
       }
   }
 
@@ -317,9 +318,9 @@ struct Lowrank {
   }
 };
 
-template <int L, int RMAX, int PREC, int W8>
+template <int L, int RMAX, int PREC, int W8, bool ONE_RHS>
 __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
-  using K = Lowrank<L, RMAX, PREC, W8>;
+  using K = Lowrank<L, RMAX, PREC, W8, ONE_RHS>;
   using T = typename K::T;
   using V = typename K::V;
   constexpr int NT = 64 * W8;
@@ -449,8 +450,12 @@ hipError_t launch_l(bool lowrank, M2LArgs a, hipStream_t s) {
     if constexpr (L >= 3) {
       tile(a, 16 * kLowrankWaves);
       const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
-      hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves>), dim3(grid),
-                         dim3(64 * kLowrankWaves), 0, s, a);
+      if (a.nrhs == 1)
+        hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, true>), dim3(grid),
+                           dim3(64 * kLowrankWaves), 0, s, a);
+      else
+        hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, false>), dim3(grid),
+                           dim3(64 * kLowrankWaves), 0, s, a);
     } else {
       return hipErrorInvalidValue;
     }
