@@ -90,62 +90,83 @@ __global__ void gather_rows_kernel(const double* __restrict__ in, const int* __r
 }
 
 // ---- P2M: W[leaf][b][r] = sum_{j in leaf} S(y_j, ybar_b) q_j[r] ----------------------------
-constexpr int kP2MThreads = 128;
-constexpr int kP2MBatch = 64;
+// One wave per leaf (four leaves per block). The 1-D basis values of a batch of the leaf's points
+// go to the wave's own LDS slice; only wave-level ordering is needed between writing and reading.
+constexpr int kP2MWaves = 4;
+constexpr int kP2MBatch = 16;
+constexpr int kP2MOut = 8;       // outputs per lane per pass
 
 template <int L>
-__global__ __launch_bounds__(kP2MThreads) void p2m_kernel(PassGeom g, const double* __restrict__ qs,
-                                                          int nrhs, double* __restrict__ W) {
+__global__ __launch_bounds__(64 * kP2MWaves) void p2m_kernel(PassGeom g, const double* __restrict__ qs,
+                                                             int nrhs, double* __restrict__ W) {
   constexpr int NN = L * L * L;
-  __shared__ double sb[kP2MBatch][3][L];
-  __shared__ double sq[kP2MBatch * kMaxRhs];
+  __shared__ double sb[kP2MWaves][kP2MBatch][3][L];
   __shared__ double stk[L * L];
   for (int i = threadIdx.x; i < L * L; i += blockDim.x) stk[i] = g.tk[i];
   __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const unsigned nleaf = 1u << (3 * g.depth);
   const int nout = NN * nrhs;
-  for (unsigned leaf = blockIdx.x; leaf < nleaf; leaf += gridDim.x) {
+  for (unsigned leaf = blockIdx.x * kP2MWaves + wave; leaf < nleaf; leaf += gridDim.x * kP2MWaves) {
     const int s = g.leaf_start[leaf], e = g.leaf_start[leaf + 1];
     double* Wl = W + (long long)leaf * nout;
     if (s == e) {
-      for (int o = threadIdx.x; o < nout; o += blockDim.x) Wl[o] = 0.0;
+      for (int o = lane; o < nout; o += 64) Wl[o] = 0.0;
       continue;
     }
     double c[3], half;
     cell_center(g, g.depth, leaf, c, &half);
     const double inv_half = 1.0 / half;
-    for (int b0 = s; b0 < e; b0 += kP2MBatch) {
-      const int nb = min(kP2MBatch, e - b0);
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < nb * 3; idx += blockDim.x) {
-        const int j = idx / 3, ax = idx % 3;
-        const double x = (ax == 0 ? g.xs : ax == 1 ? g.ys : g.zs)[b0 + j];
-        cheb_basis_all<L>((x - c[ax]) * inv_half, stk, sb[j][ax]);
+    for (int o0 = 0; o0 < nout; o0 += 64 * kP2MOut) {
+      double acc[kP2MOut];
+#pragma unroll
+      for (int u = 0; u < kP2MOut; ++u) acc[u] = 0.0;
+      for (int b0 = s; b0 < e; b0 += kP2MBatch) {
+        const int nb = min(kP2MBatch, e - b0);
+        if (lane < nb * 3) {
+          const int jj = lane / 3, ax = lane % 3;
+          const double x = (ax == 0 ? g.xs : ax == 1 ? g.ys : g.zs)[b0 + jj];
+          cheb_basis_all<L>((x - c[ax]) * inv_half, stk, sb[wave][jj][ax]);
+        }
+        // the wave's LDS writes complete before its lanes read each other's values
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+        for (int u = 0; u < kP2MOut; ++u) {
+          const int o = o0 + lane + 64 * u;
+          if (o < nout) {
+            const int beta = o / nrhs, r = o - beta * nrhs;
+            const int a0 = beta % L, a1 = (beta / L) % L, a2 = beta / (L * L);
+            double t = 0.0;
+            for (int jj = 0; jj < nb; ++jj)
+              t += sb[wave][jj][0][a0] * sb[wave][jj][1][a1] * sb[wave][jj][2][a2] *
+                   qs[(long long)(b0 + jj) * nrhs + r];
+            acc[u] += t;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       }
-      for (int idx = threadIdx.x; idx < nb * nrhs; idx += blockDim.x)
-        sq[idx] = qs[(long long)b0 * nrhs + idx];
-      __syncthreads();
-      for (int o = threadIdx.x; o < nout; o += blockDim.x) {
-        const int beta = o / nrhs, r = o - beta * nrhs;
-        const int a0 = beta % L, a1 = (beta / L) % L, a2 = beta / (L * L);
-        double acc = 0.0;
-        for (int j = 0; j < nb; ++j) acc += sb[j][0][a0] * sb[j][1][a1] * sb[j][2][a2] * sq[j * nrhs + r];
-        if (b0 == s) Wl[o] = acc; else Wl[o] += acc;
+#pragma unroll
+      for (int u = 0; u < kP2MOut; ++u) {
+        const int o = o0 + lane + 64 * u;
+        if (o < nout) Wl[o] = acc[u];
       }
     }
   }
 }
 
 // ---- M2M / L2L: three 1-D contractions per child (separable tensor interpolation) ---------
-constexpr int kM2MThreads = 256;
+constexpr int kM2MThreads = 128;
 constexpr int kM2MBuf = 2048;      // doubles per LDS stage buffer
 
-template <int L>
+template <int L, int RC>
 __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(PassGeom g, int parent_level,
                                                           const double* __restrict__ Wc,
                                                           double* __restrict__ Wp, int nrhs) {
   constexpr int NN = L * L * L;
-  constexpr int RC = (kM2MBuf / NN) > 0 ? (kM2MBuf / NN) : 1;
   constexpr int OUT = (NN * RC + kM2MThreads - 1) / kM2MThreads;
   __shared__ double sM[2 * L * L];
   __shared__ double bufA[NN * RC], bufB[NN * RC], bufC[NN * RC];
@@ -215,12 +236,11 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(PassGeom g, int parent
   }
 }
 
-template <int L>
+template <int L, int RC>
 __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(PassGeom g, int parent_level,
                                                           const double* __restrict__ Fp,
                                                           double* __restrict__ Fc, int nrhs) {
   constexpr int NN = L * L * L;
-  constexpr int RC = (kM2MBuf / NN) > 0 ? (kM2MBuf / NN) : 1;
   __shared__ double sM[2 * L * L];
   __shared__ double bufA[NN * RC], bufB[NN * RC], bufC[NN * RC];
   for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) sM[i] = g.m2m[i];
@@ -472,19 +492,46 @@ hipError_t dispatch_order(int order, Args... args) {
 template <int L> struct P2MRun {
   static hipError_t run(const PassGeom& g, const double* qs, int nrhs, double* W, hipStream_t s) {
     const unsigned nleaf = 1u << (3 * g.depth);
-    hipLaunchKernelGGL(p2m_kernel<L>, dim3(nleaf), dim3(kP2MThreads), 0, s, g, qs, nrhs, W);
+    const unsigned blocks = (nleaf + kP2MWaves - 1) / kP2MWaves;
+    hipLaunchKernelGGL(p2m_kernel<L>, dim3(blocks), dim3(64 * kP2MWaves), 0, s, g, qs, nrhs, W);
     return hipGetLastError();
   }
 };
+// right-hand sides per LDS pass: the smallest power of two covering nrhs, capped by the buffer
+template <int L> constexpr int rc_cap() { return (kM2MBuf / (L * L * L)) >= 16 ? 16 : (kM2MBuf / (L * L * L)) >= 8 ? 8 : (kM2MBuf / (L * L * L)) >= 4 ? 4 : (kM2MBuf / (L * L * L)) >= 2 ? 2 : 1; }
+inline int rc_for(int nrhs, int cap) { int rc = 1; while (rc < nrhs && rc < cap) rc *= 2; return rc; }
+
 template <int L> struct M2MRun {
+  template <int RC>
+  static void go(const PassGeom& g, int pl, const double* Wc, double* Wp, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL((m2m_kernel<L, RC>), dim3(1u << (3 * pl)), dim3(kM2MThreads), 0, s, g, pl, Wc, Wp, nrhs);
+  }
   static hipError_t run(const PassGeom& g, int pl, const double* Wc, double* Wp, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(m2m_kernel<L>, dim3(1u << (3 * pl)), dim3(kM2MThreads), 0, s, g, pl, Wc, Wp, nrhs);
+    constexpr int cap = rc_cap<L>();
+    switch (rc_for(nrhs, cap)) {
+      case 1: go<1>(g, pl, Wc, Wp, nrhs, s); break;
+      case 2: go<(cap >= 2 ? 2 : 1)>(g, pl, Wc, Wp, nrhs, s); break;
+      case 4: go<(cap >= 4 ? 4 : 1)>(g, pl, Wc, Wp, nrhs, s); break;
+      case 8: go<(cap >= 8 ? 8 : 1)>(g, pl, Wc, Wp, nrhs, s); break;
+      default: go<cap>(g, pl, Wc, Wp, nrhs, s); break;
+    }
     return hipGetLastError();
   }
 };
 template <int L> struct L2LRun {
+  template <int RC>
+  static void go(const PassGeom& g, int pl, const double* Fp, double* Fc, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL((l2l_kernel<L, RC>), dim3(1u << (3 * pl)), dim3(kM2MThreads), 0, s, g, pl, Fp, Fc, nrhs);
+  }
   static hipError_t run(const PassGeom& g, int pl, const double* Fp, double* Fc, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(l2l_kernel<L>, dim3(1u << (3 * pl)), dim3(kM2MThreads), 0, s, g, pl, Fp, Fc, nrhs);
+    constexpr int cap = rc_cap<L>();
+    switch (rc_for(nrhs, cap)) {
+      case 1: go<1>(g, pl, Fp, Fc, nrhs, s); break;
+      case 2: go<(cap >= 2 ? 2 : 1)>(g, pl, Fp, Fc, nrhs, s); break;
+      case 4: go<(cap >= 4 ? 4 : 1)>(g, pl, Fp, Fc, nrhs, s); break;
+      case 8: go<(cap >= 8 ? 8 : 1)>(g, pl, Fp, Fc, nrhs, s); break;
+      default: go<cap>(g, pl, Fp, Fc, nrhs, s); break;
+    }
     return hipGetLastError();
   }
 };
