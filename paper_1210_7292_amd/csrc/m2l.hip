@@ -299,22 +299,31 @@ struct Lowrank {
     }
   }
 
+  // GEMM 2 with the operator reads of the next step issued before the current step's MFMAs
   template <int ZB>
   static __device__ inline void gemm2(const T* uhi, const T* ulo, const int (&urow)[MB], int kq, int r,
                                       const V (&z)[2], V (&acc)[MB]) {
+    constexpr int NSTEP = 4 * ZB;
+    T abuf[2][MB];
 #pragma unroll
-    for (int b2 = 0; b2 < ZB; ++b2)
+    for (int mb = 0; mb < MB; ++mb) abuf[0][mb] = uhi[urow[mb] + out_row<PREC>(kq, 0)];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (16 * b2 + (PREC == 0 ? 4 * v : v) >= r) continue;   // uniform: columns beyond the rank
-        const int kcol = 16 * b2 + out_row<PREC>(kq, v);
-        const T bz = z[b2][v];
+    for (int st = 0; st < NSTEP; ++st) {
+      const int b2 = st / 4, v = st % 4;
+      if (16 * b2 + (PREC == 0 ? 4 * v : v) >= r) break;   // uniform: columns beyond the rank
+      if (st + 1 < NSTEP) {
+        const int kn = 16 * ((st + 1) / 4) + out_row<PREC>(kq, (st + 1) % 4);
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          acc[mb] = A::mfma(uhi[urow[mb] + kcol], bz, acc[mb]);
-          if (SPLIT) acc[mb] = A::mfma(ulo[urow[mb] + kcol], bz, acc[mb]);
-        }
+        for (int mb = 0; mb < MB; ++mb) abuf[(st + 1) & 1][mb] = uhi[urow[mb] + kn];
       }
+      const T bz = z[b2][v];
+      const int kcol = 16 * b2 + out_row<PREC>(kq, v);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        acc[mb] = A::mfma(abuf[st & 1][mb], bz, acc[mb]);
+        if (SPLIT) acc[mb] = A::mfma(ulo[urow[mb] + kcol], bz, acc[mb]);
+      }
+    }
   }
 };
 
