@@ -7,7 +7,8 @@
  *     phi_i = sum_{j != i} K(x_i, x_j) q_j          (Sec. 2, Eq. direct; sources = targets)
  *
  * with P2M/M2M (Eq. m2m_bbfmm), M2L (Eq. m2l_bbfmm) and L2L/L2P (Eq. l2l_bbfmm) on a uniform
- * octree, plus a direct near field over the 27 neighbour leaves (Sec. 3.2). The M2L uses only
+ * octree, plus a direct near field over the 27 neighbour leaves (Sec. 3.2), or on an adaptive
+ * octree with the four interaction lists described at bbfmm_build_octree. The M2L uses only
  * the 16 operators of the cone t1 >= t2 >= t3 >= 0 (Eqs. z_sym, reduced_interaction_list), the
  * other 300 being row/column permutations of them (Eqs. axial_permutation,
  * diagonal_permutation, permutations), applied in blocks as dense matrix products (Sec. 4.2.3,
@@ -69,8 +70,10 @@ typedef enum {
 } bbfmm_m2l_prec;
 
 typedef struct {
-  int32_t depth;            /* leaf level of the uniform octree, 0..8 (level l has 8^l cells) */
-  int32_t max_leaf_points;  /* reserved (adaptive trees); must be 0 */
+  int32_t depth;            /* leaf level of the uniform octree, 0..8 (level l has 8^l cells);
+                               -1: adaptive octree */
+  int32_t max_leaf_points;  /* adaptive: cells holding more points are split (>= 1);
+                               uniform: must be 0 */
   double root_lo[3];        /* lower corner of the root cube (used when root_width > 0) */
   double root_width;        /* > 0: root cube [lo, lo + width)^3, every point must lie in it;
                                <= 0: tight bounding cube of the points, enlarged by 1e-12
@@ -89,11 +92,12 @@ typedef struct {
 
 typedef struct {
   int64_t n_points;
-  int32_t depth, order, n_levels_m2l;   /* M2L runs on levels 2..depth */
+  int32_t depth, order, n_levels_m2l;   /* M2L runs on levels 2..depth (adaptive: deepest level) */
   int32_t n_operator_sets;              /* 1 for homogeneous kernels, depth-1 otherwise */
   int32_t rank[16];                     /* rank of each unique operator (order^3 if full) */
   double root_lo[3], root_width;
-  int64_t pairs_total;                  /* far pairs of all M2L levels with both cells in the box */
+  int64_t pairs_total;                  /* far pairs of all M2L levels with both cells in the box
+                                           (adaptive: the V-list pairs) */
   int64_t pairs_nonempty;               /* ... of which both cells hold points (plan_stats only) */
   double m2l_flops_algorithmic;         /* per right-hand side: sum over non-empty pairs of
                                            2 l^6 (full) or 4 l^3 r_p (compressed) */
@@ -105,12 +109,28 @@ typedef struct {
 typedef struct bbfmm_tree bbfmm_tree;
 typedef struct bbfmm_plan bbfmm_plan;
 
-/* Builds the uniform octree of Sec. 3 (Alg. SeparateNearAndFarField, smooth branch): each point
- * goes to leaf floor((x - lo) / w_leaf) per axis, clamped into the root; points are counting-
- * sorted into Morton leaf order (ties kept in input order) and leaf offsets are stored.
+/* Builds the octree.
+ * Uniform (depth >= 0) — Sec. 3, Alg. SeparateNearAndFarField, smooth branch: each point goes to
+ * leaf floor((x - lo) / w_leaf) per axis, clamped into the root; points are counting-sorted into
+ * Morton leaf order (ties kept in input order) and leaf offsets are stored.
+ * Adaptive (depth = -1) — an extension beyond the paper, whose separation assumes source and
+ * target cells are subdivided together: points get 63-bit Morton keys (21 levels, cell
+ * coordinates floor(2^21 (x - lo) / width) clamped) and are stably sorted by key; from the root
+ * down, a cell holding more than max_leaf_points points is split into its non-empty children
+ * (never below level 21). Interaction lists (closed boxes that intersect "touch"):
+ *   U(B), leaf B: leaves touching B, B included              -> direct near field
+ *   V(X), any X:  children of the neighbours of X's parent that do not touch X
+ *                 (the 189 transfer vectors of X's octant)   -> M2L, as for the uniform tree
+ *   W(B), leaf B: cells below B's same-level non-leaf neighbours that do not touch B while
+ *                 their parent does                          -> multipole evaluated at B's points
+ *   X(C):         the leaves B with C in W(B)                -> B's points into C's local
+ * The list topology is built on the host from the device-sorted cells (one synchronisation per
+ * level) and uploaded. Adaptive trees support bbfmm_apply and bbfmm_apply_adjoint; gradients
+ * and the uniform-only inspection calls return EUNSUPPORTED.
  * d_points: n x 3 row-major FP64 device array (copied; may be freed after the call).
- * Errors: EINVAL for n < 1, null pointers, depth outside [0, 8], max_leaf_points != 0, a
- * non-finite coordinate, or (root_width > 0) a point outside the root cube. */
+ * Errors: EINVAL for n < 1, null pointers, depth outside [-1, 8], max_leaf_points < 1 with
+ * depth = -1 or != 0 otherwise, a non-finite coordinate, or (root_width > 0) a point outside the
+ * root cube. */
 bbfmm_status bbfmm_build_octree(const double* d_points, int64_t n, const bbfmm_tree_opts* opts,
                                 void* stream, bbfmm_tree** out);
 
@@ -188,6 +208,39 @@ bbfmm_status bbfmm_debug_m2l_level(bbfmm_plan* plan, int32_t level, const double
  * order (n int32), and d_leaf_start (8^depth + 1 int32 offsets into that order). */
 bbfmm_status bbfmm_debug_tree_order(const bbfmm_tree* tree, int32_t* d_perm, int32_t* d_leaf_start,
                                     void* stream);
+
+/* Adaptive-tree inspection. Counts of the tree's arrays: */
+typedef struct {
+  int32_t n_levels;          /* levels 0 .. n_levels - 1 hold cells */
+  int32_t n_nodes, n_leaves;
+  int64_t n_u, n_w, n_x_nodes, n_x, n_m2l_targets;   /* list lengths (see arrays below) */
+  int64_t v_pairs;           /* (target, source) pairs of the V lists */
+  int64_t u_point_pairs;     /* (target point, source point) pairs of the U lists, i = j included */
+  int64_t w_pairs;           /* (leaf, cell) pairs of the W lists */
+} bbfmm_adaptive_info;
+
+/* Fills `out` for an adaptive tree. Errors: EINVAL (null, uniform tree). */
+bbfmm_status bbfmm_adaptive_info_of(const bbfmm_tree* tree, bbfmm_adaptive_info* out);
+
+/* Copies one array of an adaptive tree into host memory `out` (int64 elements). Nodes are
+ * numbered level by level, Morton order inside a level; `which`:
+ *   0 level offsets (n_levels + 1)       1 node key at its own level (n_nodes)
+ *   2 node level                          3 node start, 4 node end (range in sorted point order)
+ *   5 node is a leaf (0/1)                6 first child, 7 end of children (node ids)
+ *   8 leaves (node ids, n_leaves)         9 U offsets (n_leaves + 1), 10 U nodes (n_u)
+ *  11 W offsets (n_leaves + 1), 12 W nodes (n_w)
+ *  13 X-list nodes (n_x_nodes), 14 X offsets (n_x_nodes + 1), 15 X leaves (n_x)
+ *  16 M2L targets (n_m2l_targets, grouped by level and octant), 17 their group offsets
+ *     (8 n_levels + 1), 18 sources per target and table entry (n_m2l_targets x 189, -1 absent)
+ *  19 permutation: input index of each sorted point (n_points)
+ * Errors: EINVAL (null, uniform tree, unknown `which`). */
+bbfmm_status bbfmm_adaptive_array(const bbfmm_tree* tree, int32_t which, int64_t* out);
+
+/* Host-only: the adaptive tree of host points built by a plain CPU path (keys, std::stable_sort,
+ * level-by-level split), for comparison with the device build through the two calls above. The
+ * result cannot be used by bbfmm_precompute_m2l (ESTATE). Root options as bbfmm_build_octree. */
+bbfmm_status bbfmm_host_adaptive_tree(const double* points, int64_t n, int32_t max_leaf_points,
+                                      const double root_lo[3], double root_width, bbfmm_tree** out);
 
 /* Host-only helpers (no GPU needed): the 16 representative transfer vectors in the library's
  * order (out_t: 16 x 3), and for transfer vector t (|t_i| <= 3, max |t_i| >= 2) the index of

@@ -163,8 +163,10 @@ def lists(tree: AdaptiveTree):
 
 
 def fmm_apply(points, q, order, max_pts, kind="inv_r", c=0.0, max_depth=MAX_DEPTH, lo=None, width=None,
-              tree: Optional[AdaptiveTree] = None):
-    """phi of the adaptive bbFMM (full-rank operators formed directly per transfer vector)."""
+              tree: Optional[AdaptiveTree] = None, eps: float = 0.0):
+    """phi of the adaptive bbFMM with operators formed directly per transfer vector and cell width:
+    full rank for eps <= 0, else K_t ~ U_t V_t^T by truncated SVD applied as U_t (V_t^T w)
+    (Eq. ialowrank)."""
     points = np.ascontiguousarray(points, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
     if q.ndim == 1:
@@ -196,12 +198,22 @@ def fmm_apply(points, q, order, max_pts, kind="inv_r", c=0.0, max_depth=MAX_DEPT
                 octant = tuple(tree.cells[ch].ijk[r] - 2 * cc.ijk[r] for r in range(3))
                 mult[k] += O.child_to_parent_matrix(octant, order).T @ mult[ch]
     # M2L over V (levels >= 2 hold all V pairs; shallower V lists are empty or handled the same)
+    ops = {}
+
+    def m2l_apply(t, w, x):
+        key = (tuple(int(v) for v in t), w)
+        if key not in ops:
+            kt = O.m2l_operator(np.asarray(key[0]), w, order, kind, c)
+            ops[key] = O.compress(kt, eps)[:2] if eps > 0 else kt
+        op = ops[key]
+        return op[0] @ (op[1].T @ x) if eps > 0 else op @ x
+
     for k, vl in V.items():
         cc = tree.cells[k]
         w = tree.cell_width(cc)
         for y in vl:
             t = np.asarray(cc.ijk) - np.asarray(tree.cells[y].ijk)
-            loc[k] += O.m2l_operator(t, w, order, kind, c) @ mult[y]
+            loc[k] += m2l_apply(t, w, mult[y])
     # P2L over X
     for k, xl in X.items():
         xs = nodes(k)

@@ -41,6 +41,18 @@ class Stats(C.Structure):
                 ("precompute_seconds", C.c_double), ("device_bytes", C.c_int64)]
 
 
+class AdaptiveInfo(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_nodes", C.c_int32), ("n_leaves", C.c_int32),
+                ("n_u", C.c_int64), ("n_w", C.c_int64), ("n_x_nodes", C.c_int64), ("n_x", C.c_int64),
+                ("n_m2l_targets", C.c_int64), ("v_pairs", C.c_int64), ("u_point_pairs", C.c_int64),
+                ("w_pairs", C.c_int64)]
+
+
+# array ids of bbfmm_adaptive_array
+ADAPTIVE_ARRAYS = ("level_off", "key", "level", "start", "end", "leaf", "child_begin", "child_end",
+                   "leaves", "u_off", "u_idx", "w_off", "w_idx", "x_node", "x_off", "x_idx",
+                   "m2l_tgt", "m2l_off", "vsrc", "perm")
+
 _lib = None
 
 # (name, restype, argtypes) of every exported symbol declared in include/bbfmm.h
@@ -65,6 +77,9 @@ SIGNATURES = [
     ("bbfmm_host_operator", C.c_int, [C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_int32,
                                       C.c_double, _P, _P, _P, _P]),
     ("bbfmm_host_singular_values", C.c_int, [_P, C.c_int32, C.c_int32, _P]),
+    ("bbfmm_adaptive_info_of", C.c_int, [_P, C.POINTER(AdaptiveInfo)]),
+    ("bbfmm_adaptive_array", C.c_int, [_P, C.c_int32, _P]),
+    ("bbfmm_host_adaptive_tree", C.c_int, [_P, C.c_int64, C.c_int32, _P, C.c_double, C.POINTER(_P)]),
 ]
 
 
@@ -108,11 +123,14 @@ def _dev_ptr(t, dtype, shape_last=None, name="tensor"):
 # ---------------------------------------------------------------------------- C-ABI names
 
 
-def build_octree(points, depth: int, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0):
-    """bbfmm_build_octree on an (n, 3) float64 device tensor; returns an opaque tree handle."""
+def build_octree(points, depth: int, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0,
+                 max_leaf_points: int = 0):
+    """bbfmm_build_octree on an (n, 3) float64 device tensor; returns an opaque tree handle.
+    depth = -1 with max_leaf_points >= 1 builds an adaptive tree."""
     import torch
     p = _dev_ptr(points, torch.float64, 3, "points")
-    o = TreeOpts(int(depth), 0, (C.c_double * 3)(*[float(v) for v in root_lo]), float(root_width))
+    o = TreeOpts(int(depth), int(max_leaf_points), (C.c_double * 3)(*[float(v) for v in root_lo]),
+                 float(root_width))
     out = C.c_void_p()
     _check(lib().bbfmm_build_octree(p, points.shape[0], C.byref(o), _P(_stream(torch, points.device)),
                                     C.byref(out)))
@@ -198,23 +216,78 @@ def host_singular_values(a: np.ndarray) -> np.ndarray:
     return s
 
 
+def adaptive_info(tree) -> dict:
+    s = AdaptiveInfo()
+    _check(lib().bbfmm_adaptive_info_of(tree, C.byref(s)))
+    return {k: getattr(s, k) for k, _ in AdaptiveInfo._fields_}
+
+
+def adaptive_arrays(tree, n_points: int) -> dict:
+    """Every array of an adaptive tree (bbfmm_adaptive_array), as int64 numpy arrays."""
+    info = adaptive_info(tree)
+    sizes = {"level_off": info["n_levels"] + 1, "key": info["n_nodes"], "level": info["n_nodes"],
+             "start": info["n_nodes"], "end": info["n_nodes"], "leaf": info["n_nodes"],
+             "child_begin": info["n_nodes"], "child_end": info["n_nodes"], "leaves": info["n_leaves"],
+             "u_off": info["n_leaves"] + 1, "u_idx": info["n_u"], "w_off": info["n_leaves"] + 1,
+             "w_idx": info["n_w"], "x_node": info["n_x_nodes"], "x_off": info["n_x_nodes"] + 1,
+             "x_idx": info["n_x"], "m2l_tgt": info["n_m2l_targets"], "m2l_off": 8 * info["n_levels"] + 1,
+             "vsrc": info["n_m2l_targets"] * 189, "perm": n_points}
+    out = {}
+    for which, name in enumerate(ADAPTIVE_ARRAYS):
+        a = np.zeros(max(1, sizes[name]), dtype=np.int64)
+        _check(lib().bbfmm_adaptive_array(tree, which, a.ctypes.data_as(_P)))
+        out[name] = a[:sizes[name]]
+    out["info"] = info
+    return out
+
+
+class HostAdaptiveTree:
+    """bbfmm_host_adaptive_tree: the adaptive tree of host points built on the CPU."""
+
+    def __init__(self, points: np.ndarray, max_leaf_points: int, root_lo=None, root_width: float = 0.0):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        self.n = pts.shape[0]
+        lo = (C.c_double * 3)(*([0.0, 0.0, 0.0] if root_lo is None else [float(v) for v in root_lo]))
+        h = C.c_void_p()
+        _check(lib().bbfmm_host_adaptive_tree(pts.ctypes.data_as(_P), self.n, int(max_leaf_points), lo,
+                                              float(root_width), C.byref(h)))
+        self.handle = h
+
+    def arrays(self) -> dict:
+        return adaptive_arrays(self.handle, self.n)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.bbfmm_tree_destroy(h)
+            self.handle = None
+
+
 # ---------------------------------------------------------------------------- objects
 
 
 class Octree:
-    """Owns a bbfmm_tree built from an (n, 3) float64 device tensor."""
+    """Owns a bbfmm_tree built from an (n, 3) float64 device tensor: uniform of leaf level `depth`,
+    or adaptive (depth=-1) with at most `max_leaf_points` points per leaf."""
 
-    def __init__(self, points, depth: int, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0):
+    def __init__(self, points, depth: int, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0,
+                 max_leaf_points: int = 0):
         self.n = points.shape[0]
         self.depth = depth
+        self.adaptive = depth == -1
         self.device = points.device
-        self.handle = build_octree(points, depth, root_lo, root_width)
+        self.handle = build_octree(points, depth, root_lo, root_width, max_leaf_points)
+
+    def arrays(self) -> dict:
+        """Adaptive trees: the node arrays and interaction lists (see adaptive_arrays)."""
+        return adaptive_arrays(self.handle, self.n)
 
     def order(self):
         """(perm, leaf_start): caller index of each sorted point and the leaf offsets."""
         import torch
         perm = torch.empty(self.n, dtype=torch.int32, device=self.device)
-        ls = torch.empty(8 ** self.depth + 1, dtype=torch.int32, device=self.device)
+        # adaptive trees have no leaf offset table: the library rejects the call
+        ls = torch.empty(1 if self.adaptive else 8 ** self.depth + 1, dtype=torch.int32, device=self.device)
         _check(lib().bbfmm_debug_tree_order(self.handle, _P(perm.data_ptr()), _P(ls.data_ptr()),
                                             _P(_stream(torch, self.device))))
         return perm, ls
@@ -282,9 +355,10 @@ class Plan:
 
 
 def fmm_apply(points, q, depth: int, order: int, kernel: str = "inv_r", svd_eps: float = 0.0,
-              m2l_prec: str = "fp64", c: float = 0.0, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0):
+              m2l_prec: str = "fp64", c: float = 0.0, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0,
+              max_leaf_points: int = 0):
     """One-shot build_octree + precompute_m2l + apply."""
-    tree = Octree(points, depth, root_lo, root_width)
+    tree = Octree(points, depth, root_lo, root_width, max_leaf_points)
     plan = Plan(tree, kernel, order, svd_eps, m2l_prec, c)
     if q.dim() == 1:
         return plan.apply(q.reshape(-1, 1).contiguous()).reshape(-1)

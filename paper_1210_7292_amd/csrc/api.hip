@@ -7,6 +7,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -115,6 +116,71 @@ M2LArgs m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double* F, int 
   return a;
 }
 
+AdaptiveGeom ageom_of(const bbfmm_plan* pl) {
+  const bbfmm_tree* t = pl->tree;
+  AdaptiveGeom g;
+  g.xs = t->xs; g.ys = t->ys; g.zs = t->zs;
+  g.perm = t->perm; g.leaf_of = t->leaf_of;
+  g.n = t->n;
+  g.start = t->d_start; g.end = t->d_end; g.cen = t->d_cen;
+  g.child_begin = t->d_child_begin; g.child_end = t->d_child_end; g.oct = t->d_oct;
+  g.tk = pl->d_tk; g.m2m = pl->d_m2m;
+  g.order = pl->order; g.kernel = pl->kernel; g.c = pl->c;
+  return g;
+}
+
+void free_tree_arrays(bbfmm_tree* t) {
+  dfree(t->xs); dfree(t->ys); dfree(t->zs); dfree(t->perm); dfree(t->leaf_of); dfree(t->leaf_start);
+  dfree(t->d_start); dfree(t->d_end); dfree(t->d_cen); dfree(t->d_child_begin); dfree(t->d_child_end);
+  dfree(t->d_oct); dfree(t->d_leaves); dfree(t->d_leaf_pos); dfree(t->d_u_off); dfree(t->d_u_idx);
+  dfree(t->d_w_off); dfree(t->d_w_idx); dfree(t->d_x_node); dfree(t->d_x_off); dfree(t->d_x_idx);
+  dfree(t->d_m2l_tgt); dfree(t->d_vsrc);
+  t->xs = t->ys = t->zs = nullptr;
+  t->perm = t->leaf_of = t->leaf_start = nullptr;
+}
+
+// Tiles the adaptive M2L segments for `nrhs` and uploads them (waits for the stream first: an
+// M2L still running may read the previous tiling).
+bbfmm_status adaptive_segments(bbfmm_plan* p, int nrhs, hipStream_t s) {
+  if (p->segs_nrhs == nrhs || p->h_segs.empty()) return BBFMM_OK;
+  BBFMM_HIP_TRY(hipStreamSynchronize(s));
+  const int cols = m2l_block_cols(p->lowrank);
+  long long blocks = 0;
+  for (M2LLevel& sg : p->h_segs) {
+    const long long c = (long long)sg.npar * nrhs;
+    sg.ntiles = (int)((c + cols - 1) / cols);
+    sg.block_begin = (int)blocks;
+    blocks += sg.ntiles;
+  }
+  if (blocks > 0x7fffff00LL) return fail(BBFMM_EUNSUPPORTED, "too many M2L blocks");
+  BBFMM_HIP_TRY(hipMemcpy(p->d_segs, p->h_segs.data(), p->h_segs.size() * sizeof(M2LLevel),
+                          hipMemcpyHostToDevice));
+  p->seg_blocks = (int)blocks;
+  p->segs_nrhs = nrhs;
+  return BBFMM_OK;
+}
+
+M2LArgs adaptive_m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double* F) {
+  const bbfmm_tree* t = p->tree;
+  M2LArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nrhs = nrhs;
+  a.lv[0].W = W;
+  a.lv[0].F = F;
+  a.nlev = 0;
+  a.nblocks = p->seg_blocks;
+  a.cols = m2l_block_cols(p->lowrank);
+  a.ops_hi = p->ops_hi; a.ops_lo = p->ops_lo;
+  a.op_off = p->d_op_off; a.op_rank = p->d_op_rank;
+  a.tab = p->d_tab; a.grp = p->d_grp; a.sig = p->d_sig; a.siginv = p->d_siginv;
+  a.zeros = p->d_zeros;
+  a.segs = p->d_segs;
+  a.nsegs = (int)p->h_segs.size();
+  a.tgt = t->d_m2l_tgt;
+  a.vsrc = t->d_vsrc;
+  return a;
+}
+
 enum Pass { kPassStart = -1, kGather = 0, kP2M, kM2M, kM2L, kL2L, kL2P, kP2P, kNumPasses };
 
 // Records an event tagged with the pass that just ended (tracing only).
@@ -131,6 +197,50 @@ hipError_t mark(bbfmm_plan* p, int tag, hipStream_t s) {
   return hipEventRecord(p->ev_pool[p->ev_used++], s);
 }
 
+// The chain on an adaptive tree: P2M at the leaves, M2M up to level 2, M2L over the V lists,
+// P2L over the X lists, L2L down, L2P and M2P over the W lists at the leaves, and the near field
+// over the U lists. P2L is timed with L2L and M2P with L2P.
+bbfmm_status run_chain_adaptive(bbfmm_plan* p, const double* in, int nrhs, double* out, int slot,
+                                hipStream_t s) {
+  const bbfmm_tree* t = p->tree;
+  const AdaptiveTopology& T = t->topo;
+  const AdaptiveGeom g = ageom_of(p);
+  double* qs = p->qs[slot];
+  BBFMM_HIP_TRY(mark(p, kPassStart, s));
+  BBFMM_HIP_TRY(launch_gather_rows(in, t->perm, t->n, nrhs, qs, s));
+  BBFMM_HIP_TRY(mark(p, kGather, s));
+  const double* far = nullptr;
+  const int nleaves = (int)T.leaves.size();
+  if (t->depth >= 2) {
+    bbfmm_status st = adaptive_segments(p, nrhs, s);
+    if (st != BBFMM_OK) return st;
+    double* W = p->W;
+    double* F = p->F[slot];
+    BBFMM_HIP_TRY(launch_ad_p2m(g, t->d_leaves, nleaves, qs, nrhs, W, s));
+    BBFMM_HIP_TRY(mark(p, kP2M, s));
+    for (int l = t->depth - 1; l >= 2; --l)
+      BBFMM_HIP_TRY(launch_ad_m2m(g, T.level_off[l], T.level_off[l + 1], W, nrhs, s));
+    BBFMM_HIP_TRY(mark(p, kM2M, s));
+    BBFMM_HIP_TRY(launch_fill_zero(F, p->exp_elems * nrhs, s));
+    const M2LArgs a = adaptive_m2l_args(p, nrhs, W, F);
+    BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, s));
+    BBFMM_HIP_TRY(mark(p, kM2L, s));
+    BBFMM_HIP_TRY(launch_ad_p2l(g, t->d_x_node, t->d_x_off, t->d_x_idx, (int)T.x_node.size(), qs, nrhs, F, s));
+    for (int l = 2; l < t->depth; ++l)
+      BBFMM_HIP_TRY(launch_ad_l2l(g, T.level_off[l], T.level_off[l + 1], F, nrhs, s));
+    BBFMM_HIP_TRY(mark(p, kL2L, s));
+    BBFMM_HIP_TRY(launch_ad_l2p(g, F, nrhs, p->phis, s));
+    if (!T.w_idx.empty())
+      BBFMM_HIP_TRY(launch_ad_m2p(g, t->d_leaves, t->d_w_off, t->d_w_idx, nleaves, W, nrhs, p->phis, s));
+    BBFMM_HIP_TRY(mark(p, kL2P, s));
+    far = p->phis;
+  }
+  BBFMM_HIP_TRY(launch_ad_p2p_scatter(g, t->d_leaf_pos, t->d_u_off, t->d_u_idx, qs, far, nrhs, out, s));
+  BBFMM_HIP_TRY(mark(p, kP2P, s));
+  p->slot_nrhs[slot] = nrhs;
+  return BBFMM_OK;
+}
+
 // One forward pass of the chain on `in` (caller order) into `out` (caller order); slot 0 keeps
 // the locals of an apply, slot 1 those of an adjoint apply.
 bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, int slot,
@@ -138,6 +248,7 @@ bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, i
   bbfmm_status st = ensure_buffers(p, nrhs, slot);
   if (st != BBFMM_OK) return st;
   const bbfmm_tree* t = p->tree;
+  if (t->adaptive) return run_chain_adaptive(p, in, nrhs, out, slot, s);
   const PassGeom g = geom_of(p);
   double* qs = p->qs[slot];
   BBFMM_HIP_TRY(mark(p, kPassStart, s));
@@ -176,6 +287,161 @@ std::vector<int> octant_tables(std::vector<int>* grp) {
   return tab;
 }
 
+// Root cube from the points' bounding box: the given cube (every point inside) or the tight
+// bounding cube enlarged by 1e-12 relative, centred on the box.
+bbfmm_status root_of(const double bblo[3], const double bbhi[3], const double root_lo[3], double root_width,
+                     bbfmm_tree* t) {
+  if (root_width > 0) {
+    for (int r = 0; r < 3; ++r) {
+      t->lo[r] = root_lo[r];
+      if (bblo[r] < root_lo[r] || bbhi[r] > root_lo[r] + root_width)
+        return fail(BBFMM_EINVAL, "a point lies outside the root cube");
+    }
+    t->width = root_width;
+  } else {
+    double ext = 0.0;
+    for (int r = 0; r < 3; ++r) ext = std::max(ext, bbhi[r] - bblo[r]);
+    if (!(ext > 0.0)) ext = 1.0;
+    const double w = ext * (1.0 + 1e-12);
+    for (int r = 0; r < 3; ++r) t->lo[r] = bblo[r] - 0.5 * (w - (bbhi[r] - bblo[r]));
+    t->width = w;
+  }
+  return BBFMM_OK;
+}
+
+// Uploads the host topology of an adaptive tree.
+hipError_t upload_topology(bbfmm_tree* t, long long* bytes) {
+  const AdaptiveTopology& T = t->topo;
+  const int nn = T.level_off.empty() ? 0 : T.level_off.back();
+  std::vector<double> cen(4 * (size_t)nn);
+  std::vector<unsigned char> oct(nn);
+  for (int g = 0; g < nn; ++g) {
+    for (int r = 0; r < 3; ++r) cen[4 * (size_t)g + r] = T.center[3 * (size_t)g + r];
+    cen[4 * (size_t)g + 3] = T.half[g];
+    oct[g] = (unsigned char)(T.key[g] & 7);
+  }
+  auto up = [&](auto** dst, const auto& v) -> hipError_t {
+    using E = typename std::remove_reference<decltype(v)>::type::value_type;
+    hipError_t e = dmalloc(dst, v.size(), bytes);
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpy(*dst, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice);
+  };
+  hipError_t e = up(&t->d_start, T.start);
+  if (e == hipSuccess) e = up(&t->d_end, T.end);
+  if (e == hipSuccess) e = up(&t->d_cen, cen);
+  if (e == hipSuccess) e = up(&t->d_child_begin, T.child_begin);
+  if (e == hipSuccess) e = up(&t->d_child_end, T.child_end);
+  if (e == hipSuccess) e = up(&t->d_oct, oct);
+  if (e == hipSuccess) e = up(&t->d_leaves, T.leaves);
+  if (e == hipSuccess) e = up(&t->d_leaf_pos, T.leaf_pos);
+  if (e == hipSuccess) e = up(&t->d_u_off, T.u_off);
+  if (e == hipSuccess) e = up(&t->d_u_idx, T.u_idx);
+  if (e == hipSuccess) e = up(&t->d_w_off, T.w_off);
+  if (e == hipSuccess) e = up(&t->d_w_idx, T.w_idx);
+  if (e == hipSuccess) e = up(&t->d_x_node, T.x_node);
+  if (e == hipSuccess) e = up(&t->d_x_off, T.x_off);
+  if (e == hipSuccess) e = up(&t->d_x_idx, T.x_idx);
+  if (e == hipSuccess) e = up(&t->d_m2l_tgt, T.m2l_tgt);
+  if (e == hipSuccess) e = up(&t->d_vsrc, T.vsrc);
+  return e;
+}
+
+// Device build of an adaptive tree: keys, stable radix sort, sorted coordinates, then one
+// segmentation step per level (cells of the level among the points still to be split), whose
+// cells are copied to the host for the topology and lists.
+bbfmm_status build_adaptive(std::unique_ptr<bbfmm_tree>& t, const double* d_points, long long n, int max_pts,
+                            hipStream_t s, bbfmm_tree** out) {
+  t->adaptive = true;
+  t->max_leaf_points = max_pts;
+  long long bytes = 0;
+  unsigned long long *keys = nullptr, *ktmp = nullptr, *nkey = nullptr;
+  int *vtmp = nullptr, *sflag = nullptr, *eflag = nullptr, *sidx = nullptr, *eidx = nullptr;
+  int *nstart = nullptr, *nend = nullptr;
+  unsigned char* active = nullptr;
+  auto cleanup = [&]() {
+    dfree(keys); dfree(ktmp); dfree(nkey); dfree(vtmp); dfree(sflag); dfree(eflag); dfree(sidx);
+    dfree(eidx); dfree(nstart); dfree(nend); dfree(active);
+  };
+  auto bad = [&](hipError_t err, const char* what) {
+    cleanup();
+    free_tree_arrays(t.get());
+    return fail(err == hipErrorOutOfMemory ? BBFMM_ENOMEM : BBFMM_EHIP,
+                std::string(what) + ": " + hipGetErrorString(err));
+  };
+  hipError_t e = hipSuccess;
+  if ((e = dmalloc(&t->xs, n, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&t->ys, n, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&t->zs, n, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&t->perm, n, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&t->leaf_of, n, &bytes)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&keys, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&ktmp, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&nkey, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&vtmp, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&sflag, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&eflag, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&sidx, n + 1, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&eidx, n + 1, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&nstart, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&nend, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = dmalloc(&active, n, nullptr)) != hipSuccess) return bad(e, "alloc");
+  if ((e = launch_keys64(d_points, n, t->lo, t->width, keys, t->perm, s)) != hipSuccess) return bad(e, "keys");
+  if ((e = radix_sort64(keys, t->perm, ktmp, vtmp, n, 3 * kAdaptiveDepth, s)) != hipSuccess)
+    return bad(e, "sort");
+  if ((e = launch_sorted_soa(d_points, t->perm, n, t->xs, t->ys, t->zs, s)) != hipSuccess)
+    return bad(e, "sorted coordinates");
+  if ((e = hipMemsetAsync(active, 1, n, s)) != hipSuccess) return bad(e, "memset");
+  std::vector<std::vector<unsigned long long>> hkeys;
+  std::vector<std::vector<int>> hstart, hend;
+  int node_base = 0;
+  for (int l = 0; l <= kAdaptiveDepth; ++l) {
+    if ((e = launch_seg_flags(keys, n, l, active, sflag, eflag, s)) != hipSuccess) return bad(e, "segment");
+    if ((e = exclusive_scan(sflag, sidx, n, s)) != hipSuccess) return bad(e, "scan");
+    if ((e = exclusive_scan(eflag, eidx, n, s)) != hipSuccess) return bad(e, "scan");
+    int cnt = 0;
+    if ((e = hipMemcpyAsync(&cnt, sidx + n, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return bad(e, "count");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "count");
+    if (cnt == 0) break;
+    if ((long long)node_base + cnt > 0x7fffffffLL) {
+      cleanup();
+      free_tree_arrays(t.get());
+      return fail(BBFMM_EUNSUPPORTED, "too many tree cells");
+    }
+    if ((e = launch_seg_compact(keys, n, l, sflag, sidx, eflag, eidx, nkey, nstart, nend, s)) != hipSuccess)
+      return bad(e, "segment");
+    hkeys.emplace_back(cnt);
+    hstart.emplace_back(cnt);
+    hend.emplace_back(cnt);
+    if ((e = hipMemcpyAsync(hkeys.back().data(), nkey, cnt * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess)
+      return bad(e, "copy");
+    if ((e = hipMemcpyAsync(hstart.back().data(), nstart, cnt * sizeof(int), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return bad(e, "copy");
+    if ((e = hipMemcpyAsync(hend.back().data(), nend, cnt * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return bad(e, "copy");
+    if ((e = launch_seg_next(n, l, max_pts, node_base, sidx, sflag, nstart, nend, active, t->leaf_of, s)) !=
+        hipSuccess)
+      return bad(e, "segment");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "segment");
+    node_base += cnt;
+  }
+  cleanup();
+  std::vector<int> grp;
+  const std::vector<int> tab = octant_tables(&grp);
+  build_adaptive_topology(t->topo, hkeys, hstart, hend, max_pts, t->lo, t->width, tab.data());
+  t->depth = t->topo.nlevels - 1;
+  if ((e = upload_topology(t.get(), &bytes)) != hipSuccess) {
+    free_tree_arrays(t.get());
+    return fail(e == hipErrorOutOfMemory ? BBFMM_ENOMEM : BBFMM_EHIP,
+                std::string("topology upload: ") + hipGetErrorString(e));
+  }
+  t->bytes = bytes;
+  *out = t.release();
+  return BBFMM_OK;
+}
+
 }  // namespace
 }  // namespace bbfmm
 
@@ -192,9 +458,13 @@ bbfmm_status bbfmm_build_octree(const double* d_points, int64_t n, const bbfmm_t
   *out = nullptr;
   if (!d_points || !opts) return fail(BBFMM_EINVAL, "null points or options");
   if (n < 1 || n > 0x7fffffffLL) return fail(BBFMM_EINVAL, "n must be in [1, 2^31 - 1]");
-  if (opts->depth < 0 || opts->depth > kMaxDepth)
-    return fail(BBFMM_EINVAL, "depth must be in [0, 8] (adaptive trees are not supported)");
-  if (opts->max_leaf_points != 0) return fail(BBFMM_EINVAL, "max_leaf_points must be 0");
+  const bool adaptive = opts->depth == -1;
+  if (opts->depth < -1 || opts->depth > kMaxDepth)
+    return fail(BBFMM_EINVAL, "depth must be in [0, 8], or -1 for an adaptive tree");
+  if (adaptive && opts->max_leaf_points < 1)
+    return fail(BBFMM_EINVAL, "max_leaf_points must be >= 1 for an adaptive tree");
+  if (!adaptive && opts->max_leaf_points != 0)
+    return fail(BBFMM_EINVAL, "max_leaf_points must be 0 for a uniform tree");
   if (opts->root_width > 0) {
     for (int r = 0; r < 3; ++r)
       if (!std::isfinite(opts->root_lo[r])) return fail(BBFMM_EINVAL, "root_lo is not finite");
@@ -217,21 +487,11 @@ bbfmm_status bbfmm_build_octree(const double* d_points, int64_t n, const bbfmm_t
   (void)hipFree(d_bb);
   if (e != hipSuccess) return fail(BBFMM_EHIP, std::string("bounding box: ") + hipGetErrorString(e));
   if (bb.nonfinite > 0) return fail(BBFMM_EINVAL, "points contain non-finite coordinates");
-  if (opts->root_width > 0) {
-    for (int r = 0; r < 3; ++r) {
-      t->lo[r] = opts->root_lo[r];
-      if (bb.lo[r] < opts->root_lo[r] || bb.hi[r] > opts->root_lo[r] + opts->root_width)
-        return fail(BBFMM_EINVAL, "a point lies outside the root cube");
-    }
-    t->width = opts->root_width;
-  } else {
-    double ext = 0.0;
-    for (int r = 0; r < 3; ++r) ext = std::max(ext, bb.hi[r] - bb.lo[r]);
-    if (!(ext > 0.0)) ext = 1.0;
-    const double w = ext * (1.0 + 1e-12);
-    for (int r = 0; r < 3; ++r) t->lo[r] = bb.lo[r] - 0.5 * (w - (bb.hi[r] - bb.lo[r]));
-    t->width = w;
+  {
+    const bbfmm_status st = root_of(bb.lo, bb.hi, opts->root_lo, opts->root_width, t.get());
+    if (st != BBFMM_OK) return st;
   }
+  if (adaptive) return build_adaptive(t, d_points, n, opts->max_leaf_points, s, out);
   const long long nleaf = 1LL << (3 * t->depth);
   long long bytes = 0;
   unsigned* keys = nullptr;
@@ -274,7 +534,7 @@ bbfmm_status bbfmm_build_octree(const double* d_points, int64_t n, const bbfmm_t
 
 void bbfmm_tree_destroy(bbfmm_tree* t) {
   if (!t) return;
-  dfree(t->xs); dfree(t->ys); dfree(t->zs); dfree(t->perm); dfree(t->leaf_of); dfree(t->leaf_start);
+  free_tree_arrays(t);
   delete t;
 }
 
@@ -290,6 +550,8 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
   if (!std::isfinite(opts->svd_eps)) return fail(BBFMM_EINVAL, "svd_eps is not finite");
   if (opts->order < 2 || opts->order > kMaxOrder)
     return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
+  if (tree->adaptive && tree->xs == nullptr)
+    return fail(BBFMM_ESTATE, "a host-only tree cannot be used for a plan");
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = (hipStream_t)stream;
   std::unique_ptr<bbfmm_plan> p(new (std::nothrow) bbfmm_plan());
@@ -433,13 +695,43 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
     return fail(e == hipErrorOutOfMemory ? BBFMM_ENOMEM : BBFMM_EHIP,
                 std::string("precompute upload: ") + hipGetErrorString(e));
   }
-  p->op_bytes = bytes;
-  long long off = 0;
-  for (int l = 2; l <= depth; ++l) {
-    p->level_off[l] = off;
-    off += (1LL << (3 * l)) * nn;
+  if (tree->adaptive) {
+    // M2L segments: the targets of one (level, octant); tiles are set per nrhs at apply time
+    const AdaptiveTopology& T = tree->topo;
+    for (int l = 2; l < T.nlevels; ++l)
+      for (int o = 0; o < 8; ++o) {
+        const int b = T.m2l_off[l * 8 + o], e2 = T.m2l_off[l * 8 + o + 1];
+        if (e2 == b) continue;
+        M2LLevel sg;
+        std::memset(&sg, 0, sizeof(sg));
+        sg.level = l;
+        sg.side = 1 << std::min(l, 30);
+        sg.npar = e2 - b;
+        sg.set = p->set_of_level[l];
+        sg.scale = p->scale_of_level[l];
+        sg.oct = o;
+        sg.tgt_off = b;
+        p->h_segs.push_back(sg);
+      }
+    if (!p->h_segs.empty() && e == hipSuccess) {
+      e = hipMalloc((void**)&p->d_segs, p->h_segs.size() * sizeof(M2LLevel));
+      if (e == hipSuccess) bytes += (long long)(p->h_segs.size() * sizeof(M2LLevel));
+    }
+    if (e != hipSuccess) {
+      destroy_partial();
+      return fail(e == hipErrorOutOfMemory ? BBFMM_ENOMEM : BBFMM_EHIP,
+                  std::string("precompute upload: ") + hipGetErrorString(e));
+    }
+    p->exp_elems = (long long)T.key.size() * nn;
+  } else {
+    long long off = 0;
+    for (int l = 2; l <= depth; ++l) {
+      p->level_off[l] = off;
+      off += (1LL << (3 * l)) * nn;
+    }
+    p->exp_elems = off;
   }
-  p->exp_elems = off;
+  p->op_bytes = bytes;
   p->precompute_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = p.release();
@@ -452,7 +744,7 @@ void bbfmm_plan_destroy(bbfmm_plan* p) {
   free_buffers(p);
   dfree(p->ops_hi); dfree(p->ops_lo); dfree(p->d_op_off); dfree(p->d_op_rank); dfree(p->d_tab);
   dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
-  dfree(p->d_zeros);
+  dfree(p->d_zeros); dfree(p->d_segs);
   delete p;
 }
 
@@ -487,6 +779,7 @@ bbfmm_status bbfmm_eval_grad(bbfmm_plan* p, const double* d_q, const double* d_g
   if (!d_q || !d_g || !d_grad_x) return fail(BBFMM_EINVAL, "null argument");
   if (roles < 1 || roles > 3) return fail(BBFMM_EINVAL, "roles must be 1, 2 or 3");
   if (nrhs < 1 || nrhs > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64]");
+  if (p->tree->adaptive) return fail(BBFMM_EUNSUPPORTED, "gradients are not supported on adaptive trees");
   if (p->slot_nrhs[0] != nrhs || p->slot_nrhs[1] != nrhs)
     return fail(BBFMM_ESTATE, "eval_grad needs bbfmm_apply(q) and bbfmm_apply_adjoint(g) with this nrhs first");
   hipStream_t s = (hipStream_t)stream;
@@ -541,6 +834,43 @@ bbfmm_status bbfmm_plan_stats(const bbfmm_plan* p, bbfmm_stats* out) {
   out->root_width = t->width;
   out->precompute_seconds = p->precompute_seconds;
   out->device_bytes = t->bytes + p->op_bytes + p->buffer_bytes;
+  if (t->adaptive) {
+    // V-list pairs by level and representative, from the host lists
+    const AdaptiveTopology& T = t->topo;
+    int nlev = 0;
+    const double nn = p->nn;
+    for (int l = 2; l < T.nlevels; ++l) {
+      std::vector<long long> cnt(kNumSym, 0);
+      bool any = false;
+      for (int o = 0; o < 8; ++o)
+        for (int slot = T.m2l_off[l * 8 + o]; slot < T.m2l_off[l * 8 + o + 1]; ++slot)
+          for (int e = 0; e < kFarPerOctant; ++e)
+            if (T.vsrc[(size_t)slot * kFarPerOctant + e] >= 0) {
+              ++cnt[(p->h_tab[o * kFarPerOctant + e] >> 9) & 15];
+              any = true;
+            }
+      nlev += any ? 1 : 0;
+      const int set = p->set_of_level[l];
+      for (int q = 0; q < kNumSym; ++q) {
+        const double c = (double)cnt[q];
+        out->pairs_total += cnt[q];
+        out->pairs_nonempty += cnt[q];
+        const double r = p->ranks[set * kNumSym + q];
+        out->m2l_flops_algorithmic += c * (p->eps > 0 ? 4.0 * nn * r : 2.0 * nn * nn);
+      }
+      // issued: every tile of 64 columns runs every transfer vector of its octant
+      for (int o = 0; o < 8; ++o) {
+        const double targets = T.m2l_off[l * 8 + o + 1] - T.m2l_off[l * 8 + o];
+        for (int q = 0; q < kNumSym; ++q) {
+          const int np_q = p->h_grp[o * 17 + q + 1] - p->h_grp[o * 17 + q];
+          const double per_t = m2l_issued_flops_per_t(p->order, p->lowrank, p->ranks[set * kNumSym + q]);
+          out->m2l_flops_issued += targets / 64.0 * np_q * per_t;
+        }
+      }
+    }
+    out->n_levels_m2l = nlev;
+    return BBFMM_OK;
+  }
   if (t->depth < 2) return BBFMM_OK;
   unsigned long long* d_counts = nullptr;
   const int nlev = t->depth - 1;
@@ -580,6 +910,7 @@ bbfmm_status bbfmm_debug_get_expansions(const bbfmm_plan* p, int32_t level, int3
                                         double* d_out, void* stream) {
   if (!p || !d_out) return fail(BBFMM_EINVAL, "null argument");
   const bbfmm_tree* t = p->tree;
+  if (t->adaptive) return fail(BBFMM_EUNSUPPORTED, "uniform trees only");
   if (level < 2 || level > t->depth) return fail(BBFMM_EINVAL, "level must be in [2, depth]");
   if (which < 0 || which > 2) return fail(BBFMM_EINVAL, "which must be 0, 1 or 2");
   const int nrhs = p->slot_nrhs[0];
@@ -602,6 +933,7 @@ bbfmm_status bbfmm_debug_get_expansions(const bbfmm_plan* p, int32_t level, int3
 bbfmm_status bbfmm_debug_m2l_level(bbfmm_plan* p, int32_t level, const double* d_w, int32_t nrhs,
                                    double* d_f, void* stream) {
   if (!p || !d_w || !d_f) return fail(BBFMM_EINVAL, "null argument");
+  if (p->tree->adaptive) return fail(BBFMM_EUNSUPPORTED, "uniform trees only");
   if (level < 2 || level > p->tree->depth) return fail(BBFMM_EINVAL, "level must be in [2, depth]");
   if (nrhs < 1 || nrhs > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64]");
   const M2LArgs a = m2l_args(p, nrhs, d_w, d_f, level);
@@ -612,10 +944,104 @@ bbfmm_status bbfmm_debug_m2l_level(bbfmm_plan* p, int32_t level, const double* d
 bbfmm_status bbfmm_debug_tree_order(const bbfmm_tree* t, int32_t* d_perm, int32_t* d_leaf_start,
                                     void* stream) {
   if (!t || !d_perm || !d_leaf_start) return fail(BBFMM_EINVAL, "null argument");
+  if (t->adaptive) return fail(BBFMM_EUNSUPPORTED, "uniform trees only");
   hipStream_t s = (hipStream_t)stream;
   BBFMM_HIP_TRY(hipMemcpyAsync(d_perm, t->perm, t->n * sizeof(int), hipMemcpyDeviceToDevice, s));
   BBFMM_HIP_TRY(hipMemcpyAsync(d_leaf_start, t->leaf_start, ((1LL << (3 * t->depth)) + 1) * sizeof(int),
                                hipMemcpyDeviceToDevice, s));
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_adaptive_info_of(const bbfmm_tree* t, bbfmm_adaptive_info* out) {
+  if (!t || !out) return fail(BBFMM_EINVAL, "null argument");
+  if (!t->adaptive) return fail(BBFMM_EINVAL, "not an adaptive tree");
+  const AdaptiveTopology& T = t->topo;
+  std::memset(out, 0, sizeof(*out));
+  out->n_levels = T.nlevels;
+  out->n_nodes = (int32_t)T.key.size();
+  out->n_leaves = (int32_t)T.leaves.size();
+  out->n_u = (int64_t)T.u_idx.size();
+  out->n_w = (int64_t)T.w_idx.size();
+  out->n_x_nodes = (int64_t)T.x_node.size();
+  out->n_x = (int64_t)T.x_idx.size();
+  out->n_m2l_targets = (int64_t)T.m2l_tgt.size();
+  out->v_pairs = T.v_pairs;
+  out->u_point_pairs = T.u_pairs;
+  out->w_pairs = T.w_pairs;
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_adaptive_array(const bbfmm_tree* t, int32_t which, int64_t* out) {
+  if (!t || !out) return fail(BBFMM_EINVAL, "null argument");
+  if (!t->adaptive) return fail(BBFMM_EINVAL, "not an adaptive tree");
+  const AdaptiveTopology& T = t->topo;
+  auto put = [&](const auto& v) {
+    for (size_t i = 0; i < v.size(); ++i) out[i] = (int64_t)v[i];
+    return BBFMM_OK;
+  };
+  switch (which) {
+    case 0: return put(T.level_off);
+    case 1: return put(T.key);
+    case 2: return put(T.level);
+    case 3: return put(T.start);
+    case 4: return put(T.end);
+    case 5: return put(T.leaf);
+    case 6: return put(T.child_begin);
+    case 7: return put(T.child_end);
+    case 8: return put(T.leaves);
+    case 9: return put(T.u_off);
+    case 10: return put(T.u_idx);
+    case 11: return put(T.w_off);
+    case 12: return put(T.w_idx);
+    case 13: return put(T.x_node);
+    case 14: return put(T.x_off);
+    case 15: return put(T.x_idx);
+    case 16: return put(T.m2l_tgt);
+    case 17: return put(T.m2l_off);
+    case 18: return put(T.vsrc);
+    case 19: {
+      if (t->xs == nullptr) return put(t->host_perm);
+      std::vector<int> perm(t->n);
+      BBFMM_HIP_TRY(hipMemcpy(perm.data(), t->perm, t->n * sizeof(int), hipMemcpyDeviceToHost));
+      return put(perm);
+    }
+    default: return fail(BBFMM_EINVAL, "unknown array");
+  }
+}
+
+bbfmm_status bbfmm_host_adaptive_tree(const double* points, int64_t n, int32_t max_leaf_points,
+                                      const double root_lo[3], double root_width, bbfmm_tree** out) {
+  if (!out) return fail(BBFMM_EINVAL, "out is null");
+  *out = nullptr;
+  if (!points) return fail(BBFMM_EINVAL, "null points");
+  if (n < 1 || n > 0x7fffffffLL) return fail(BBFMM_EINVAL, "n must be in [1, 2^31 - 1]");
+  if (max_leaf_points < 1) return fail(BBFMM_EINVAL, "max_leaf_points must be >= 1");
+  if (root_width > 0 && !root_lo) return fail(BBFMM_EINVAL, "root_lo is null");
+  double lo[3], hi[3];
+  for (int r = 0; r < 3; ++r) {
+    lo[r] = points[r];
+    hi[r] = points[r];
+  }
+  for (long long i = 0; i < n; ++i)
+    for (int r = 0; r < 3; ++r) {
+      const double x = points[3 * i + r];
+      if (!std::isfinite(x)) return fail(BBFMM_EINVAL, "points contain non-finite coordinates");
+      lo[r] = std::min(lo[r], x);
+      hi[r] = std::max(hi[r], x);
+    }
+  std::unique_ptr<bbfmm_tree> t(new (std::nothrow) bbfmm_tree());
+  if (!t) return fail(BBFMM_ENOMEM, "host allocation");
+  const double zero[3] = {0, 0, 0};
+  const bbfmm_status st = root_of(lo, hi, root_lo ? root_lo : zero, root_width, t.get());
+  if (st != BBFMM_OK) return st;
+  t->n = n;
+  t->adaptive = true;
+  t->max_leaf_points = max_leaf_points;
+  std::vector<int> grp;
+  const std::vector<int> tab = octant_tables(&grp);
+  host_adaptive_build(points, n, max_leaf_points, t->lo, t->width, tab.data(), t->topo, t->host_perm);
+  t->depth = t->topo.nlevels - 1;
+  *out = t.release();
   return BBFMM_OK;
 }
 

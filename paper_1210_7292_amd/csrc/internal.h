@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/bbfmm.h"
+#include "adaptive_host.h"
 #include "host_math.h"
 
 namespace bbfmm {
@@ -15,6 +16,7 @@ namespace bbfmm {
 constexpr int kMaxDepth = 8;
 constexpr int kMaxLevels = kMaxDepth + 1;
 constexpr int kMaxRhs = 64;
+constexpr int kMaxPlanLevels = kAdaptiveDepth + 1;   // levels a plan may hold operators for
 
 // ---- Morton order: x bit lowest, then y, then z (10 bits per axis) -------------------------
 __host__ __device__ inline uint32_t spread3(uint32_t v) {
@@ -69,6 +71,8 @@ struct M2LLevel {
   int block_begin;       // first logical block of the level
   int set;               // operator set
   double scale;          // homogeneity factor of the level
+  int oct;               // adaptive segments: octant of all targets of the segment
+  int tgt_off;           // adaptive segments: first slot of the segment in tgt / vsrc
 };
 
 struct M2LArgs {
@@ -86,11 +90,21 @@ struct M2LArgs {
   const short* sig;            // [48][NP]; entries >= l^3 map to l^3
   const short* siginv;         // [48][NP]
   const double* zeros;         // l^3 * 64 zeros: the multipoles of a missing source
+  // adaptive trees: one segment per (level, octant) in device memory; W and F of every segment
+  // are the whole node arrays [node][l^3][nrhs]; target and sources come from the lists
+  const M2LLevel* segs;        // nsegs segments, block_begin filled by launch_m2l
+  int nsegs;
+  const int* tgt;              // node of each target slot
+  const int* vsrc;             // [slot][189]: source node of table entry e, or -1
 };
 
 // Returns the LDS-capacity rank limit of the compressed M2L kernel for an order.
 int m2l_ia_rank_limit(int order);
-// Launches the M2L over the levels in `a` (blocks = a.nblocks rounded up to 8).
+// Columns ((target, rhs) pairs) per M2L workgroup.
+int m2l_block_cols(bool lowrank);
+// Launches the M2L over the levels in `a` (blocks = a.nblocks rounded up to 8). Uniform trees:
+// the tiling is computed here. Adaptive trees (a.segs set): a.nblocks, a.cols and the segments'
+// block_begin come from the caller, with a.cols = m2l_block_cols(lowrank).
 hipError_t launch_m2l(int order, bool lowrank, int prec, const M2LArgs& a, hipStream_t s);
 // MFMA work actually issued per (target tile of 64 columns, representative p, one t),
 // in flops, for reporting.
@@ -109,6 +123,23 @@ hipError_t launch_scatter(const unsigned* keys, long long n, const int* leaf_sta
 hipError_t launch_order(const double* pts, const unsigned* keys, long long n,
                         const int* leaf_start, const int* tmp, int* perm, int* leaf_of,
                         double* xs, double* ys, double* zs, hipStream_t s);
+
+// ---- adaptive tree build ------------------------------------------------------------------
+hipError_t launch_keys64(const double* pts, long long n, const double lo[3], double width,
+                         unsigned long long* keys, int* idx, hipStream_t s);
+// Stable LSD radix sort of (keys, vals) by the low `bits` bits; the result ends in keys / vals.
+hipError_t radix_sort64(unsigned long long* keys, int* vals, unsigned long long* ktmp, int* vtmp,
+                        long long n, int bits, hipStream_t s);
+hipError_t launch_seg_flags(const unsigned long long* keys, long long n, int level,
+                            const unsigned char* active, int* sflag, int* eflag, hipStream_t s);
+hipError_t launch_seg_compact(const unsigned long long* keys, long long n, int level, const int* sflag,
+                              const int* sidx, const int* eflag, const int* eidx,
+                              unsigned long long* node_key, int* node_start, int* node_end, hipStream_t s);
+hipError_t launch_seg_next(long long n, int level, int max_pts, int node_base, const int* sidx,
+                           const int* sflag, const int* node_start, const int* node_end,
+                           unsigned char* active, int* leaf_of, hipStream_t s);
+hipError_t launch_sorted_soa(const double* pts, const int* idx, long long n, double* xs, double* ys,
+                             double* zs, hipStream_t s);
 
 // ---- passes -------------------------------------------------------------------------------
 struct PassGeom {
@@ -134,17 +165,59 @@ hipError_t launch_grad(const PassGeom& g, const double* qs, const double* gs, co
 hipError_t launch_count_pairs(const int* leaf_start, int depth, int level, const int* tab,
                               unsigned long long* counts16, hipStream_t s);
 
+// ---- adaptive passes ----------------------------------------------------------------------
+// Node arrays of an adaptive tree on the device (global node ids, level-major).
+struct AdaptiveGeom {
+  const double* xs; const double* ys; const double* zs;   // sorted points
+  const int* perm; const int* leaf_of;                     // leaf_of: global node id
+  long long n;
+  const int* start; const int* end;                        // point range of each node
+  const double* cen;                                       // [node][4]: centre x, y, z, half width
+  const int* child_begin; const int* child_end;
+  const unsigned char* oct;                                // octant of each node in its parent
+  const double* tk; const double* m2m;
+  int order; int kernel; double c;
+};
+// Kernel fill (not a memset, so that the call may sit in a captured graph).
+hipError_t launch_fill_zero(double* x, long long n, hipStream_t s);
+hipError_t launch_ad_p2m(const AdaptiveGeom& g, const int* leaves, int nleaves, const double* qs,
+                         int nrhs, double* W, hipStream_t s);
+hipError_t launch_ad_m2m(const AdaptiveGeom& g, int node_begin, int node_end, double* W, int nrhs,
+                         hipStream_t s);
+hipError_t launch_ad_l2l(const AdaptiveGeom& g, int node_begin, int node_end, double* F, int nrhs,
+                         hipStream_t s);
+hipError_t launch_ad_p2l(const AdaptiveGeom& g, const int* x_node, const int* x_off, const int* x_idx,
+                         int nx, const double* qs, int nrhs, double* F, hipStream_t s);
+hipError_t launch_ad_l2p(const AdaptiveGeom& g, const double* F, int nrhs, double* phis, hipStream_t s);
+hipError_t launch_ad_m2p(const AdaptiveGeom& g, const int* leaves, const int* w_off, const int* w_idx,
+                         int nleaves, const double* W, int nrhs, double* phis, hipStream_t s);
+hipError_t launch_ad_p2p_scatter(const AdaptiveGeom& g, const int* leaf_pos, const int* u_off,
+                                 const int* u_idx, const double* qs, const double* phis_far, int nrhs,
+                                 double* phi_out, hipStream_t s);
+
 }  // namespace bbfmm
 
 struct bbfmm_tree {
   long long n = 0;
-  int depth = 0;
+  int depth = 0;                 // uniform: leaf level; adaptive: deepest level
+  bool adaptive = false;
+  int max_leaf_points = 0;
   double lo[3] = {0, 0, 0};
   double width = 1.0;
   int device = 0;
   double* xs = nullptr; double* ys = nullptr; double* zs = nullptr;
   int* perm = nullptr; int* leaf_of = nullptr; int* leaf_start = nullptr;
   long long bytes = 0;
+  // adaptive trees: host topology and its device copy
+  bbfmm::AdaptiveTopology topo;
+  std::vector<int> host_perm;    // host-only trees: the sorted order
+  int* d_start = nullptr; int* d_end = nullptr; double* d_cen = nullptr;
+  int* d_child_begin = nullptr; int* d_child_end = nullptr; unsigned char* d_oct = nullptr;
+  int* d_leaves = nullptr; int* d_leaf_pos = nullptr;
+  int* d_u_off = nullptr; int* d_u_idx = nullptr;
+  int* d_w_off = nullptr; int* d_w_idx = nullptr;
+  int* d_x_node = nullptr; int* d_x_off = nullptr; int* d_x_idx = nullptr;
+  int* d_m2l_tgt = nullptr; int* d_vsrc = nullptr;
 };
 
 struct bbfmm_plan {
@@ -153,8 +226,8 @@ struct bbfmm_plan {
   int nn = 0; int np = 0;
   bool lowrank = false;
   int nsets = 1;
-  int set_of_level[bbfmm::kMaxLevels] = {0};
-  double scale_of_level[bbfmm::kMaxLevels] = {0};
+  int set_of_level[bbfmm::kMaxPlanLevels] = {0};
+  double scale_of_level[bbfmm::kMaxPlanLevels] = {0};
   std::vector<int> ranks;                 // [set][16]
   std::vector<long long> op_off;          // [set][16][2]
   double precompute_seconds = 0;
@@ -168,7 +241,11 @@ struct bbfmm_plan {
   // work buffers
   int nrhs_cap = 0;
   long long level_off[bbfmm::kMaxLevels] = {0};   // element offsets (per rhs) into W / F
-  long long exp_elems = 0;                         // per rhs
+  long long exp_elems = 0;                         // per rhs (adaptive: nodes * l^3)
+  std::vector<bbfmm::M2LLevel> h_segs;             // adaptive M2L segments
+  bbfmm::M2LLevel* d_segs = nullptr;
+  int segs_nrhs = 0;                               // nrhs the uploaded segment tiling is for
+  int seg_blocks = 0;
   double* W = nullptr;
   double* F[2] = {nullptr, nullptr};               // forward / adjoint locals
   double* qs[2] = {nullptr, nullptr};              // sorted q / g

@@ -68,6 +68,7 @@ struct BlockPos {
   int tile;
 };
 
+template <bool AD>
 __device__ inline bool locate(const M2LArgs& a, BlockPos& bp) {
   // Logical block order is level-major, then tile, then octant, so the 8 octants of one group of
   // parents are adjacent. Hardware sends block b to XCD b % 8; remapping gives each XCD a
@@ -75,6 +76,21 @@ __device__ inline bool locate(const M2LArgs& a, BlockPos& bp) {
   const int per = gridDim.x / 8;
   const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= a.nblocks) return false;
+  if (AD) {
+    // adaptive: the last (level, octant) segment starting at or before this block
+    int lo = 0, hi = a.nsegs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (a.segs[mid].block_begin <= logical) lo = mid;
+      else hi = mid - 1;
+    }
+    bp.lv = a.segs[lo];
+    bp.lv.W = a.lv[0].W;     // every segment reads and writes the whole node arrays
+    bp.lv.F = a.lv[0].F;
+    bp.oct = bp.lv.oct;
+    bp.tile = logical - bp.lv.block_begin;
+    return true;
+  }
   // static indices only: a dynamic index would copy the argument struct to scratch memory
   bp.lv = a.lv[0];
 #pragma unroll
@@ -87,12 +103,14 @@ __device__ inline bool locate(const M2LArgs& a, BlockPos& bp) {
 }
 
 struct Column {
-  int tx, ty, tz;     // target cell coordinates
-  unsigned target;    // Morton index of the target cell
+  int tx, ty, tz;     // target cell coordinates (uniform trees)
+  unsigned target;    // Morton index (uniform) or node (adaptive) of the target cell
+  int slot;           // adaptive: row of the target in the source lists
   int rhs;
   bool valid;
 };
 
+template <bool AD>
 __device__ inline Column column_of(const M2LArgs& a, const BlockPos& bp, int col_in_tile) {
   Column c;
   const int col = bp.tile * a.cols + col_in_tile;
@@ -100,14 +118,28 @@ __device__ inline Column column_of(const M2LArgs& a, const BlockPos& bp, int col
   c.rhs = col - P * a.nrhs;
   c.valid = P < bp.lv.npar;
   const unsigned Pm = c.valid ? (unsigned)P : 0u;
-  c.target = Pm * 8u + (unsigned)bp.oct;
-  demorton3(c.target, c.tx, c.ty, c.tz);
+  if (AD) {
+    c.slot = bp.lv.tgt_off + (int)Pm;
+    c.target = (unsigned)a.tgt[c.slot];
+    c.tx = c.ty = c.tz = 0;
+  } else {
+    c.slot = 0;
+    c.target = Pm * 8u + (unsigned)bp.oct;
+    demorton3(c.target, c.tx, c.ty, c.tz);
+  }
   return c;
 }
 
-// Multipole column of the source Y = X + d for this lane, or null outside the level.
-__device__ inline const double* source_of(const M2LArgs& a, const BlockPos& bp, const Column& c,
+// Multipole column of the source of table entry e (offset `ent`) for this lane, or null when the
+// source is outside the level (uniform) or absent (adaptive).
+template <bool AD>
+__device__ inline const double* source_of(const M2LArgs& a, const BlockPos& bp, const Column& c, int e,
                                           int ent, int nn) {
+  if (AD) {
+    const int y = c.valid ? a.vsrc[(long long)c.slot * kFarPerOctant + e] : -1;
+    if (y < 0) return nullptr;
+    return bp.lv.W + ((long long)y * nn) * a.nrhs + c.rhs;
+  }
   const int sx = c.tx + (ent & 7) - 3, sy = c.ty + ((ent >> 3) & 7) - 3,
             sz = c.tz + ((ent >> 6) & 7) - 3;
   const int side = bp.lv.side;
@@ -132,7 +164,7 @@ __device__ inline void store_tile(const M2LArgs& a, const BlockPos& bp, const Co
 }
 
 // ------------------------------------------------------------------------ full-rank M2L ----
-template <int L, int KC, int PREC>
+template <int L, int KC, int PREC, bool AD>
 __global__ __launch_bounds__(kThreads) void m2l_full_kernel(M2LArgs a) {
   using A = Arith<PREC>;
   using T = typename A::T;
@@ -147,10 +179,10 @@ __global__ __launch_bounds__(kThreads) void m2l_full_kernel(M2LArgs a) {
   __shared__ T klo[SPLIT ? (NN + 1) * LDK : 1];
 
   BlockPos bp;
-  if (!locate(a, bp)) return;
+  if (!locate<AD>(a, bp)) return;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int j = lane % 16, kq = lane / 16;
-  const Column col = column_of(a, bp, 16 * wave + j);
+  const Column col = column_of<AD>(a, bp, 16 * wave + j);
   const int set = bp.lv.set;
 
   V acc[MB];
@@ -179,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void m2l_full_kernel(M2LArgs a) {
       for (int e = g0; e < g1; ++e) {
         const int ent = a.tab[bp.oct * kFarPerOctant + e];
         const int perm = ent >> 13;
-        const double* src = source_of(a, bp, col, ent, NN);
+        const double* src = source_of<AD>(a, bp, col, e, ent, NN);
         const short* sg = a.sig + perm * NP;
         const short* si = a.siginv + perm * NP;
         int srow[MB];
@@ -327,7 +359,7 @@ struct Lowrank {
   }
 };
 
-template <int L, int RMAX, int PREC, int W8, bool ONE_RHS>
+template <int L, int RMAX, int PREC, int W8, bool ONE_RHS, bool AD>
 __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
   using K = Lowrank<L, RMAX, PREC, W8, ONE_RHS>;
   using T = typename K::T;
@@ -345,10 +377,10 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
   __shared__ short sgs[SIGLDS ? kNumPerms * NP : 1];
 
   BlockPos bp;
-  if (!locate(a, bp)) return;
+  if (!locate<AD>(a, bp)) return;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int j = lane % 16, kq = lane / 16;
-  const Column col = column_of(a, bp, 16 * wave + j);
+  const Column col = column_of<AD>(a, bp, 16 * wave + j);
   const int set = bp.lv.set;
   const int nrhs = a.nrhs;
   const int* tab = a.tab + bp.oct * kFarPerOctant;
@@ -366,14 +398,14 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
     acc64[mb] = f64x4{0, 0, 0, 0};
   }
 
-  auto source = [&](int ent) -> gdouble* {
-    const double* s = source_of(a, bp, col, ent, NN);
+  auto source = [&](int e, int ent) -> gdouble* {
+    const double* s = source_of<AD>(a, bp, col, e, ent, NN);
     return s ? (gdouble*)s : zero_src;
   };
 
   double w[CH][4];
   int cur_p = -1, r = 0, zb = 0;
-  gdouble* src = source(tab[0]);
+  gdouble* src = source(0, tab[0]);
   if (PREFETCH) K::load(src, nrhs, kq, 0, w);
   for (int e = 0; e < kFarPerOctant; ++e) {
     const int ent = tab[e];
@@ -413,7 +445,7 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
     }
     // ---- next transfer vector's multipoles, in flight during GEMM 2 ----
     if (e + 1 < kFarPerOctant) {
-      src = source(tab[e + 1]);
+      src = source(e + 1, tab[e + 1]);
       if (PREFETCH) K::load(src, nrhs, kq, 0, w);
     }
     // ---- GEMM 2 ----
@@ -453,27 +485,33 @@ void tile(M2LArgs& a, int cols) {
   a.nblocks = blocks;
 }
 
-template <int L, int PREC>
-hipError_t launch_l(bool lowrank, M2LArgs a, hipStream_t s) {
+template <int L, int PREC, bool AD>
+hipError_t launch_ld(bool lowrank, M2LArgs a, hipStream_t s) {
   if (lowrank) {
     if constexpr (L >= 3) {
-      tile(a, 16 * kLowrankWaves);
+      if (!AD) tile(a, 16 * kLowrankWaves);
       const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
       if (a.nrhs == 1)
-        hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, true>), dim3(grid),
+        hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, true, AD>), dim3(grid),
                            dim3(64 * kLowrankWaves), 0, s, a);
       else
-        hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, false>), dim3(grid),
+        hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, false, AD>), dim3(grid),
                            dim3(64 * kLowrankWaves), 0, s, a);
     } else {
       return hipErrorInvalidValue;
     }
   } else {
-    tile(a, kCols);
+    if (!AD) tile(a, kCols);
     const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
-    hipLaunchKernelGGL((m2l_full_kernel<L, full_kc<L>(), PREC>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((m2l_full_kernel<L, full_kc<L>(), PREC, AD>), dim3(grid), dim3(kThreads), 0, s, a);
   }
   return hipGetLastError();
+}
+
+template <int L, int PREC>
+hipError_t launch_l(bool lowrank, const M2LArgs& a, hipStream_t s) {
+  if (a.segs != nullptr) return launch_ld<L, PREC, true>(lowrank, a, s);
+  return launch_ld<L, PREC, false>(lowrank, a, s);
 }
 
 template <int PREC>
@@ -497,8 +535,11 @@ int m2l_ia_rank_limit(int order) {
   return order <= 6 ? 32 : 16;
 }
 
+int m2l_block_cols(bool lowrank) { return lowrank ? 16 * kLowrankWaves : kCols; }
+
 hipError_t launch_m2l(int order, bool lowrank, int prec, const M2LArgs& a0, hipStream_t s) {
-  if (a0.nlev <= 0) return hipSuccess;
+  if (a0.segs == nullptr && a0.nlev <= 0) return hipSuccess;
+  if (a0.segs != nullptr && (a0.nsegs <= 0 || a0.nblocks <= 0)) return hipSuccess;
   const M2LArgs& a = a0;
   switch (prec) {
     case 0: return launch_prec<0>(order, lowrank, a, s);

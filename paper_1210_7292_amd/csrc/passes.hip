@@ -5,45 +5,12 @@
 // Layouts: points sorted in Morton leaf order (SoA), densities [point][rhs], expansions
 // [cell][l^3][rhs] with cells of a level in Morton order and interpolation points in the order
 // m(a) = a1 + l a2 + l^2 a3 (Sec. 3.1).
+#include "device_math.h"
 #include "internal.h"
 
 namespace bbfmm {
 
 namespace {
-
-// S_l(u, xbar_m) = 1/l + 2/l sum_{k>=1} T_k(u) T_k(xbar_m) for all m; tk[k*L + m] = T_k(xbar_m).
-template <int L>
-__device__ inline void cheb_basis_all(double u, const double* tk, double* out) {
-  double t[L];
-  t[0] = 1.0;
-  if (L > 1) t[1] = u;
-#pragma unroll
-  for (int k = 2; k < L; ++k) t[k] = 2.0 * u * t[k - 1] - t[k - 2];
-#pragma unroll
-  for (int m = 0; m < L; ++m) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 1; k < L; ++k) s += t[k] * tk[k * L + m];
-    out[m] = (1.0 + 2.0 * s) / L;
-  }
-}
-
-// d/du of the same basis: T_k'(u) = k U_{k-1}(u).
-template <int L>
-__device__ inline void cheb_basis_deriv_all(double u, const double* tk, double* out) {
-  double uu[L > 1 ? L - 1 : 1];
-  uu[0] = 1.0;
-  if (L > 2) uu[1] = 2.0 * u;
-#pragma unroll
-  for (int k = 2; k < L - 1; ++k) uu[k] = 2.0 * u * uu[k - 1] - uu[k - 2];
-#pragma unroll
-  for (int m = 0; m < L; ++m) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 1; k < L; ++k) s += k * uu[k - 1] * tk[k * L + m];
-    out[m] = 2.0 * s / L;
-  }
-}
 
 __device__ inline void cell_center(const PassGeom& g, int level, unsigned cell, double* c,
                                    double* half) {
@@ -54,30 +21,6 @@ __device__ inline void cell_center(const PassGeom& g, int level, unsigned cell, 
   c[1] = g.lo[1] + (iy + 0.5) * w;
   c[2] = g.lo[2] + (iz + 0.5) * w;
   *half = 0.5 * w;
-}
-
-template <int KIND>
-__device__ inline double kern(double r2, double c2) {
-  if (KIND == kInvR) return r2 > 0.0 ? rsqrt(r2) : 0.0;
-  if (KIND == kInvSqrtR2C2) return rsqrt(r2 + c2);
-  if (KIND == kR2) return r2;
-  return r2 * r2;
-}
-
-// (1/r) dK/dr, so that grad_x K(x, y) = kern_dr(r2) * (x - y).
-template <int KIND>
-__device__ inline double kern_dr(double r2, double c2) {
-  if (KIND == kInvR) {
-    if (!(r2 > 0.0)) return 0.0;
-    const double ir = rsqrt(r2);
-    return -ir * ir * ir;
-  }
-  if (KIND == kInvSqrtR2C2) {
-    const double ir = rsqrt(r2 + c2);
-    return -ir * ir * ir;
-  }
-  if (KIND == kR2) return 2.0;
-  return 4.0 * r2;
 }
 
 __global__ void gather_rows_kernel(const double* __restrict__ in, const int* __restrict__ perm,

@@ -64,7 +64,8 @@ def test_polynomial_kernel_is_exact_on_adaptive_tree(kind, order):
     assert O.rel_l2(phi, O.brute_force(pts, q, kind)) < 1e-12
 
 
-def test_uniform_refinement_reduces_to_uniform_oracle():
+@pytest.mark.parametrize("eps", [0.0, 1e-5])
+def test_uniform_refinement_reduces_to_uniform_oracle(eps):
     # 8 points per depth-2 cell in a regular pattern: with max_pts = 8 the adaptive tree is the
     # uniform tree of depth 2 (every level-1 cell holds 64 > 8 points)
     rng = np.random.default_rng(4)
@@ -74,9 +75,11 @@ def test_uniform_refinement_reduces_to_uniform_oracle():
     q = rng.uniform(-1, 1, (pts.shape[0], 1))
     tree = A.build(pts, 8, lo=np.zeros(3), width=1.0)
     assert all(c.level == 2 for c in tree.cells if c.leaf)
-    phi, _ = A.fmm_apply(pts, q, 4, 8, tree=tree)
-    ref = O.fmm_apply(pts, q, 4, 2).phi
+    phi, _ = A.fmm_apply(pts, q, 4, 8, tree=tree, eps=eps)
+    ref = O.fmm_apply(pts, q, 4, 2, eps=eps).phi
     assert O.rel_l2(phi, ref) < 1e-13
+    if eps > 0:       # the compression is really applied
+        assert O.rel_l2(phi, A.fmm_apply(pts, q, 4, 8, tree=tree)[0]) > 1e-9
 
 
 def test_inverse_r_error_small_and_falls_with_order():
