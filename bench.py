@@ -50,6 +50,51 @@ def direct_sum_gpu(torch, pts, q, targets, kernel, c, chunk=1 << 16):
     return out
 
 
+def pass_work(np, tree, w, nrhs):
+    """Algorithmic HBM bytes of the bandwidth-bound passes and the near-field interaction count
+    of one apply: P2M reads positions and densities and writes leaf multipoles; L2P the reverse;
+    M2M reads children and writes parents; L2L reads parents and updates children; every
+    expansion is l^3 nrhs FP64 values."""
+    nn = w.order ** 3
+    e = 8.0 * nn * nrhs                      # bytes of one expansion
+    n = w.n
+    if w.depth >= 0:
+        d = w.depth
+        _, ls = tree.order()
+        counts = np.diff(ls.cpu().numpy().astype(np.int64))
+        s = 1 << d
+        # leaf coordinates of Morton index m (x bit lowest)
+        m = np.arange(s ** 3, dtype=np.int64)
+        ijk = np.zeros((m.size, 3), dtype=np.int64)
+        for b in range(d):
+            for r in range(3):
+                ijk[:, r] |= ((m >> (3 * b + r)) & 1) << b
+        grid = np.zeros((s, s, s), dtype=np.int64)
+        grid[ijk[:, 0], ijk[:, 1], ijk[:, 2]] = counts
+        pad = np.pad(grid, 1)
+        nb = sum(pad[1 + dx:1 + dx + s, 1 + dy:1 + dy + s, 1 + dz:1 + dz + s]
+                 for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1))
+        pairs = int((grid * nb).sum()) - n
+        nleaf = s ** 3
+        m2m = sum((8 ** (l + 1) + 8 ** l) * e for l in range(2, d))
+        l2l = sum((8 ** l + 2 * 8 ** (l + 1)) * e for l in range(2, d))
+    else:
+        a = tree.arrays()
+        nleaf = a["info"]["n_leaves"]
+        pairs = a["info"]["u_point_pairs"] - n
+        lev = a["level"]
+        nonleaf = (a["child_end"] > a["child_begin"]) & (lev >= 2)
+        kids = int((a["child_end"] - a["child_begin"])[nonleaf].sum())
+        m2m = (kids + int(nonleaf.sum())) * e
+        nonleaf_l2l = (a["child_end"] > a["child_begin"]) & (lev >= 2)
+        kids2 = int((a["child_end"] - a["child_begin"])[nonleaf_l2l].sum())
+        l2l = (int(nonleaf_l2l.sum()) + 2 * kids2) * e
+    p2m = n * (24 + 8 * nrhs) + nleaf * e
+    l2p = nleaf * e + n * (24 + 8 * nrhs)
+    return {"p2m_bytes": p2m, "m2m_bytes": m2m, "l2l_bytes": l2l, "l2p_bytes": l2p,
+            "p2p_interactions": pairs}
+
+
 def cpu_baseline(w, inp, sample_n, grad_mode=False):
     """The oracle (as it stands) on a bounded sample of the same workload, on the host cores."""
     import numpy as np
@@ -73,12 +118,32 @@ def cpu_baseline(w, inp, sample_n, grad_mode=False):
                       f"one oracle {'apply + adjoint + gradient' if grad_mode else 'fmm_apply'} in {dt:.2f} s"}
 
 
+def cpu_baseline_adaptive(w, inp, sample_n):
+    """The adaptive oracle on an evenly strided sample of the workload's points (both parts of
+    the cloud), same order, leaf size, kernel and right-hand sides."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import adaptive_oracle as A
+    stride = max(1, inp.points.shape[0] // sample_n)
+    pts = inp.points[::stride][:sample_n]
+    q = inp.q[::stride][:sample_n]
+    t0 = time.perf_counter()
+    _, tree = A.fmm_apply(pts, q, w.order, w.max_leaf_points, w.kernel, w.c, eps=w.svd_eps)
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    n = pts.shape[0]
+    return {"value": n / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"every {stride}-th point of the workload ({n} points, {len(tree.cells)} cells, "
+                      f"{w.nrhs} right-hand sides), one adaptive-oracle fmm_apply in {dt:.2f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, help="workload number (1-4)")
+    ap.add_argument("--config", type=int, default=2, help="workload number (1-5)")
     ap.add_argument("--prec", default=None, help="override M2L precision: fp64 | fp32 | split32")
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="points in the oracle sample (default: 100000; 20000 for order 7)")
@@ -111,9 +176,7 @@ def main():
     from workloads import WORKLOADS, make_inputs
 
     w = WORKLOADS[args.config]
-    if w.depth < 0:
-        print("the adaptive-tree workload is not built", file=sys.stderr)
-        sys.exit(2)
+    adaptive = w.depth < 0
     prec = args.prec or w.m2l_prec
     dev = torch.device("cuda:0")
     log(f"[bench] workload {w.name}: drawing inputs")
@@ -124,12 +187,18 @@ def main():
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()
-    tree = pk.Octree(pts, w.depth)
+    if adaptive:
+        tree = pk.Octree(pts, -1, root_width=0.0, max_leaf_points=w.max_leaf_points)
+    else:
+        tree = pk.Octree(pts, w.depth)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
     plan = pk.Plan(tree, w.kernel, w.order, w.svd_eps, prec, w.c)
     st = plan.stats()
     log(f"[bench] tree {build_ms:.1f} ms, precompute {st['precompute_seconds']:.2f} s, ranks {st['rank']}")
+    tree_info = tree.arrays()["info"] if adaptive else None
+    if adaptive:
+        log(f"[bench] adaptive tree: {tree_info}")
 
     # config 4 differentiates: a step is forward, adjoint and position gradient
     grad_mode = args.config == 4
@@ -167,6 +236,19 @@ def main():
         + ", ".join(f"{k} {v / max(calls, 1):.3f}" for k, v in passes.items()))
 
     m2l_ms = passes["m2l"] / calls
+    work = pass_work(np, tree, w, w.nrhs)
+    per = {k: v / calls for k, v in passes.items()}
+    achieved_bw = {
+        "p2m_GBps": work["p2m_bytes"] / (per["p2m"] * 1e-3) / 1e9 if per["p2m"] > 0 else None,
+        "m2m_GBps": work["m2m_bytes"] / (per["m2m"] * 1e-3) / 1e9 if per["m2m"] > 0 else None,
+        "l2l_GBps": work["l2l_bytes"] / (per["l2l"] * 1e-3) / 1e9 if per["l2l"] > 0 else None,
+        "l2p_GBps": work["l2p_bytes"] / (per["l2p"] * 1e-3) / 1e9 if per["l2p"] > 0 else None,
+        "p2p_interactions_per_s": work["p2p_interactions"] / (per["p2p"] * 1e-3) if per["p2p"] > 0 else None,
+        "hbm_peak_GBps": 8000.0,
+        "note": ("algorithmic bytes per pass / pass time (HIP events); adaptive trees time P2L "
+                 "with L2L and M2P with L2P" if adaptive else
+                 "algorithmic bytes per pass / pass time (HIP events)"),
+    }
     flops = st["m2l_flops_algorithmic"] * w.nrhs
     achieved = flops / (m2l_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
@@ -211,9 +293,14 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        n_cpu = args.cpu_sample or (20_000 if w.order >= 7 else 100_000)
-        log(f"[bench] oracle on {n_cpu} points (host cores)")
-        cpu = cpu_baseline(w, inp, n_cpu, grad_mode)
+        if adaptive:
+            n_cpu = args.cpu_sample or 5_000
+            log(f"[bench] adaptive oracle on {n_cpu} points (host cores)")
+            cpu = cpu_baseline_adaptive(w, inp, n_cpu)
+        else:
+            n_cpu = args.cpu_sample or (20_000 if w.order >= 7 else 100_000)
+            log(f"[bench] oracle on {n_cpu} points (host cores)")
+            cpu = cpu_baseline(w, inp, n_cpu, grad_mode)
         log(f"[bench] oracle: {cpu['value']:.3e} points/s")
 
     # HBM traffic of the M2L launch from the committed rocprofv3 counters, only while the kernel
@@ -249,7 +336,9 @@ def main():
                    "m2l_prec": prec, "m2l_variant": variant},
         "m2l_gflops": achieved * 1e3,
         "rel_l2_err_vs_direct": err,
-        "passes_ms_per_call": {k: v / calls for k, v in passes.items()},
+        "passes_ms_per_call": per,
+        "passes_achieved": achieved_bw,
+        "passes_work": work,
         "tree_build_ms": build_ms,
         "precompute_s": st["precompute_seconds"],
         "m2l_pairs_nonempty": st["pairs_nonempty"],
@@ -260,6 +349,10 @@ def main():
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)"},
         "cpu_baseline": cpu,
     }
+    if adaptive:
+        line["config"]["depth"] = tree_info["n_levels"] - 1
+        line["config"]["tree"] = f"adaptive, at most {w.max_leaf_points} points per leaf"
+        line["adaptive_tree"] = tree_info
     if grad_mode:
         line["metric"] = ("FMM points/sec of one forward + adjoint + position-gradient step (bbFMM, "
                           "symmetry-blocked M2L), with M2L TFLOP/s vs MFMA peak")

@@ -62,11 +62,13 @@ typedef enum {
  * near field) is FP64 in every mode. */
 typedef enum {
   BBFMM_M2L_FP64 = 0,     /* FP64 MFMA */
-  BBFMM_M2L_FP32 = 1,     /* FP32 operands and FP32 MFMA accumulation within one transfer
-                             vector's product (full rank: within 32-wide k chunks), added into
-                             FP64 accumulators */
+  BBFMM_M2L_FP32 = 1,     /* FP32 operands and FP32 MFMA accumulation, added into FP64
+                             accumulators after each transfer vector (compressed operators) or
+                             after at most 64 products (full rank) */
   BBFMM_M2L_SPLIT32 = 2   /* hi/lo FP32 split of operator and multipoles, three FP32 MFMA
-                             products (hi*hi + hi*lo + lo*hi), accumulated as FP32 */
+                             products (hi*hi + hi*lo + lo*hi), accumulated as FP32 and added
+                             into FP64 after each transfer vector (compressed) or k chunk of 32
+                             (full rank) */
 } bbfmm_m2l_prec;
 
 typedef struct {

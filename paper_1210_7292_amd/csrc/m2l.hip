@@ -26,6 +26,8 @@
 // MFMA v_mfma_{f64,f32}_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]. It holds
 // D[row][l%16], v = 0..3, with row = l/16 + 4v for f64 and row = 4(l/16) + v for f32 (the two
 // output layouts differ on gfx950).
+#include <type_traits>
+
 #include "internal.h"
 
 namespace bbfmm {
@@ -164,99 +166,197 @@ __device__ inline void store_tile(const M2LArgs& a, const BlockPos& bp, const Co
 }
 
 // ------------------------------------------------------------------------ full-rank M2L ----
-template <int L, int KC, int PREC, bool AD>
-__global__ __launch_bounds__(kThreads) void m2l_full_kernel(M2LArgs a) {
+// Adaptive trees: bit e of the mask is set when some column of the block has a source at table
+// entry e; transfer vectors without one are skipped (the sources of adaptive trees are sparse).
+constexpr int kMaskWords = (kFarPerOctant + 31) / 32;
+// FP32 mode of the full-rank kernel: products summed in FP32 between additions into FP64 (the
+// split mode adds every k chunk)
+constexpr int kFlushTerms = 64;
+
+template <bool AD>
+__device__ inline void block_mask(const M2LArgs& a, const BlockPos& bp, unsigned* mask, int tid, int nt) {
+  if (!AD) return;
+  for (int w = tid; w < kMaskWords; w += nt) mask[w] = 0u;
+  __syncthreads();
+  const int ncol = a.cols;
+  for (int x = tid; x < ncol * kFarPerOctant; x += nt) {
+    const int cl = x / kFarPerOctant, e = x - cl * kFarPerOctant;
+    const int col = bp.tile * a.cols + cl;
+    const int P = col / a.nrhs;
+    if (P >= bp.lv.npar) continue;
+    if (a.vsrc[(long long)(bp.lv.tgt_off + P) * kFarPerOctant + e] >= 0) atomicOr(&mask[e >> 5], 1u << (e & 31));
+  }
+  __syncthreads();
+}
+
+template <bool AD>
+__device__ inline bool entry_active(const unsigned* mask, int e) {
+  return !AD || ((mask[e >> 5] >> (e & 31)) & 1u);
+}
+
+// Workgroup of 4 RS waves, 64 columns: wave w owns columns 16 (w % 4) .. +16 and row blocks
+// (w / 4) MB/RS .. +MB/RS of the l^3 x 64 output tile. K_p is staged in LDS in column chunks of
+// KC; within a chunk the transfer vectors of representative p run in turn, each lane's B values
+// for the next one loaded before the current one's MFMAs.
+template <int L, int KC, int PREC, bool AD, int RS>
+__global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
   using A = Arith<PREC>;
   using T = typename A::T;
   using V = typename A::V;
+  constexpr int NT = kThreads * RS;
   constexpr int NN = L * L * L;
   constexpr int NP = (NN + 15) / 16 * 16;
   constexpr int MB = NP / 16;
+  static_assert(MB % RS == 0, "row blocks split evenly over the waves of a column group");
+  constexpr int MBW = MB / RS;
   constexpr int NCH = (NN + KC - 1) / KC;
   constexpr int LDK = KC + 1;              // odd stride in elements: rows hit distinct banks
+  constexpr int KS = KC / 4;
   constexpr bool SPLIT = PREC == 2;
   __shared__ T khi[(NN + 1) * LDK];
   __shared__ T klo[SPLIT ? (NN + 1) * LDK : 1];
+  constexpr bool SIGLDS =
+      ((SPLIT ? 2 : 1) * (NN + 1) * LDK * (int)sizeof(T) + 2 * kNumPerms * NP * 2) <= 150 * 1024;
+  __shared__ short sgs[SIGLDS ? kNumPerms * NP : 1];
+  __shared__ short sis[SIGLDS ? kNumPerms * NP : 1];
+  __shared__ unsigned amask[kMaskWords];
 
   BlockPos bp;
   if (!locate<AD>(a, bp)) return;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int j = lane % 16, kq = lane / 16;
-  const Column col = column_of<AD>(a, bp, 16 * wave + j);
+  const int cw = wave % kWaves, mb0 = (wave / kWaves) * MBW;
+  const Column col = column_of<AD>(a, bp, 16 * cw + j);
   const int set = bp.lv.set;
+  const int* tab = a.tab + bp.oct * kFarPerOctant;
 
-  V acc[MB];
-  f64x4 acc64[MB];
+  if (SIGLDS)
+    for (int x = tid; x < kNumPerms * NP; x += NT) {
+      sgs[x] = a.sig[x];
+      sis[x] = a.siginv[x];
+    }
+  block_mask<AD>(a, bp, amask, tid, NT);
+  if (!AD) __syncthreads();
+  const short* sgb = SIGLDS ? sgs : a.sig;
+  const short* sib = SIGLDS ? sis : a.siginv;
+
+  V acc[MBW];
+  f64x4 acc64[MBW];
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-    acc[mb] = V{0, 0, 0, 0};
-    acc64[mb] = f64x4{0, 0, 0, 0};
+  for (int m = 0; m < MBW; ++m) {
+    acc[m] = V{0, 0, 0, 0};
+    acc64[m] = f64x4{0, 0, 0, 0};
   }
+
+  // B operand of entry e, chunk ch: w[sigma^-1(k)] for the chunk's natural columns k, held in
+  // the MFMA type (FP64 for the split mode, which needs the low part)
+  using BT = typename std::conditional<PREC == 1, float, double>::type;
+  auto load_b = [&](int e, int ch, BT (&bv)[KS]) {
+    const int ent = tab[e];
+    const double* src = source_of<AD>(a, bp, col, e, ent, NN);
+    const short* si = sib + (ent >> 13) * NP;
+#pragma unroll
+    for (int s2 = 0; s2 < KS; ++s2) {
+      const int k = ch * KC + 4 * s2 + kq;
+      bv[s2] = (BT)((src != nullptr && k < NN) ? src[(long long)si[k] * a.nrhs] : 0.0);
+    }
+  };
+  auto next_active = [&](int e, int g1) {
+    while (e < g1 && !entry_active<AD>(amask, e)) ++e;
+    return e;
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[m][v] += (double)acc[m][v];
+      acc[m] = V{0, 0, 0, 0};
+    }
+  };
+  int pend = 0;      // products held in the FP32 accumulators (FP32 modes)
 
   for (int p = 0; p < kNumSym; ++p) {
     const int g0 = a.grp[bp.oct * 17 + p], g1 = a.grp[bp.oct * 17 + p + 1];
-    if (g0 == g1) continue;
+    const int e0 = next_active(g0, g1);
+    if (e0 >= g1) continue;
     const long long off = a.op_off[(set * kNumSym + p) * 2];
     const T* Kp = static_cast<const T*>(a.ops_hi) + off;
     const T* Kl = SPLIT ? static_cast<const T*>(a.ops_lo) + off : nullptr;
     for (int ch = 0; ch < NCH; ++ch) {
       __syncthreads();
-      for (int e = tid; e < (NN + 1) * KC; e += kThreads) {
-        const int row = e / KC, cc = e - row * KC, k = ch * KC + cc;
+      for (int x = tid; x < (NN + 1) * KC; x += NT) {
+        const int row = x / KC, cc = x - row * KC, k = ch * KC + cc;
         const bool in = row < NN && k < NN;
         khi[row * LDK + cc] = in ? Kp[(long long)row * NN + k] : T(0);
         if (SPLIT) klo[row * LDK + cc] = in ? Kl[(long long)row * NN + k] : T(0);
       }
       __syncthreads();
-      for (int e = g0; e < g1; ++e) {
-        const int ent = a.tab[bp.oct * kFarPerOctant + e];
-        const int perm = ent >> 13;
-        const double* src = source_of<AD>(a, bp, col, e, ent, NN);
-        const short* sg = a.sig + perm * NP;
-        const short* si = a.siginv + perm * NP;
-        int srow[MB];
+      BT bv[KS], bn[KS];
+      int e = e0;
+      load_b(e, ch, bv);
+      while (e < g1) {
+        const int en = next_active(e + 1, g1);
+        if (en < g1) load_b(en, ch, bn);
+        const short* sg = sgb + (tab[e] >> 13) * NP;
+        // LDS offsets of (sigma(i), kq) for this lane's rows, two 16-bit values per register; the
+        // k step 4 s2 then folds into the LDS reads' immediate offsets
+        constexpr int NPK = (MBW + 1) / 2;
+        static_assert((NN + 1) * LDK < 65536, "row offsets fit 16 bits");
+        unsigned srow2[NPK];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) srow[mb] = sg[16 * mb + j] * LDK;
-        // B operand: w[sigma^-1(k)] for the chunk's natural columns k.
-        double bv[KC / 4];
-#pragma unroll
-        for (int s = 0; s < KC / 4; ++s) {
-          const int k = ch * KC + 4 * s + kq;
-          bv[s] = (src != nullptr && k < NN) ? src[(long long)si[k] * a.nrhs] : 0.0;
+        for (int m2 = 0; m2 < NPK; ++m2) {
+          const unsigned lo = (unsigned)(sg[16 * (mb0 + 2 * m2) + j] * LDK + kq);
+          const unsigned hi =
+              (2 * m2 + 1 < MBW) ? (unsigned)(sg[16 * (mb0 + 2 * m2 + 1) + j] * LDK + kq) : 0u;
+          srow2[m2] = lo | (hi << 16);
         }
+        auto srow = [&](int m) -> int { return (int)((m & 1) ? (srow2[m >> 1] >> 16) : (srow2[m >> 1] & 0xffffu)); };
 #pragma unroll
-        for (int s = 0; s < KC / 4; ++s) {
-          const int kl = 4 * s + kq;
+        for (int s2 = 0; s2 < KS; ++s2) {
+          const int kl = 4 * s2;
           if (!SPLIT) {
-            const T b = (T)bv[s];
+            const T b = (T)bv[s2];
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb] = A::mfma(khi[srow[mb] + kl], b, acc[mb]);
+            for (int m = 0; m < MBW; ++m) acc[m] = A::mfma(khi[srow(m) + kl], b, acc[m]);
           } else {
-            const T bh = (T)bv[s];
-            const T bl = (T)(bv[s] - (double)bh);
+            const T bh = (T)bv[s2];
+            const T bl = (T)(bv[s2] - (double)bh);
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-              const T ah = khi[srow[mb] + kl], al = klo[srow[mb] + kl];
-              acc[mb] = A::mfma(ah, bh, acc[mb]);
-              acc[mb] = A::mfma(ah, bl, acc[mb]);
-              acc[mb] = A::mfma(al, bh, acc[mb]);
+            for (int m = 0; m < MBW; ++m) {
+              const T ah = khi[srow(m) + kl], al = klo[srow(m) + kl];
+              acc[m] = A::mfma(ah, bh, acc[m]);
+              acc[m] = A::mfma(ah, bl, acc[m]);
+              acc[m] = A::mfma(al, bh, acc[m]);
             }
           }
         }
-        // FP32 modes: each (transfer vector, k chunk) product of KC terms is accumulated in FP32
-        // by the MFMA and then added into FP64
+        // FP32 modes: the MFMA accumulates at most kFlushTerms products (of one or more
+        // transfer vectors and k chunks) in FP32 before they are added into FP64
         if (PREC != 0) {
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc64[mb][v] += (double)acc[mb][v];
-            acc[mb] = V{0, 0, 0, 0};
+          pend += KC;
+          if (pend >= (SPLIT ? KC : kFlushTerms)) {
+            flush();
+            pend = 0;
           }
         }
+#pragma unroll
+        for (int s2 = 0; s2 < KS; ++s2) bv[s2] = bn[s2];
+        e = en;
       }
     }
   }
-  store_tile<L, MB, PREC, V>(a, bp, col, kq, acc, acc64, PREC != 0);
+  if (PREC != 0 && pend > 0) flush();
+  // output rows of this wave's row blocks
+  if (!col.valid) return;
+  const double sc = bp.lv.scale;
+  double* dst = bp.lv.F + ((long long)col.target * NN) * a.nrhs + col.rhs;
+#pragma unroll
+  for (int m = 0; m < MBW; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * (mb0 + m) + out_row<PREC>(kq, v);
+      if (i < NN) dst[(long long)i * a.nrhs] = sc * (PREC != 0 ? acc64[m][v] : (double)acc[m][v]);
+    }
 }
 
 // ----------------------------------------------------------------------- compressed M2L ----
@@ -467,7 +567,12 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
   store_tile<L, MB, PREC, V>(a, bp, col, kq, acc, acc64, PREC != 0);
 }
 
-template <int L> constexpr int full_kc() { return L <= 2 ? 8 : 32; }
+// K_p column chunk of the full-rank kernel; order 8 in FP32 takes 16 so that the permutation
+// tables fit in LDS beside the chunk
+template <int L, int PREC> constexpr int full_kc() { return L <= 2 ? 8 : (L == 8 && PREC == 1) ? 16 : 32; }
+// waves per column group of the full-rank kernel: row blocks split so that the accumulators of
+// the largest orders fit the register file with two waves per SIMD
+template <int L> constexpr int full_rs() { return L >= 7 ? 2 : 1; }
 template <int L> constexpr int rank_limit() { return L <= 6 ? 32 : 16; }
 constexpr int kLowrankWaves = 8;
 
@@ -503,7 +608,9 @@ hipError_t launch_ld(bool lowrank, M2LArgs a, hipStream_t s) {
   } else {
     if (!AD) tile(a, kCols);
     const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
-    hipLaunchKernelGGL((m2l_full_kernel<L, full_kc<L>(), PREC, AD>), dim3(grid), dim3(kThreads), 0, s, a);
+    constexpr int RS = full_rs<L>();
+    hipLaunchKernelGGL((m2l_full_kernel<L, full_kc<L, PREC>(), PREC, AD, RS>), dim3(grid), dim3(kThreads * RS), 0, s,
+                       a);
   }
   return hipGetLastError();
 }
