@@ -165,6 +165,8 @@ __device__ inline void store_tile(const M2LArgs& a, const BlockPos& bp, const Co
     }
 }
 
+typedef __attribute__((address_space(1))) const double gdouble;
+
 // ------------------------------------------------------------------------ full-rank M2L ----
 // Adaptive trees: bit e of the mask is set when some column of the block has a source at table
 // entry e; transfer vectors without one are skipped (the sources of adaptive trees are sparse).
@@ -173,18 +175,24 @@ constexpr int kMaskWords = (kFarPerOctant + 31) / 32;
 // split mode adds every k chunk)
 constexpr int kFlushTerms = 64;
 
+// Targets of one full-rank block whose source nodes are cached in LDS (adaptive trees with at
+// least 4 right-hand sides; fewer fall back to the global lists).
+constexpr int kSrcTargets = 17;
+
 template <bool AD>
-__device__ inline void block_mask(const M2LArgs& a, const BlockPos& bp, unsigned* mask, int tid, int nt) {
+__device__ inline void block_mask(const M2LArgs& a, const BlockPos& bp, unsigned* mask, int* ssrc, int tid,
+                                  int nt) {
   if (!AD) return;
   for (int w = tid; w < kMaskWords; w += nt) mask[w] = 0u;
   __syncthreads();
-  const int ncol = a.cols;
-  for (int x = tid; x < ncol * kFarPerOctant; x += nt) {
-    const int cl = x / kFarPerOctant, e = x - cl * kFarPerOctant;
-    const int col = bp.tile * a.cols + cl;
-    const int P = col / a.nrhs;
-    if (P >= bp.lv.npar) continue;
-    if (a.vsrc[(long long)(bp.lv.tgt_off + P) * kFarPerOctant + e] >= 0) atomicOr(&mask[e >> 5], 1u << (e & 31));
+  const int P0 = bp.tile * a.cols / a.nrhs;
+  const int P1 = min((bp.tile * a.cols + a.cols - 1) / a.nrhs, bp.lv.npar - 1);
+  const bool cache = P1 - P0 < kSrcTargets;
+  for (int x = tid; x < (P1 - P0 + 1) * kFarPerOctant; x += nt) {
+    const int lt = x / kFarPerOctant, e = x - lt * kFarPerOctant;
+    const int y = a.vsrc[(long long)(bp.lv.tgt_off + P0 + lt) * kFarPerOctant + e];
+    if (cache) ssrc[x] = y;
+    if (y >= 0) atomicOr(&mask[e >> 5], 1u << (e & 31));
   }
   __syncthreads();
 }
@@ -193,6 +201,43 @@ template <bool AD>
 __device__ inline bool entry_active(const unsigned* mask, int e) {
   return !AD || ((mask[e >> 5] >> (e & 31)) & 1u);
 }
+
+// LDS layout of a staged K_p chunk. Row r = a0 + l a1 + l^2 a2 starts at s0 a0 + s1 a1 + s2 a2
+// and holds the chunk's KC columns; row l^3 (the zero row that padded sigma entries point to)
+// follows the last one. The 16 lanes of an A-operand read fetch rows sigma(16 m + j), whose
+// indices differ by multiples of 1, l and l^2 in an order that depends on sigma; with the plain
+// stride KC + 1 those rows fall into few LDS banks (up to 5-6 lanes per bank on average at order
+// 8). The strides below were chosen by counting, over all 48 permutations and row blocks, the
+// lanes per bank for 32- and 64-bank LDS (8-byte elements in bank pairs).
+template <int L, int KC, int ESZ> struct RowLayout {
+  static constexpr int S[3] = {KC + 1, L * (KC + 1), L * L * (KC + 1)};
+};
+template <> struct RowLayout<3, 32, 4> { static constexpr int S[3] = {34, 107, 337}; };
+template <> struct RowLayout<3, 32, 8> { static constexpr int S[3] = {34, 105, 323}; };
+template <> struct RowLayout<4, 32, 4> { static constexpr int S[3] = {34, 136, 550}; };
+template <> struct RowLayout<4, 32, 8> { static constexpr int S[3] = {33, 132, 531}; };
+template <> struct RowLayout<5, 32, 4> { static constexpr int S[3] = {34, 180, 914}; };
+template <> struct RowLayout<5, 32, 8> { static constexpr int S[3] = {34, 185, 933}; };
+template <> struct RowLayout<6, 32, 4> { static constexpr int S[3] = {34, 206, 1236}; };
+template <> struct RowLayout<6, 32, 8> { static constexpr int S[3] = {38, 241, 1449}; };
+template <> struct RowLayout<7, 32, 4> { static constexpr int S[3] = {34, 238, 1676}; };
+template <> struct RowLayout<7, 32, 8> { static constexpr int S[3] = {38, 273, 1911}; };
+template <> struct RowLayout<8, 16, 4> { static constexpr int S[3] = {18, 152, 1220}; };
+template <> struct RowLayout<8, 32, 4> { static constexpr int S[3] = {34, 276, 2216}; };
+template <> struct RowLayout<8, 32, 8> { static constexpr int S[3] = {33, 266, 2132}; };
+
+template <int L, int KC, int ESZ>
+struct KLayout {
+  static constexpr int S0 = RowLayout<L, KC, ESZ>::S[0], S1 = RowLayout<L, KC, ESZ>::S[1],
+                       S2 = RowLayout<L, KC, ESZ>::S[2];
+  static constexpr int ZERO = (L - 1) * (S0 + S1 + S2) + S0;   // offset of the zero row
+  static constexpr int SIZE = ZERO + KC;
+  static_assert(S0 >= KC && S1 >= (L - 1) * S0 + KC && S2 >= (L - 1) * S1 + (L - 1) * S0 + KC,
+                "rows do not overlap");
+  static __host__ __device__ constexpr int off(int r) {
+    return r >= L * L * L ? ZERO : S0 * (r % L) + S1 * ((r / L) % L) + S2 * (r / (L * L));
+  }
+};
 
 // Workgroup of 4 RS waves, 64 columns: wave w owns columns 16 (w % 4) .. +16 and row blocks
 // (w / 4) MB/RS .. +MB/RS of the l^3 x 64 output tile. K_p is staged in LDS in column chunks of
@@ -210,32 +255,37 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
   static_assert(MB % RS == 0, "row blocks split evenly over the waves of a column group");
   constexpr int MBW = MB / RS;
   constexpr int NCH = (NN + KC - 1) / KC;
-  constexpr int LDK = KC + 1;              // odd stride in elements: rows hit distinct banks
+  using KL = KLayout<L, KC, (int)sizeof(T)>;
   constexpr int KS = KC / 4;
   constexpr bool SPLIT = PREC == 2;
-  __shared__ T khi[(NN + 1) * LDK];
-  __shared__ T klo[SPLIT ? (NN + 1) * LDK : 1];
+  __shared__ T khi[KL::SIZE];
+  __shared__ T klo[SPLIT ? KL::SIZE : 1];
+  // sigma tables in LDS when they fit; the row table then holds LDS row offsets
   constexpr bool SIGLDS =
-      ((SPLIT ? 2 : 1) * (NN + 1) * LDK * (int)sizeof(T) + 2 * kNumPerms * NP * 2) <= 150 * 1024;
+      ((SPLIT ? 2 : 1) * KL::SIZE * (int)sizeof(T) + 2 * kNumPerms * NP * 2) <= 150 * 1024;
   __shared__ short sgs[SIGLDS ? kNumPerms * NP : 1];
   __shared__ short sis[SIGLDS ? kNumPerms * NP : 1];
   __shared__ unsigned amask[kMaskWords];
+  __shared__ short roff_tab[NN + 1];       // LDS offset of each K_p row
+  __shared__ int ssrc[AD ? kSrcTargets * kFarPerOctant : 1];
+  __shared__ int stab[kFarPerOctant];      // the octant's table entries
 
   BlockPos bp;
   if (!locate<AD>(a, bp)) return;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int j = lane % 16, kq = lane / 16;
   const int cw = wave % kWaves, mb0 = (wave / kWaves) * MBW;
+  for (int r = tid; r <= NN; r += NT) roff_tab[r] = (short)KL::off(r);
+  for (int e = tid; e < kFarPerOctant; e += NT) stab[e] = a.tab[bp.oct * kFarPerOctant + e];
   const Column col = column_of<AD>(a, bp, 16 * cw + j);
   const int set = bp.lv.set;
-  const int* tab = a.tab + bp.oct * kFarPerOctant;
 
   if (SIGLDS)
     for (int x = tid; x < kNumPerms * NP; x += NT) {
-      sgs[x] = a.sig[x];
+      sgs[x] = (short)KL::off(a.sig[x]);
       sis[x] = a.siginv[x];
     }
-  block_mask<AD>(a, bp, amask, tid, NT);
+  block_mask<AD>(a, bp, amask, ssrc, tid, NT);
   if (!AD) __syncthreads();
   const short* sgb = SIGLDS ? sgs : a.sig;
   const short* sib = SIGLDS ? sis : a.siginv;
@@ -251,14 +301,29 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
   // B operand of entry e, chunk ch: w[sigma^-1(k)] for the chunk's natural columns k, held in
   // the MFMA type (FP64 for the split mode, which needs the low part)
   using BT = typename std::conditional<PREC == 1, float, double>::type;
-  auto load_b = [&](int e, int ch, BT (&bv)[KS]) {
-    const int ent = tab[e];
-    const double* src = source_of<AD>(a, bp, col, e, ent, NN);
+  // Missing sources and invalid columns read a zero buffer, and k >= l^3 reads entry l^3 - 1
+  // (its product meets the zero columns of the staged chunk), so the loads need no branches.
+  const int P0 = bp.tile * a.cols / a.nrhs;
+  const bool src_lds = AD && (min((bp.tile * a.cols + a.cols - 1) / a.nrhs, bp.lv.npar - 1) - P0 < kSrcTargets);
+  gdouble* zero_src = (gdouble*)a.zeros + col.rhs;
+  auto source = [&](int e, int ent) -> gdouble* {
+    if (AD && src_lds) {
+      const int y = col.valid ? ssrc[(col.slot - bp.lv.tgt_off - P0) * kFarPerOctant + e] : -1;
+      return y >= 0 ? (gdouble*)(bp.lv.W + ((long long)y * NN) * a.nrhs + col.rhs) : zero_src;
+    }
+    const double* sp = source_of<AD>(a, bp, col, e, ent, NN);
+    return sp ? (gdouble*)sp : zero_src;
+  };
+  // raw FP64 values: a conversion at load time would wait for the loads there
+  auto load_b = [&](int e, int ch, double (&bv)[KS]) {
+    const int ent = stab[e];
+    gdouble* src = source(e, ent);
     const short* si = sib + (ent >> 13) * NP;
 #pragma unroll
     for (int s2 = 0; s2 < KS; ++s2) {
-      const int k = ch * KC + 4 * s2 + kq;
-      bv[s2] = (BT)((src != nullptr && k < NN) ? src[(long long)si[k] * a.nrhs] : 0.0);
+      int k = ch * KC + 4 * s2 + kq;
+      k = k < NN ? k : NN - 1;
+      bv[s2] = src[(long long)si[k] * a.nrhs];
     }
   };
   auto next_active = [&](int e, int g1) {
@@ -284,30 +349,60 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
     const T* Kl = SPLIT ? static_cast<const T*>(a.ops_lo) + off : nullptr;
     for (int ch = 0; ch < NCH; ++ch) {
       __syncthreads();
-      for (int x = tid; x < (NN + 1) * KC; x += NT) {
-        const int row = x / KC, cc = x - row * KC, k = ch * KC + cc;
-        const bool in = row < NN && k < NN;
-        khi[row * LDK + cc] = in ? Kp[(long long)row * NN + k] : T(0);
-        if (SPLIT) klo[row * LDK + cc] = in ? Kl[(long long)row * NN + k] : T(0);
+      // loads in batches of SB issued back to back, then their LDS stores: a few memory
+      // latencies per chunk rather than one per element
+      constexpr int PER = ((NN + 1) * KC + NT - 1) / NT;
+      constexpr int SB = 4;
+#pragma unroll 1
+      for (int u0 = 0; u0 < PER; u0 += SB) {
+        T th[SB], tl[SPLIT ? SB : 1];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          const int x = tid + (u0 + u) * NT;
+          const int row = x / KC, cc = x - row * KC, k = ch * KC + cc;
+          const bool in = row < NN && k < NN;
+          const long long g = in ? (long long)row * NN + k : 0;
+          th[u] = Kp[g];
+          if (SPLIT) tl[u] = Kl[g];
+          if (!in) {
+            th[u] = T(0);
+            if (SPLIT) tl[u] = T(0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          const int x = tid + (u0 + u) * NT;
+          const int row = x / KC, cc = x - row * KC;
+          if (row <= NN) {
+            const int o = roff_tab[row] + cc;
+            khi[o] = th[u];
+            if (SPLIT) klo[o] = tl[u];
+          }
+        }
       }
       __syncthreads();
-      BT bv[KS], bn[KS];
+      BT bv[KS];
+      double bn[KS];
       int e = e0;
-      load_b(e, ch, bv);
+      load_b(e, ch, bn);
+#pragma unroll
+      for (int s2 = 0; s2 < KS; ++s2) bv[s2] = (BT)bn[s2];
       while (e < g1) {
         const int en = next_active(e + 1, g1);
         if (en < g1) load_b(en, ch, bn);
-        const short* sg = sgb + (tab[e] >> 13) * NP;
+        const short* sg = sgb + (stab[e] >> 13) * NP;
         // LDS offsets of (sigma(i), kq) for this lane's rows, two 16-bit values per register; the
         // k step 4 s2 then folds into the LDS reads' immediate offsets
         constexpr int NPK = (MBW + 1) / 2;
-        static_assert((NN + 1) * LDK < 65536, "row offsets fit 16 bits");
+        static_assert(KL::SIZE < 32768, "row offsets fit 16 bits");
+        auto roff = [&](int i) -> unsigned {
+          return (unsigned)((SIGLDS ? (int)sg[i] : (int)roff_tab[sg[i]]) + kq);
+        };
         unsigned srow2[NPK];
 #pragma unroll
         for (int m2 = 0; m2 < NPK; ++m2) {
-          const unsigned lo = (unsigned)(sg[16 * (mb0 + 2 * m2) + j] * LDK + kq);
-          const unsigned hi =
-              (2 * m2 + 1 < MBW) ? (unsigned)(sg[16 * (mb0 + 2 * m2 + 1) + j] * LDK + kq) : 0u;
+          const unsigned lo = roff(16 * (mb0 + 2 * m2) + j);
+          const unsigned hi = (2 * m2 + 1 < MBW) ? roff(16 * (mb0 + 2 * m2 + 1) + j) : 0u;
           srow2[m2] = lo | (hi << 16);
         }
         auto srow = [&](int m) -> int { return (int)((m & 1) ? (srow2[m >> 1] >> 16) : (srow2[m >> 1] & 0xffffu)); };
@@ -340,7 +435,7 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
           }
         }
 #pragma unroll
-        for (int s2 = 0; s2 < KS; ++s2) bv[s2] = bn[s2];
+        for (int s2 = 0; s2 < KS; ++s2) bv[s2] = (BT)bn[s2];
         e = en;
       }
     }
@@ -371,8 +466,6 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
 //           order, so nothing moves between the two products.
 // Invalid columns and sources outside the level read a zero buffer; k >= l^3 reads a real entry
 // that meets the zero row l^3 of V in LDS. The loads therefore need no branches.
-typedef __attribute__((address_space(1))) const double gdouble;
-
 template <int L, int RMAX, int PREC, int W8, bool ONE_RHS>
 struct Lowrank {
   using A = Arith<PREC>;
