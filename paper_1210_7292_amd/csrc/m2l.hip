@@ -568,6 +568,10 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
   // permutation tables in LDS when they fit beside the factors
   constexpr bool SIGLDS = (2 * (SPLIT ? 2 : 1) * (NN + 1) * LD * (int)sizeof(T) + kNumPerms * NP * 2) <= 160 * 1024;
   __shared__ short sgs[SIGLDS ? kNumPerms * NP : 1];
+  // the octant's table entries and the level's ranks and factor offsets, read once per block
+  __shared__ int stab[kFarPerOctant];
+  __shared__ int srank[kNumSym];
+  __shared__ long long soff[2 * kNumSym];
 
   BlockPos bp;
   if (!locate<AD>(a, bp)) return;
@@ -576,11 +580,15 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
   const Column col = column_of<AD>(a, bp, 16 * wave + j);
   const int set = bp.lv.set;
   const int nrhs = a.nrhs;
-  const int* tab = a.tab + bp.oct * kFarPerOctant;
+  const int* tab = stab;
   gdouble* zero_src = (gdouble*)a.zeros + col.rhs;
 
   if (SIGLDS)
     for (int e = tid; e < kNumPerms * NP; e += NT) sgs[e] = a.sig[e];
+  for (int e = tid; e < kFarPerOctant; e += NT) stab[e] = a.tab[bp.oct * kFarPerOctant + e];
+  for (int q = tid; q < kNumSym; q += NT) srank[q] = a.op_rank[set * kNumSym + q];
+  for (int q = tid; q < 2 * kNumSym; q += NT) soff[q] = a.op_off[set * kNumSym * 2 + q];
+  __syncthreads();
   const short* sgbase = SIGLDS ? sgs : a.sig;
 
   V acc[MB];
@@ -606,23 +614,52 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
     if (p != cur_p) {
       __syncthreads();
       cur_p = p;
-      r = a.op_rank[set * kNumSym + p];
+      r = srank[p];
       zb = (r + 15) / 16;
       const int rv = 16 * zb, ru = (r + 3) / 4 * 4;
-      const long long offu = a.op_off[(set * kNumSym + p) * 2];
-      const long long offv = a.op_off[(set * kNumSym + p) * 2 + 1];
+      const long long offu = soff[2 * p];
+      const long long offv = soff[2 * p + 1];
       const T* Ug = static_cast<const T*>(a.ops_hi) + offu;   // [NN][ru]
       const T* Vg = static_cast<const T*>(a.ops_hi) + offv;   // [NN][rv]
       const T* Ul = SPLIT ? static_cast<const T*>(a.ops_lo) + offu : nullptr;
       const T* Vl = SPLIT ? static_cast<const T*>(a.ops_lo) + offv : nullptr;
-      for (int x = tid; x < (NN + 1) * rv; x += NT) {
-        const int row = x / rv, cc = x - row * rv;
-        const bool in = row < NN;
-        vhi[row * LD + cc] = in ? Vg[(long long)row * rv + cc] : T(0);
-        uhi[row * LD + cc] = (in && cc < ru) ? Ug[(long long)row * ru + cc] : T(0);
-        if (SPLIT) {
-          vlo[row * LD + cc] = in ? Vl[(long long)row * rv + cc] : T(0);
-          ulo[row * LD + cc] = (in && cc < ru) ? Ul[(long long)row * ru + cc] : T(0);
+      // factor loads in batches of SB issued back to back, then their LDS stores
+      constexpr int SB = 4;
+      const int tot = (NN + 1) * rv;
+#pragma unroll 1
+      for (int x0 = tid; x0 < tot; x0 += SB * NT) {
+        T tv[SB], tu[SB], tvl[SPLIT ? SB : 1], tul[SPLIT ? SB : 1];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          const int x = x0 + u * NT;
+          const int row = x / rv, cc = x - row * rv;
+          const bool inv = x < tot && row < NN, inu = inv && cc < ru;
+          const long long gv = inv ? (long long)row * rv + cc : 0, gu = inu ? (long long)row * ru + cc : 0;
+          tv[u] = Vg[gv];
+          tu[u] = Ug[gu];
+          if (SPLIT) {
+            tvl[u] = Vl[gv];
+            tul[u] = Ul[gu];
+          }
+          if (!inv) tv[u] = T(0);
+          if (!inu) tu[u] = T(0);
+          if (SPLIT) {
+            if (!inv) tvl[u] = T(0);
+            if (!inu) tul[u] = T(0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          const int x = x0 + u * NT;
+          if (x < tot) {
+            const int row = x / rv, cc = x - row * rv;
+            vhi[row * LD + cc] = tv[u];
+            uhi[row * LD + cc] = tu[u];
+            if (SPLIT) {
+              vlo[row * LD + cc] = tvl[u];
+              ulo[row * LD + cc] = tul[u];
+            }
+          }
         }
       }
       __syncthreads();
