@@ -176,8 +176,9 @@ M2LArgs adaptive_m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double
   a.zeros = p->d_zeros;
   a.segs = p->d_segs;
   a.nsegs = (int)p->h_segs.size();
-  a.tgt = t->d_m2l_tgt;
-  a.vsrc = t->d_vsrc;
+  a.tgt = p->m2l_tgt;
+  a.vsrc = p->m2l_vsrc;
+  (void)t;
   return a;
 }
 
@@ -264,8 +265,17 @@ bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, i
     for (int l = d - 1; l >= 2; --l)
       BBFMM_HIP_TRY(launch_m2m(g, l, W + p->level_off[l + 1] * nrhs, W + p->level_off[l] * nrhs, nrhs, s));
     BBFMM_HIP_TRY(mark(p, kM2M, s));
-    const M2LArgs a = m2l_args(p, nrhs, W, F, -1);
-    BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, s));
+    if (p->sparse_m2l) {
+      // only targets holding points are computed: the locals of empty cells start at zero
+      bbfmm_status st2 = adaptive_segments(p, nrhs, s);
+      if (st2 != BBFMM_OK) return st2;
+      BBFMM_HIP_TRY(launch_fill_zero(F, p->exp_elems * nrhs, s));
+      const M2LArgs a = adaptive_m2l_args(p, nrhs, W, F);
+      BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, s));
+    } else {
+      const M2LArgs a = m2l_args(p, nrhs, W, F, -1);
+      BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, s));
+    }
     BBFMM_HIP_TRY(mark(p, kM2L, s));
     for (int l = 3; l <= d; ++l)
       BBFMM_HIP_TRY(launch_l2l(g, l - 1, F + p->level_off[l - 1] * nrhs, F + p->level_off[l] * nrhs, nrhs, s));
@@ -344,6 +354,69 @@ hipError_t upload_topology(bbfmm_tree* t, long long* bytes) {
   if (e == hipSuccess) e = up(&t->d_m2l_tgt, T.m2l_tgt);
   if (e == hipSuccess) e = up(&t->d_vsrc, T.vsrc);
   return e;
+}
+
+// Segments of the full-rank M2L on a uniform tree restricted to cells that hold points: per
+// (level, octant) the non-empty target cells in Morton order, and their source lists (empty or
+// outside sources are absent, so blocks skip transfer vectors none of their targets needs).
+bbfmm_status build_sparse_uniform(bbfmm_plan* p, hipStream_t s, long long* bytes) {
+  const bbfmm_tree* t = p->tree;
+  const int d = t->depth, nn = p->nn;
+  std::vector<int> ls((1LL << (3 * d)) + 1);
+  BBFMM_HIP_TRY(hipMemcpyAsync(ls.data(), t->leaf_start, ls.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  BBFMM_HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int> tgt;
+  std::vector<long long> level_first(d + 2, 0);
+  for (int l = 2; l <= d; ++l) {
+    level_first[l] = (long long)tgt.size();
+    const int sh = 3 * (d - l);
+    const unsigned ncell = 1u << (3 * l);
+    const int node_base = (int)(p->level_off[l] / nn);
+    for (int o = 0; o < 8; ++o) {
+      const int b = (int)tgt.size();
+      for (unsigned c = (unsigned)o; c < ncell; c += 8)
+        if (ls[(size_t)(c + 1) << sh] > ls[(size_t)c << sh]) tgt.push_back(node_base + (int)c);
+      const int cnt = (int)tgt.size() - b;
+      if (cnt == 0) continue;
+      M2LLevel sg;
+      std::memset(&sg, 0, sizeof(sg));
+      sg.level = l;
+      sg.side = 1 << l;
+      sg.npar = cnt;
+      sg.set = p->set_of_level[l];
+      sg.scale = p->scale_of_level[l];
+      sg.oct = o;
+      sg.tgt_off = b;
+      p->h_segs.push_back(sg);
+    }
+  }
+  level_first[d + 1] = (long long)tgt.size();
+  if (tgt.empty() || (long long)tgt.size() * kFarPerOctant > 0x7fffffffLL) {   // keep the dense path
+    p->h_segs.clear();
+    return BBFMM_OK;
+  }
+  hipError_t e = dmalloc(&p->d_utgt, tgt.size(), bytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->d_utgt, tgt.data(), tgt.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = dmalloc(&p->d_uvsrc, tgt.size() * kFarPerOctant, bytes);
+  for (int l = 2; l <= d && e == hipSuccess; ++l) {
+    const int ntgt = (int)(level_first[l + 1] - level_first[l]);
+    e = launch_uniform_vsrc(t->leaf_start, d, l, p->d_utgt + level_first[l], ntgt, (int)(p->level_off[l] / nn),
+                            p->d_tab, p->d_uvsrc + level_first[l] * kFarPerOctant, s);
+  }
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_segs, p->h_segs.size() * sizeof(M2LLevel));
+  if (e == hipSuccess) *bytes += (long long)(p->h_segs.size() * sizeof(M2LLevel));
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    dfree(p->d_utgt); dfree(p->d_uvsrc); dfree(p->d_segs);
+    p->d_utgt = nullptr; p->d_uvsrc = nullptr; p->d_segs = nullptr;
+    p->h_segs.clear();
+    return fail(e == hipErrorOutOfMemory ? BBFMM_ENOMEM : BBFMM_EHIP,
+                std::string("M2L lists: ") + hipGetErrorString(e));
+  }
+  p->sparse_m2l = true;
+  p->m2l_tgt = p->d_utgt;
+  p->m2l_vsrc = p->d_uvsrc;
+  return BBFMM_OK;
 }
 
 // Device build of an adaptive tree: keys, stable radix sort, sorted coordinates, then one
@@ -723,6 +796,8 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
                   std::string("precompute upload: ") + hipGetErrorString(e));
     }
     p->exp_elems = (long long)T.key.size() * nn;
+    p->m2l_tgt = tree->d_m2l_tgt;
+    p->m2l_vsrc = tree->d_vsrc;
   } else {
     long long off = 0;
     for (int l = 2; l <= depth; ++l) {
@@ -730,6 +805,14 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
       off += (1LL << (3 * l)) * nn;
     }
     p->exp_elems = off;
+    // full-rank operators: M2L over the targets that hold points only
+    if (!p->lowrank && depth >= 2) {
+      const bbfmm_status st = build_sparse_uniform(p.get(), s, &bytes);
+      if (st != BBFMM_OK) {
+        destroy_partial();
+        return st;
+      }
+    }
   }
   p->op_bytes = bytes;
   p->precompute_seconds =
@@ -744,7 +827,7 @@ void bbfmm_plan_destroy(bbfmm_plan* p) {
   free_buffers(p);
   dfree(p->ops_hi); dfree(p->ops_lo); dfree(p->d_op_off); dfree(p->d_op_rank); dfree(p->d_tab);
   dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
-  dfree(p->d_zeros); dfree(p->d_segs);
+  dfree(p->d_zeros); dfree(p->d_segs); dfree(p->d_utgt); dfree(p->d_uvsrc);
   delete p;
 }
 
@@ -894,13 +977,20 @@ bbfmm_status bbfmm_plan_stats(const bbfmm_plan* p, bbfmm_stats* out) {
       const double r = p->ranks[set * kNumSym + q];
       out->m2l_flops_algorithmic += c * (p->eps > 0 ? 4.0 * nn * r : 2.0 * nn * nn);
     }
-    // issued: every tile runs every transfer vector of its octant
-    const long long npar = 1LL << (3 * (l - 1));
-    const double tiles_per_rhs = (double)npar / 64.0;   // per right-hand side
-    for (int q = 0; q < kNumSym; ++q) {
-      const int np_q = p->h_grp[q + 1] - p->h_grp[q];
-      const double per_t = m2l_issued_flops_per_t(p->order, p->lowrank, p->ranks[set * kNumSym + q]);
-      out->m2l_flops_issued += 8.0 * tiles_per_rhs * np_q * per_t;
+    // issued: every tile runs every transfer vector of its octant (upper bound for the segment
+    // path, which skips transfer vectors without a source in the tile)
+    for (int o = 0; o < 8; ++o) {
+      double targets = (double)(1LL << (3 * (l - 1)));
+      if (p->sparse_m2l) {
+        targets = 0;
+        for (const M2LLevel& sg : p->h_segs)
+          if (sg.level == l && sg.oct == o) targets += sg.npar;
+      }
+      for (int q = 0; q < kNumSym; ++q) {
+        const int np_q = p->h_grp[o * 17 + q + 1] - p->h_grp[o * 17 + q];
+        const double per_t = m2l_issued_flops_per_t(p->order, p->lowrank, p->ranks[set * kNumSym + q]);
+        out->m2l_flops_issued += targets / 64.0 * np_q * per_t;
+      }
     }
   }
   return BBFMM_OK;

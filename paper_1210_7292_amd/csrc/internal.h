@@ -118,6 +118,9 @@ int bbox_parts(long long n);
 hipError_t launch_leaf_keys(const double* pts, long long n, const double lo[3], double wleaf,
                             int depth, unsigned* keys, int* counts, hipStream_t s);
 hipError_t exclusive_scan(const int* in, int* out, long long n, hipStream_t s);  // out has n+1
+// Source lists (table entry -> source node or -1) of the given non-empty targets of a uniform level.
+hipError_t launch_uniform_vsrc(const int* leaf_start, int depth, int level, const int* tgt_node, int ntgt,
+                               int node_base, const int* tab, int* vsrc, hipStream_t s);
 hipError_t launch_scatter(const unsigned* keys, long long n, const int* leaf_start, int* cursor,
                           int* tmp, hipStream_t s);
 hipError_t launch_order(const double* pts, const unsigned* keys, long long n,
@@ -242,8 +245,15 @@ struct bbfmm_plan {
   int nrhs_cap = 0;
   long long level_off[bbfmm::kMaxLevels] = {0};   // element offsets (per rhs) into W / F
   long long exp_elems = 0;                         // per rhs (adaptive: nodes * l^3)
-  std::vector<bbfmm::M2LLevel> h_segs;             // adaptive M2L segments
+  std::vector<bbfmm::M2LLevel> h_segs;             // M2L segments (adaptive, or sparse uniform)
   bbfmm::M2LLevel* d_segs = nullptr;
+  // Segment-based M2L on a uniform tree (full rank): only targets that hold points, with source
+  // lists in which empty sources are absent
+  bool sparse_m2l = false;
+  int* d_utgt = nullptr;
+  int* d_uvsrc = nullptr;
+  const int* m2l_tgt = nullptr;                    // target nodes / source lists used by the
+  const int* m2l_vsrc = nullptr;                   // segment M2L (tree's or the plan's)
   int segs_nrhs = 0;                               // nrhs the uploaded segment tiling is for
   int seg_blocks = 0;
   double* W = nullptr;

@@ -174,6 +174,30 @@ hipError_t scan_rec(const int* in, int* out, long long n, hipStream_t s) {
   return e;
 }
 
+// Source lists of the non-empty targets of one uniform level: entry e of target `slot` is the
+// node (node_base + Morton cell) of the source at the octant table's offset e when it lies in
+// the level and holds points, else -1.
+__global__ void uniform_vsrc_kernel(const int* __restrict__ leaf_start, int depth, int level,
+                                    const int* __restrict__ tgt_node, int ntgt, int node_base,
+                                    const int* __restrict__ tab, int* __restrict__ vsrc) {
+  const long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (x >= (long long)ntgt * kFarPerOctant) return;
+  const int slot = (int)(x / kFarPerOctant), e = (int)(x - (long long)slot * kFarPerOctant);
+  const unsigned c = (unsigned)(tgt_node[slot] - node_base);
+  int tx, ty, tz;
+  demorton3(c, tx, ty, tz);
+  const int ent = tab[(c & 7u) * kFarPerOctant + e];
+  const int sx = tx + (ent & 7) - 3, sy = ty + ((ent >> 3) & 7) - 3, sz = tz + ((ent >> 6) & 7) - 3;
+  const int side = 1 << level;
+  int out = -1;
+  if (sx >= 0 && sy >= 0 && sz >= 0 && sx < side && sy < side && sz < side) {
+    const unsigned sc = morton3(sx, sy, sz);
+    const int sh = 3 * (depth - level);
+    if (leaf_start[(sc + 1u) << sh] > leaf_start[sc << sh]) out = node_base + (int)sc;
+  }
+  vsrc[x] = out;
+}
+
 }  // namespace
 
 int bbox_parts(long long n) {
@@ -217,6 +241,15 @@ hipError_t launch_order(const double* pts, const unsigned* keys, long long n,
                         double* xs, double* ys, double* zs, hipStream_t s) {
   hipLaunchKernelGGL(order_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pts, keys, n,
                      leaf_start, tmp, perm, leaf_of, xs, ys, zs);
+  return hipGetLastError();
+}
+
+hipError_t launch_uniform_vsrc(const int* leaf_start, int depth, int level, const int* tgt_node, int ntgt,
+                               int node_base, const int* tab, int* vsrc, hipStream_t s) {
+  const long long tot = (long long)ntgt * kFarPerOctant;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(uniform_vsrc_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, leaf_start, depth,
+                     level, tgt_node, ntgt, node_base, tab, vsrc);
   return hipGetLastError();
 }
 
