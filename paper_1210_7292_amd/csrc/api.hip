@@ -113,6 +113,13 @@ M2LArgs m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double* F, int 
   a.op_off = p->d_op_off; a.op_rank = p->d_op_rank;
   a.tab = p->d_tab; a.grp = p->d_grp; a.sig = p->d_sig; a.siginv = p->d_siginv;
   a.zeros = p->d_zeros;
+  // the split of the last round needs the whole-apply launch (all levels)
+  if (only_level < 0) {
+    a.scratch = p->d_split;
+    a.split_cap = p->split_cap;
+    a.tcount = p->d_tcount;
+    a.tcount_len = p->tcount_len;
+  }
   return a;
 }
 
@@ -805,6 +812,26 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
       off += (1LL << (3 * l)) * nn;
     }
     p->exp_elems = off;
+    // compressed operators: scratch for splitting the M2L's last round of workgroups
+    if (p->lowrank && depth >= 2) {
+      int dev = 0, cus = 0;
+      hipError_t e2 = hipGetDevice(&dev);
+      if (e2 == hipSuccess) e2 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      const int slots = 2 * cus;       // resident compressed-kernel workgroups at most
+      if (e2 == hipSuccess && slots > 0) {
+        p->split_cap = m2l_split_scratch_doubles(L, slots);
+        p->tcount_len = slots / 2;
+        e2 = dmalloc(&p->d_split, (size_t)p->split_cap, &bytes);
+        if (e2 == hipSuccess) e2 = dmalloc(&p->d_tcount, (size_t)p->tcount_len, &bytes);
+        if (e2 == hipSuccess) e2 = hipMemset(p->d_tcount, 0, sizeof(unsigned) * p->tcount_len);
+      }
+      if (e2 != hipSuccess) {
+        destroy_partial();
+        dfree(p->d_split); dfree(p->d_tcount);
+        return fail(e2 == hipErrorOutOfMemory ? BBFMM_ENOMEM : BBFMM_EHIP,
+                    std::string("M2L scratch: ") + hipGetErrorString(e2));
+      }
+    }
     // full-rank operators: M2L over the targets that hold points only
     if (!p->lowrank && depth >= 2) {
       const bbfmm_status st = build_sparse_uniform(p.get(), s, &bytes);
@@ -828,6 +855,7 @@ void bbfmm_plan_destroy(bbfmm_plan* p) {
   dfree(p->ops_hi); dfree(p->ops_lo); dfree(p->d_op_off); dfree(p->d_op_rank); dfree(p->d_tab);
   dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
   dfree(p->d_zeros); dfree(p->d_segs); dfree(p->d_utgt); dfree(p->d_uvsrc);
+  dfree(p->d_split); dfree(p->d_tcount);
   delete p;
 }
 

@@ -96,7 +96,21 @@ struct M2LArgs {
   int nsegs;
   const int* tgt;              // node of each target slot
   const int* vsrc;             // [slot][189]: source node of table entry e, or -1
+  // Compressed kernel, uniform trees: the tiles of the last, partial round of workgroups are split
+  // by transfer-vector range into tsplit parts whose partial tiles go to `scratch`; the last part
+  // of a tile to finish (counted in `tcount`, which it resets) sums them in part order.
+  int nmain;                   // tiles computed whole (the first nmain logical tiles)
+  int main_grid;               // workgroups of those tiles (nmain rounded up to 8)
+  int ntail, tsplit;           // split tiles and parts per tile (0: no split)
+  double* scratch;             // [tail tile][part][l^3 padded][cols]
+  long long split_cap;         // doubles in scratch
+  unsigned* tcount;            // [tail tile], zero between launches
+  int tcount_len;
 };
+
+// Scratch, in doubles, that lets a compressed-kernel launch split its last round when at most
+// `slots` workgroups are resident at once (tile counters needed: slots / 2).
+long long m2l_split_scratch_doubles(int order, int slots);
 
 // Returns the LDS-capacity rank limit of the compressed M2L kernel for an order.
 int m2l_ia_rank_limit(int order);
@@ -245,6 +259,11 @@ struct bbfmm_plan {
   int nrhs_cap = 0;
   long long level_off[bbfmm::kMaxLevels] = {0};   // element offsets (per rhs) into W / F
   long long exp_elems = 0;                         // per rhs (adaptive: nodes * l^3)
+  // scratch of the compressed M2L's split last round
+  double* d_split = nullptr;
+  long long split_cap = 0;
+  unsigned* d_tcount = nullptr;
+  int tcount_len = 0;
   std::vector<bbfmm::M2LLevel> h_segs;             // M2L segments (adaptive, or sparse uniform)
   bbfmm::M2LLevel* d_segs = nullptr;
   // Segment-based M2L on a uniform tree (full rank): only targets that hold points, with source

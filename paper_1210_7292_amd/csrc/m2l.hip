@@ -26,6 +26,7 @@
 // MFMA v_mfma_{f64,f32}_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]. It holds
 // D[row][l%16], v = 0..3, with row = l/16 + 4v for f64 and row = 4(l/16) + v for f32 (the two
 // output layouts differ on gfx950).
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -68,6 +69,8 @@ struct BlockPos {
   M2LLevel lv;     // the block's level, by value (uniform)
   int oct;
   int tile;
+  int part;        // transfer-vector part of a split tile, -1 for a whole tile
+  int tail;        // index of the split tile
 };
 
 template <bool AD>
@@ -75,9 +78,21 @@ __device__ inline bool locate(const M2LArgs& a, BlockPos& bp) {
   // Logical block order is level-major, then tile, then octant, so the 8 octants of one group of
   // parents are adjacent. Hardware sends block b to XCD b % 8; remapping gives each XCD a
   // contiguous range of logical blocks, keeping shared source cells in one L2.
-  const int per = gridDim.x / 8;
-  const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (logical >= a.nblocks) return false;
+  bp.part = -1;
+  bp.tail = 0;
+  int logical;
+  if (!AD && (int)blockIdx.x >= a.main_grid) {
+    // parts of the split tiles, after all whole tiles, spread over the XCDs in hardware order
+    const int q = (int)blockIdx.x - a.main_grid;
+    if (q >= a.ntail * a.tsplit) return false;
+    bp.tail = q / a.tsplit;
+    bp.part = q - bp.tail * a.tsplit;
+    logical = a.nmain + bp.tail;
+  } else {
+    const int per = (AD ? (int)gridDim.x : a.main_grid) / 8;
+    logical = ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8;
+    if (logical >= (AD ? a.nblocks : a.nmain)) return false;
+  }
   if (AD) {
     // adaptive: the last (level, octant) segment starting at or before this block
     int lo = 0, hi = a.nsegs - 1;
@@ -604,11 +619,14 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
     return s ? (gdouble*)s : zero_src;
   };
 
+  // transfer vectors of this workgroup: all, or one part of a split tile
+  const int e_begin = bp.part < 0 ? 0 : bp.part * kFarPerOctant / a.tsplit;
+  const int e_end = bp.part < 0 ? kFarPerOctant : (bp.part + 1) * kFarPerOctant / a.tsplit;
   double w[CH][4];
   int cur_p = -1, r = 0, zb = 0;
-  gdouble* src = source(0, tab[0]);
+  gdouble* src = source(e_begin, tab[e_begin]);
   if (PREFETCH) K::load(src, nrhs, kq, 0, w);
-  for (int e = 0; e < kFarPerOctant; ++e) {
+  for (int e = e_begin; e < e_end; ++e) {
     const int ent = tab[e];
     const int p = (ent >> 9) & 15;
     if (p != cur_p) {
@@ -674,7 +692,7 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
       else K::template gemm1<RMAX / 16>(vhi, vlo, sg, j, kq, c0, w, z);
     }
     // ---- next transfer vector's multipoles, in flight during GEMM 2 ----
-    if (e + 1 < kFarPerOctant) {
+    if (e + 1 < e_end) {
       src = source(e + 1, tab[e + 1]);
       if (PREFETCH) K::load(src, nrhs, kq, 0, w);
     }
@@ -694,7 +712,45 @@ __global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
       }
     }
   }
-  store_tile<L, MB, PREC, V>(a, bp, col, kq, acc, acc64, PREC != 0);
+  if (bp.part < 0) {
+    store_tile<L, MB, PREC, V>(a, bp, col, kq, acc, acc64, PREC != 0);
+    return;
+  }
+  // split tile: write this part's tile, and the last part to finish sums all parts in order
+  const int cols = a.cols;
+  const int c = 16 * wave + j;
+  double* part_base = a.scratch + (long long)bp.tail * a.tsplit * NP * cols;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * mb + out_row<PREC>(kq, v);
+      part_base[((long long)bp.part * NP + i) * cols + c] = PREC != 0 ? acc64[mb][v] : (double)acc[mb][v];
+    }
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned prev = __hip_atomic_fetch_add(&a.tcount[bp.tail], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = prev == (unsigned)(a.tsplit - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (col.valid) {
+    const double sc = bp.lv.scale;
+    double* dst = bp.lv.F + ((long long)col.target * NN) * nrhs + col.rhs;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * mb + out_row<PREC>(kq, v);
+        double t = 0.0;
+        for (int q = 0; q < a.tsplit; ++q) t += part_base[((long long)q * NP + i) * cols + c];
+        if (i < NN) dst[(long long)i * nrhs] = sc * t;
+      }
+  }
+  if (tid == 0) __hip_atomic_store(&a.tcount[bp.tail], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // K_p column chunk of the full-rank kernel; order 8 in FP32 takes 16 so that the permutation
@@ -720,23 +776,62 @@ void tile(M2LArgs& a, int cols) {
   a.nblocks = blocks;
 }
 
+constexpr int kSplitMaxParts = 16;
+
+// Splits the tiles of the last, partial round of workgroups (when the launch has scratch):
+// with R workgroups resident at once and B tiles, the last B mod R tiles are cut by transfer-
+// vector range into parts so that the last round is filled.
+void split_tail(M2LArgs& a, const void* kern, int threads, int np) {
+  a.nmain = a.nblocks;
+  a.main_grid = (a.nblocks + 7) / 8 * 8;
+  a.ntail = 0;
+  a.tsplit = 1;
+  if (a.scratch == nullptr || a.tcount == nullptr || a.split_cap <= 0) return;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess) return;
+  const int slots = cus * per_cu;
+  if (slots <= 0) return;
+  const int rem = a.nblocks % slots;
+  if (a.nblocks < slots || rem == 0 || rem > slots / 2 || rem > a.tcount_len) return;
+  const int parts = std::min(kSplitMaxParts, std::max(2, slots / rem));
+  if ((long long)rem * parts * np * a.cols > a.split_cap) return;
+  a.nmain = a.nblocks - rem;
+  a.main_grid = (a.nmain + 7) / 8 * 8;
+  a.ntail = rem;
+  a.tsplit = parts;
+  a.nblocks = a.nmain + rem * parts;
+}
+
 template <int L, int PREC, bool AD>
 hipError_t launch_ld(bool lowrank, M2LArgs a, hipStream_t s) {
   if (lowrank) {
     if constexpr (L >= 3) {
-      if (!AD) tile(a, 16 * kLowrankWaves);
-      const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
+      auto kern1 = m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, true, AD>;
+      auto kernn = m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, false, AD>;
+      unsigned grid;
+      if (!AD) {
+        tile(a, 16 * kLowrankWaves);
+        split_tail(a, a.nrhs == 1 ? (const void*)kern1 : (const void*)kernn, 64 * kLowrankWaves,
+                   (L * L * L + 15) / 16 * 16);
+        grid = (unsigned)(a.main_grid + a.ntail * a.tsplit);
+      } else {
+        grid = (unsigned)((a.nblocks + 7) / 8 * 8);
+      }
       if (a.nrhs == 1)
-        hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, true, AD>), dim3(grid),
-                           dim3(64 * kLowrankWaves), 0, s, a);
+        hipLaunchKernelGGL(kern1, dim3(grid), dim3(64 * kLowrankWaves), 0, s, a);
       else
-        hipLaunchKernelGGL((m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, false, AD>), dim3(grid),
-                           dim3(64 * kLowrankWaves), 0, s, a);
+        hipLaunchKernelGGL(kernn, dim3(grid), dim3(64 * kLowrankWaves), 0, s, a);
     } else {
       return hipErrorInvalidValue;
     }
   } else {
     if (!AD) tile(a, kCols);
+    a.nmain = a.nblocks;
+    a.main_grid = (a.nblocks + 7) / 8 * 8;
+    a.ntail = 0;
+    a.tsplit = 1;
     const unsigned grid = (unsigned)((a.nblocks + 7) / 8 * 8);
     constexpr int RS = full_rs<L>();
     hipLaunchKernelGGL((m2l_full_kernel<L, full_kc<L, PREC>(), PREC, AD, RS>), dim3(grid), dim3(kThreads * RS), 0, s,
@@ -773,6 +868,13 @@ int m2l_ia_rank_limit(int order) {
 }
 
 int m2l_block_cols(bool lowrank) { return lowrank ? 16 * kLowrankWaves : kCols; }
+
+long long m2l_split_scratch_doubles(int order, int slots) {
+  // split parts of one launch: rem * parts <= slots (parts <= slots / rem, or 2 when rem is
+  // within slots / 2)
+  const int np = (order * order * order + 15) / 16 * 16;
+  return (long long)slots * np * 16 * kLowrankWaves;
+}
 
 hipError_t launch_m2l(int order, bool lowrank, int prec, const M2LArgs& a0, hipStream_t s) {
   if (a0.segs == nullptr && a0.nlev <= 0) return hipSuccess;
