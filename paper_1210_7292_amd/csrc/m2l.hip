@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
     return sp ? (gdouble*)sp : zero_src;
   };
   // raw FP64 values: a conversion at load time would wait for the loads there
-  auto load_b = [&](int e, int ch, double (&bv)[KS]) {
+  auto load_b = [&](int e, int ch, double (&bv)[KS]) -> bool {
     const int ent = stab[e];
     gdouble* src = source(e, ent);
     const short* si = sib + (ent >> 13) * NP;
@@ -340,6 +340,7 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
       k = k < NN ? k : NN - 1;
       bv[s2] = src[(long long)si[k] * a.nrhs];
     }
+    return src != zero_src;
   };
   auto next_active = [&](int e, int g1) {
     while (e < g1 && !entry_active<AD>(amask, e)) ++e;
@@ -399,12 +400,20 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
       BT bv[KS];
       double bn[KS];
       int e = e0;
-      load_b(e, ch, bn);
+      bool pres = load_b(e, ch, bn), pres_n = false;
 #pragma unroll
       for (int s2 = 0; s2 < KS; ++s2) bv[s2] = (BT)bn[s2];
       while (e < g1) {
         const int en = next_active(e + 1, g1);
-        if (en < g1) load_b(en, ch, bn);
+        if (en < g1) pres_n = load_b(en, ch, bn);
+        // a wave none of whose columns has this source skips its products (they are zero)
+        if (__ballot(pres) == 0ull) {
+#pragma unroll
+          for (int s2 = 0; s2 < KS; ++s2) bv[s2] = (BT)bn[s2];
+          pres = pres_n;
+          e = en;
+          continue;
+        }
         const short* sg = sgb + (stab[e] >> 13) * NP;
         // LDS offsets of (sigma(i), kq) for this lane's rows, two 16-bit values per register; the
         // k step 4 s2 then folds into the LDS reads' immediate offsets
@@ -451,6 +460,7 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
         }
 #pragma unroll
         for (int s2 = 0; s2 < KS; ++s2) bv[s2] = (BT)bn[s2];
+        pres = pres_n;
         e = en;
       }
     }
