@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
       // loads in batches of SB issued back to back, then their LDS stores: a few memory
       // latencies per chunk rather than one per element
       constexpr int PER = ((NN + 1) * KC + NT - 1) / NT;
-      constexpr int SB = 4;
+      constexpr int SB = L >= 8 ? 4 : (sizeof(T) == 8 ? 8 : 16);   // order 8: register-bound
 #pragma unroll 1
       for (int u0 = 0; u0 < PER; u0 += SB) {
         T th[SB], tl[SPLIT ? SB : 1];
