@@ -95,6 +95,42 @@ def pass_work(np, tree, w, nrhs):
             "p2p_interactions": pairs}
 
 
+def run_ablation(torch, np, pk, tree, plan, w, level, stream, reps=3):
+    """M2L of one uniform level: the blocked kernel against the unblocked variants (Sec. 4.2), on
+    the same seeded multipoles; times from HIP events, FP64."""
+    nn = w.order ** 3
+    nrhs = w.nrhs if w.nrhs in (1, 2, 4) else 1
+    if w.m2l_prec != "fp64" or w.depth < level:
+        return None
+    p64 = plan
+    gen = torch.Generator(device="cuda:0").manual_seed(1210729200 + level)
+    W = torch.randn((8 ** level, nn, nrhs), dtype=torch.float64, device="cuda:0", generator=gen)
+
+    def timed(fn):
+        out = fn()
+        torch.cuda.synchronize()
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        for _ in range(reps):
+            out = fn()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        return out, a0.elapsed_time(a1) / reps
+
+    ref, t_blk = timed(lambda: p64.m2l_level(level, W))
+    s = 1 << level
+    pairs = (6 * s - 8) ** 3 - (3 * s - 2) ** 3
+    res = [{"variant": "IAblk" if w.svd_eps > 0 else "NAblk", "level": level, "pairs": pairs, "ms": t_blk}]
+    names = ["NA", "NAsym"] + (["IA", "IAsym"] if w.svd_eps > 0 else [])
+    for v in names:
+        out, t = timed(lambda: p64.m2l_unblocked(level, W, v))
+        res.append({"variant": v, "level": level, "pairs": pairs, "ms": t,
+                    "blocked_speedup": t / t_blk,
+                    "rel_l2_vs_blocked": float(torch.linalg.norm(out - ref) / torch.linalg.norm(ref))})
+        log(f"[bench] unblocked {v}: {t:.3f} ms (blocked {t_blk:.3f} ms)")
+    return res
+
+
 def cpu_baseline(w, inp, sample_n, grad_mode=False):
     """The oracle (as it stands) on a bounded sample of the same workload, on the host cores."""
     import numpy as np
@@ -149,6 +185,8 @@ def main():
                     help="points in the oracle sample (default: 100000; 20000 for order 7)")
     ap.add_argument("--variants", action="store_true",
                     help="also time the other M2L precisions and report their errors vs this one")
+    ap.add_argument("--ablation", type=int, default=0, metavar="LEVEL",
+                    help="also time the M2L of LEVEL with the unblocked variants (NA, NAsym, IA, IAsym)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -299,6 +337,10 @@ def main():
             variants.append(v)
             del p2, o2
 
+    ablation = None
+    if args.ablation:
+        ablation = run_ablation(torch, np, pk, tree, plan, w, args.ablation, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         if adaptive:
@@ -367,6 +409,8 @@ def main():
         line["config"]["step"] = "apply(q) + apply_adjoint(g) + eval_grad(q, g)"
     if variants is not None:
         line["precision_variants"] = variants
+    if ablation is not None:
+        line["unblocked_ablation"] = ablation
     print(json.dumps(line), flush=True)
 
 

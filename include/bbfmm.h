@@ -206,6 +206,19 @@ bbfmm_status bbfmm_debug_get_expansions(const bbfmm_plan* plan, int32_t level, i
 bbfmm_status bbfmm_debug_m2l_level(bbfmm_plan* plan, int32_t level, const double* d_w,
                                    int32_t nrhs, double* d_f, void* stream);
 
+/* Unblocked M2L variants of Sec. 4.2 (before blocking), for measuring the blocking: runs the M2L
+ * of `level` on caller multipoles d_w (layout as bbfmm_debug_m2l_level, nrhs 1, 2 or 4) with
+ * the plan's operators and writes d_f, one workgroup per target cell applying its transfer vectors
+ * one at a time as matrix-vector products read from memory:
+ *   variant 0 NA:    the 316 operators K_t (K_p with sigma_t applied, Eq. permutations)
+ *   variant 1 NAsym: the 16 operators, permutations applied on the fly (Eqs. perm_mult..perm_loc)
+ *   variant 2 IA:    the 316 factor pairs U_t, V_t (Eq. ialowrank); needs svd_eps > 0
+ *   variant 3 IAsym: the 16 factor pairs, permutations on the fly; needs svd_eps > 0
+ * Results equal bbfmm_debug_m2l_level up to rounding. FP64 only; uniform trees only.
+ * Errors: EINVAL, EUNSUPPORTED (adaptive tree, IA without compression, ranks above 64). */
+bbfmm_status bbfmm_m2l_unblocked(bbfmm_plan* plan, int32_t level, int32_t variant, const double* d_w,
+                                 int32_t nrhs, double* d_f, void* stream);
+
 /* Sorted-order permutation of the tree: d_perm[i] = caller index of the i-th point in leaf
  * order (n int32), and d_leaf_start (8^depth + 1 int32 offsets into that order). */
 bbfmm_status bbfmm_debug_tree_order(const bbfmm_tree* tree, int32_t* d_perm, int32_t* d_leaf_start,

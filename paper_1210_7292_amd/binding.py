@@ -77,6 +77,7 @@ SIGNATURES = [
     ("bbfmm_host_operator", C.c_int, [C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_int32,
                                       C.c_double, _P, _P, _P, _P]),
     ("bbfmm_host_singular_values", C.c_int, [_P, C.c_int32, C.c_int32, _P]),
+    ("bbfmm_m2l_unblocked", C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_int32, _P, _P]),
     ("bbfmm_adaptive_info_of", C.c_int, [_P, C.POINTER(AdaptiveInfo)]),
     ("bbfmm_adaptive_array", C.c_int, [_P, C.c_int32, _P]),
     ("bbfmm_host_adaptive_tree", C.c_int, [_P, C.c_int64, C.c_int32, _P, C.c_double, C.POINTER(_P)]),
@@ -345,6 +346,15 @@ class Plan:
         f = torch.empty_like(w)
         _check(lib().bbfmm_debug_m2l_level(self.handle, level, _dev_ptr(w, torch.float64, None, "w"),
                                            w.shape[2], _P(f.data_ptr()), _P(_stream(torch, w.device))))
+        return f
+
+    def m2l_unblocked(self, level: int, w, variant: str):
+        """Runs the M2L of `level` with an unblocked variant: "NA", "NAsym", "IA" or "IAsym"."""
+        import torch
+        f = torch.empty_like(w)
+        v = {"NA": 0, "NAsym": 1, "IA": 2, "IAsym": 3}[variant]
+        _check(lib().bbfmm_m2l_unblocked(self.handle, level, v, _dev_ptr(w, torch.float64, None, "w"), w.shape[2],
+                                         _P(f.data_ptr()), _P(_stream(torch, w.device))))
         return f
 
     def __del__(self):

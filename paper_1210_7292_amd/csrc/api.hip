@@ -687,6 +687,9 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
     }
   }
   p->lowrank = p->eps > 0 && nsets > 0 && L >= 3 && max_rank <= m2l_ia_rank_limit(L);
+  p->h_k = kfull;
+  p->h_u = ufac;
+  p->h_v = vfac;
   // ---- device layout ----
   std::vector<double> blob;
   p->op_off.assign(std::max(1, nsets) * kNumSym * 2, 0);
@@ -856,6 +859,7 @@ void bbfmm_plan_destroy(bbfmm_plan* p) {
   dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
   dfree(p->d_zeros); dfree(p->d_segs); dfree(p->d_utgt); dfree(p->d_uvsrc);
   dfree(p->d_split); dfree(p->d_tcount);
+  dfree(p->d_abl_ops); dfree(p->d_abl_off); dfree(p->d_abl_rank);
   delete p;
 }
 
@@ -1056,6 +1060,81 @@ bbfmm_status bbfmm_debug_m2l_level(bbfmm_plan* p, int32_t level, const double* d
   if (nrhs < 1 || nrhs > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64]");
   const M2LArgs a = m2l_args(p, nrhs, d_w, d_f, level);
   BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, (hipStream_t)stream));
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_m2l_unblocked(bbfmm_plan* p, int32_t level, int32_t variant, const double* d_w,
+                                 int32_t nrhs, double* d_f, void* stream) {
+  if (!p || !d_w || !d_f) return fail(BBFMM_EINVAL, "null argument");
+  if (p->tree->adaptive) return fail(BBFMM_EUNSUPPORTED, "uniform trees only");
+  if (level < 2 || level > p->tree->depth) return fail(BBFMM_EINVAL, "level must be in [2, depth]");
+  if (variant < 0 || variant > 3) return fail(BBFMM_EINVAL, "variant must be 0 (NA), 1 (NAsym), 2 (IA) or 3 (IAsym)");
+  if (nrhs != 1 && nrhs != 2 && nrhs != 4) return fail(BBFMM_EINVAL, "nrhs must be 1, 2 or 4");
+  const bool lowrank_variant = variant >= 2;
+  if (lowrank_variant && !(p->eps > 0)) return fail(BBFMM_EUNSUPPORTED, "IA variants need a compressed plan");
+  const int L = p->order, nn = p->nn, np = p->np;
+  const int set = p->set_of_level[level];
+  if (lowrank_variant)
+    for (int q = 0; q < kNumSym; ++q)
+      if (p->ranks[set * kNumSym + q] > 64) return fail(BBFMM_EUNSUPPORTED, "ranks above 64");
+  hipStream_t s = (hipStream_t)stream;
+  if (p->abl_variant != variant || p->abl_set != set) {
+    // operators of the variant on the host, transposed, then uploaded
+    const bool sym = variant == 1 || variant == 3;
+    const int nidx = sym ? kNumSym : 512;       // representatives, or offset codes of t
+    std::vector<double> blob;
+    std::vector<long long> off(2 * (size_t)nidx, 0);
+    std::vector<int> rank(nidx, 0);
+    std::vector<int32_t> sg(nn);
+    for (int idx = 0; idx < nidx; ++idx) {
+      int q = idx;
+      if (!sym) {
+        const int t[3] = {-((idx & 7) - 3), -(((idx >> 3) & 7) - 3), -(((idx >> 6) & 7) - 3)};
+        const int linf = std::max(std::abs(t[0]), std::max(std::abs(t[1]), std::abs(t[2])));
+        if ((idx & 7) > 6 || ((idx >> 3) & 7) > 6 || ((idx >> 6) & 7) > 6 || linf < 2) continue;
+        const SymInfo si = symmetry_of(t);
+        q = si.p;
+        sigma_table(L, si.perm_id, sg.data());
+      } else {
+        for (int i = 0; i < nn; ++i) sg[i] = i;
+      }
+      const int opi = set * kNumSym + q;
+      if (!lowrank_variant) {
+        const std::vector<double>& K = p->h_k[opi];
+        off[2 * idx] = (long long)blob.size();
+        for (int j = 0; j < nn; ++j)
+          for (int i = 0; i < nn; ++i) blob.push_back(K[(size_t)sg[i] * nn + sg[j]]);   // K_t^T
+      } else {
+        const int r = p->ranks[opi];
+        rank[idx] = r;
+        const std::vector<double>& U = p->h_u[opi];
+        const std::vector<double>& V = p->h_v[opi];
+        off[2 * idx] = (long long)blob.size();
+        for (int k = 0; k < r; ++k)
+          for (int i = 0; i < nn; ++i) blob.push_back(U[(size_t)sg[i] * r + k]);           // U_t^T
+        off[2 * idx + 1] = (long long)blob.size();
+        for (int k = 0; k < r; ++k)
+          for (int j = 0; j < nn; ++j) blob.push_back(V[(size_t)sg[j] * r + k]);           // V_t^T
+      }
+    }
+    dfree(p->d_abl_ops); dfree(p->d_abl_off); dfree(p->d_abl_rank);
+    p->d_abl_ops = nullptr; p->d_abl_off = nullptr; p->d_abl_rank = nullptr;
+    p->abl_variant = -1;
+    BBFMM_HIP_TRY(dmalloc(&p->d_abl_ops, blob.size(), nullptr));
+    BBFMM_HIP_TRY(dmalloc(&p->d_abl_off, off.size(), nullptr));
+    BBFMM_HIP_TRY(dmalloc(&p->d_abl_rank, rank.size(), nullptr));
+    BBFMM_HIP_TRY(hipMemcpy(p->d_abl_ops, blob.data(), blob.size() * sizeof(double), hipMemcpyHostToDevice));
+    BBFMM_HIP_TRY(hipMemcpy(p->d_abl_off, off.data(), off.size() * sizeof(long long), hipMemcpyHostToDevice));
+    BBFMM_HIP_TRY(hipMemcpy(p->d_abl_rank, rank.data(), rank.size() * sizeof(int), hipMemcpyHostToDevice));
+    p->abl_variant = variant;
+    p->abl_set = set;
+  }
+  (void)np;
+  AblationArgs a;
+  a.W = d_w; a.F = d_f; a.level = level; a.scale = p->scale_of_level[level];
+  a.ops = p->d_abl_ops; a.op_off = p->d_abl_off; a.op_rank = p->d_abl_rank;
+  a.tab = p->d_tab; a.sig = p->d_sig; a.variant = variant; a.nrhs = nrhs;
+  BBFMM_HIP_TRY(launch_m2l_unblocked(L, a, s));
   return BBFMM_OK;
 }
 

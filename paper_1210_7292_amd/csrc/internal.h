@@ -141,6 +141,22 @@ hipError_t launch_order(const double* pts, const unsigned* keys, long long n,
                         const int* leaf_start, const int* tmp, int* perm, int* leaf_of,
                         double* xs, double* ys, double* zs, hipStream_t s);
 
+// ---- unblocked M2L variants (measurement of the blocking) -----------------------------------
+struct AblationArgs {
+  const double* W;             // multipoles of one uniform level, [cell][l^3][nrhs], Morton cells
+  double* F;                   // output, overwritten
+  int level;
+  double scale;                // homogeneity factor of the level
+  const double* ops;           // operators, transposed ([j][i] or [r][i])
+  const long long* op_off;     // [index][2]: dense K^T (or U^T) and V^T offsets, in doubles
+  const int* op_rank;          // [index]
+  const int* tab;              // [8][189]
+  const short* sig;            // [48][NP]
+  int variant;                 // 0 NA, 1 NAsym, 2 IA, 3 IAsym
+  int nrhs;                    // 1, 2 or 4
+};
+hipError_t launch_m2l_unblocked(int order, const AblationArgs& a, hipStream_t s);
+
 // ---- adaptive tree build ------------------------------------------------------------------
 hipError_t launch_keys64(const double* pts, long long n, const double lo[3], double width,
                          unsigned long long* keys, int* idx, hipStream_t s);
@@ -246,6 +262,14 @@ struct bbfmm_plan {
   int set_of_level[bbfmm::kMaxPlanLevels] = {0};
   double scale_of_level[bbfmm::kMaxPlanLevels] = {0};
   std::vector<int> ranks;                 // [set][16]
+  // host FP64 operators ([set][16]: full or truncated K, and the factors when compressed), kept
+  // for the unblocked variants
+  std::vector<std::vector<double>> h_k, h_u, h_v;
+  // device operators of the unblocked variant last used: (variant, set) and its buffers
+  int abl_variant = -1, abl_set = -1;
+  double* d_abl_ops = nullptr;
+  long long* d_abl_off = nullptr;
+  int* d_abl_rank = nullptr;
   std::vector<long long> op_off;          // [set][16][2]
   double precompute_seconds = 0;
   // device data

@@ -94,6 +94,26 @@ def test_m2l_level_matches_oracle(order, eps, prec, level, nrhs, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("order,eps,variant,level,nrhs", [
+    (4, 0.0, "NA", 3, 1), (4, 0.0, "NAsym", 3, 2), (5, 1e-5, "NA", 3, 1), (5, 1e-5, "NAsym", 2, 4),
+    (5, 1e-5, "IA", 3, 1), (5, 1e-5, "IAsym", 3, 2), (3, 1e-3, "IAsym", 4, 1), (7, 0.0, "NAsym", 2, 1),
+])
+def test_unblocked_variants_match_oracle(order, eps, variant, level, nrhs):
+    """The unblocked variants (per-pair products with the 316 operators or the 16 permuted ones)
+    compute the same M2L as the oracle."""
+    say("unblocked", order, eps, variant, level, nrhs)
+    pts, _ = cube(64, 1, 1)
+    tree = pk.Octree(dev(pts), level)
+    plan = pk.Plan(tree, "inv_r", order, eps, "fp64")
+    rng = np.random.default_rng(200 + level)
+    w = rng.standard_normal((8 ** level, order ** 3, nrhs))
+    f_gpu = host(plan.m2l_unblocked(level, dev(oracle_to_morton(w, level)), variant))
+    f_ref = O.m2l_level(w, level, 1.0, order, "inv_r", 0.0, eps)
+    err = rel(morton_to_oracle(f_gpu, level), f_ref)
+    say("  rel err", err)
+    assert err < 1e-12
+
+
 # ------------------------------------------------------------------------------ full apply
 
 
