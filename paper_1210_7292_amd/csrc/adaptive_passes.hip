@@ -412,9 +412,10 @@ __global__ void ad_p2p_kernel(AdaptiveGeom g, const int* __restrict__ leaf_pos, 
   }
 }
 
+// Grid-stride: a dispatch holds fewer than 2^32 work-items, and n may exceed that.
 __global__ void fill_zero_kernel(double* __restrict__ x, long long n) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i < n) x[i] = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) x[i] = 0.0;
 }
 
 // ---- dispatch -------------------------------------------------------------------------------
@@ -601,7 +602,8 @@ template <int KIND> struct AdP2P {
 
 hipError_t launch_fill_zero(double* x, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
+  const long long blocks = std::min<long long>((n + 255) / 256, 1LL << 20);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n);
   return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 // Layouts: points sorted in Morton leaf order (SoA), densities [point][rhs], expansions
 // [cell][l^3][rhs] with cells of a level in Morton order and interpolation points in the order
 // m(a) = a1 + l a2 + l^2 a3 (Sec. 3.1).
+#include <algorithm>
+
 #include "device_math.h"
 #include "internal.h"
 
@@ -23,13 +25,15 @@ __device__ inline void cell_center(const PassGeom& g, int level, unsigned cell, 
   *half = 0.5 * w;
 }
 
+// Grid-stride: n * nrhs may exceed the 2^32 work-items of one dispatch.
 __global__ void gather_rows_kernel(const double* __restrict__ in, const int* __restrict__ perm,
                                    long long n, int nrhs, double* __restrict__ out) {
-  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (idx >= n * nrhs) return;
-  const long long i = idx / nrhs;
-  const int r = (int)(idx - i * nrhs);
-  out[idx] = in[(long long)perm[i] * nrhs + r];
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n * nrhs; idx += stride) {
+    const long long i = idx / nrhs;
+    const int r = (int)(idx - i * nrhs);
+    out[idx] = in[(long long)perm[i] * nrhs + r];
+  }
 }
 
 // ---- P2M: W[leaf][b][r] = sum_{j in leaf} S(y_j, ybar_b) q_j[r] ----------------------------
@@ -524,7 +528,8 @@ template <int KIND> struct GradAtKind {
 hipError_t launch_gather_rows(const double* in, const int* perm, long long n, int nrhs,
                               double* out, hipStream_t s) {
   const long long tot = n * nrhs;
-  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, perm,
+  const long long blocks = std::min<long long>((tot + 255) / 256, 1LL << 20);
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, perm,
                      n, nrhs, out);
   return hipGetLastError();
 }

@@ -79,6 +79,9 @@ def test_tree_order_is_stable_morton_sort(n, depth):
     (4, 0.0, "fp32", 3, 1, 1e-6),
     (4, 0.0, "split32", 3, 1, 1e-6),
     (5, 1e-5, "fp32", 3, 1, 1e-6),
+    (8, 0.0, "fp64", 2, 1, 1e-12),
+    (8, 0.0, "fp32", 2, 4, 1e-6),
+    (6, 0.0, "fp64", 3, 2, 1e-12),
 ])
 def test_m2l_level_matches_oracle(order, eps, prec, level, nrhs, tol):
     say("m2l level", order, eps, prec, level, nrhs)
@@ -131,6 +134,8 @@ CASES = [
     ("fp32_p7", 2000, 4, 7, 3, "inv_sqrt_r2c2", 1e-3, 0.0, "fp32", 1e-5),
     # 304 compressed-kernel workgroups: more than one round, so the last round is split by
     # transfer-vector range and reduced by the last part to finish
+    ("p8_d3_fp64", 3000, 2, 8, 3, "inv_r", 0.0, 0.0, "fp64", 1e-12),
+    ("p8_d3_fp32_16rhs", 3000, 16, 8, 3, "inv_r", 0.0, 0.0, "fp32", 1e-6),
     ("ia_p5_d5_split", 40000, 1, 5, 5, "inv_r", 0.0, 1e-5, "fp64", 1e-12),
     ("ia_p4_d5_split_fp32", 30000, 1, 4, 5, "inv_r", 0.0, 1e-5, "fp32", 1e-6),
 ]

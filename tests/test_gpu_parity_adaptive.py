@@ -91,6 +91,12 @@ CASES = [
     ("clustered_p4_fp32", "clustered", 1500, 16, 4, "inv_r", 0.0, 0.0, "fp32", 1, 1e-6),
     ("clustered_p6_split", "clustered", 1000, 10, 6, "inv_r", 0.0, 0.0, "split32", 1, 1e-6),
     ("clustered_p5_ia_fp32", "clustered", 1500, 16, 5, "inv_r", 0.0, 1e-5, "fp32", 1, 1e-6),
+    # 4 and 16 right-hand sides: a full-rank workgroup holds at most 17 targets, whose source
+    # lists it keeps in LDS
+    ("shellblob_p4_4rhs", "shell_blob", 2500, 20, 4, "inv_r", 0.0, 0.0, "fp64", 4, 1e-12),
+    ("clustered_p3_16rhs_fp32", "clustered", 1200, 12, 3, "inv_r", 0.0, 0.0, "fp32", 16, 1e-6),
+    ("shellblob_p8_fp64", "shell_blob", 2500, 32, 8, "inv_r", 0.0, 0.0, "fp64", 2, 1e-12),
+    ("shellblob_p8_16rhs_fp32", "shell_blob", 2500, 32, 8, "inv_r", 0.0, 0.0, "fp32", 16, 1e-6),
 ]
 
 
@@ -165,3 +171,57 @@ def test_adaptive_stats_count_v_pairs():
     assert st["pairs_total"] == info["v_pairs"] == st["pairs_nonempty"]
     assert st["m2l_flops_algorithmic"] == pytest.approx(info["v_pairs"] * 2 * 64 ** 2)
     assert st["m2l_flops_issued"] >= st["m2l_flops_algorithmic"]
+
+
+def test_full_size_cfg5_properties():
+    """8M points (sphere shell + Gaussian blob), adaptive <= 64 points per leaf, order 8, 16
+    right-hand sides, FP32 M2L (the oracle is too slow at this size): the device tree equals the
+    host build, the FP32 result matches the direct sum at sampled targets to the interpolation
+    error and stays within 1e-6 of the FP64 M2L, and the operator is symmetric."""
+    from workloads import WORKLOADS, make_inputs
+    say("full size cfg5")
+    w = WORKLOADS[5]
+    inp = make_inputs(w)
+    P = dev(inp.points)
+    tree = pk.Octree(P, -1, root_width=0.0, max_leaf_points=w.max_leaf_points)
+    a = tree.arrays()
+    b = B.HostAdaptiveTree(inp.points, w.max_leaf_points).arrays()
+    assert a["info"] == b["info"]
+    for name in ("level_off", "key", "start", "end", "u_off", "w_off", "x_off", "m2l_off", "perm"):
+        assert np.array_equal(a[name], b[name]), name
+    del b
+    q = dev(inp.q)
+    tg = torch.from_numpy(inp.sample_targets[:128].astype(np.int64)).to(DEV)
+    # direct sum at the sampled targets, FP64 on the device (measurement only)
+    direct = torch.zeros((tg.numel(), w.nrhs), dtype=torch.float64, device=DEV)
+    x = P[tg]
+    for s0 in range(0, w.n, 1 << 18):
+        y = P[s0:s0 + (1 << 18)]
+        d2 = ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1)
+        k = torch.where(d2 > 0, d2.rsqrt(), torch.zeros_like(d2))
+        direct += k @ q[s0:s0 + (1 << 18)]
+    direct = host(direct)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        plan = pk.Plan(tree, w.kernel, w.order, 0.0, prec, w.c)
+        out[prec] = host(plan.apply(q))
+        e = rel(out[prec][inp.sample_targets[:128]], direct)
+        say("  ", prec, "vs direct", e)
+        assert e < 1e-5
+        if prec == "fp64":
+            # the expansions (34.9 GB each) exceed 2^32 doubles: work sized by them must not be
+            # launched as one dispatch of that many work-items
+            g = dev(inp.g)
+            ag = host(plan.apply(g))
+            lhs, rhs = float(np.sum(inp.g * out[prec])), float(np.sum(inp.q * ag))
+            scale = float(np.linalg.norm(inp.g) * np.linalg.norm(out[prec]))
+            say("  symmetry", lhs, rhs, abs(lhs - rhs) / scale)
+            assert abs(lhs - rhs) < 1e-13 * scale
+            again = host(plan.apply(q))
+            assert np.array_equal(again, out[prec])
+        del plan
+        torch.cuda.empty_cache()
+    e = rel(out["fp32"], out["fp64"])
+    say("  fp32 vs fp64", e)
+    assert e < 1e-6
+
