@@ -163,9 +163,10 @@ def lists(tree: AdaptiveTree):
 
 
 def fmm_apply(points, q, order, max_pts, kind="inv_r", c=0.0, max_depth=MAX_DEPTH, lo=None, width=None,
-              tree: Optional[AdaptiveTree] = None, eps: float = 0.0):
+              tree: Optional[AdaptiveTree] = None, eps: float = 0.0, compressor: str = "svd"):
     """phi of the adaptive bbFMM with operators formed directly per transfer vector and cell width:
-    full rank for eps <= 0, else K_t ~ U_t V_t^T by truncated SVD applied as U_t (V_t^T w)
+    full rank for eps <= 0, else K_t ~ U_t V_t^T (truncated SVD, or ACA + SVD of the
+    representative, `bbfmm_oracle.compressed_operator`) applied as U_t (V_t^T w)
     (Eq. ialowrank)."""
     points = np.ascontiguousarray(points, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
@@ -203,8 +204,10 @@ def fmm_apply(points, q, order, max_pts, kind="inv_r", c=0.0, max_depth=MAX_DEPT
     def m2l_apply(t, w, x):
         key = (tuple(int(v) for v in t), w)
         if key not in ops:
-            kt = O.m2l_operator(np.asarray(key[0]), w, order, kind, c)
-            ops[key] = O.compress(kt, eps)[:2] if eps > 0 else kt
+            if eps > 0:
+                ops[key] = O.compressed_operator(key[0], w, order, kind, c, eps, compressor)
+            else:
+                ops[key] = O.m2l_operator(np.asarray(key[0]), w, order, kind, c)
         op = ops[key]
         return op[0] @ (op[1].T @ x) if eps > 0 else op @ x
 

@@ -17,6 +17,8 @@ interpolation based fast multipole method"):
 * Sec. 3.2: near field |t| <= sqrt(3) (27 cells), far field of a cell = children of the parent's
   near field that are not near (at most 189), 316 transfer vectors per level — `interaction_pairs`.
 * Sec. 4.2, Eq. (ialowrank): individual truncated-SVD low rank K_t ~ U_t V_t^T — `compress`.
+* Sec. 4.1 and Sec. 5 (the compressors of SA and IA): adaptive cross approximation followed by a
+  truncated SVD — `aca`, `compress_aca`, `compressed_operator(..., "aca")`.
 * Sec. 4.2.1, Eqs. (axial_permutation), (diagonal_permutation), (permutations): the
   symmetry tables, used only by the invariant tests — `symmetry`.
 
@@ -36,9 +38,17 @@ Readings taken where the paper is silent, ambiguous or garbled:
     cluster of values within 1e-10 * sigma_1 of the last kept one, so the truncated operator
     is unique.
  6. M2L runs on levels >= 2; a point belongs to leaf floor((x - lo) / w_leaf), clamped.
+ 7. ACA (the paper names it and cites Bebendorf, without details): partial pivoting starting at
+    row 0, Bebendorf's stopping test ||u_k|| ||v_k|| <= tol ||S_k||_F with tol = 1e-2 eps, pivot
+    candidates within a relative 1e-12 of the largest taken as tied (first index wins). ACA's
+    result depends on the row order, so it is run on the 16 representatives and mapped to each
+    t by sigma_t; before the truncated SVD the approximation is made to satisfy the exact
+    operator's K_p^T = K_p[Q][:, Q] (Q = sigma of -t_p), which keeps K_{-t} = K_t^T and with it
+    A^T = A.
 """
 from __future__ import annotations
 
+import functools
 import itertools
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional, Tuple
@@ -248,6 +258,106 @@ def compress(kmat: np.ndarray, eps: float):
     return u[:, :r] * s[:r], vt[:r].T.copy(), s
 
 
+# ACA tolerance relative to the truncation eps, and the relative window within which two pivot
+# candidates count as tied (the first index wins)
+ACA_REL_TOL = 1e-2
+PIVOT_TIE = 1e-12
+
+
+def _pivot(x: np.ndarray, allowed: np.ndarray) -> Tuple[int, float]:
+    """Index of the largest |x_i| over `allowed`; candidates within a relative PIVOT_TIE of the
+    largest are tied and the first of them is taken."""
+    a = np.where(allowed, np.abs(x), -1.0)
+    m = float(a.max())
+    return int(np.flatnonzero(a >= m * (1.0 - PIVOT_TIE))[0]), m
+
+
+def aca(kmat: np.ndarray, tol: float):
+    """Adaptive cross approximation with partial pivoting (Sec. 4.1 cites it as the faster
+    replacement of the SVD): K ~ sum_k u_k v_k^T built one cross at a time from single rows and
+    columns of K.
+
+    Step k takes the residual of the pivot row i_k, its largest entry j_k, v_k = that row divided
+    by the pivot entry and u_k = the residual of column j_k; the next pivot row is the largest
+    entry of u_k among rows not used yet. ||S_k||_F^2 of the sum so far is updated from the inner
+    products of the crosses; the loop ends when ||u_k|| ||v_k|| <= tol ||S_k||_F, or when every
+    row has been used. A residual row that is exactly zero is skipped (next unused row).
+    Returns U (m x k), V (n x k)."""
+    m, n = kmat.shape
+    us: List[np.ndarray] = []
+    vs: List[np.ndarray] = []
+    free = np.ones(m, dtype=bool)
+    i = 0
+    norm2 = 0.0
+    while len(us) < min(m, n):
+        free[i] = False
+        row = kmat[i].copy()
+        for u, v in zip(us, vs):
+            row -= u[i] * v
+        j, rmax = _pivot(row, np.ones(n, dtype=bool))
+        if rmax == 0.0:
+            if not free.any():
+                break
+            i = int(np.flatnonzero(free)[0])
+            continue
+        v = row / row[j]
+        u = kmat[:, j].copy()
+        for ul, vl in zip(us, vs):
+            u -= vl[j] * ul
+        norm2 += 2.0 * sum(float(u @ ul) * float(v @ vl) for ul, vl in zip(us, vs))
+        norm2 += float(u @ u) * float(v @ v)
+        us.append(u)
+        vs.append(v)
+        if np.sqrt(float(u @ u) * float(v @ v)) <= tol * np.sqrt(norm2) or not free.any():
+            break
+        i, _ = _pivot(u, free)
+    if not us:
+        return np.zeros((m, 0)), np.zeros((n, 0))
+    return np.stack(us, axis=1), np.stack(vs, axis=1)
+
+
+def transpose_permutation(p_t, order: int) -> np.ndarray:
+    """Q with K_p^T = K_p[Q][:, Q] for representative p: the permutation sigma of -t_p (the
+    reflection of every axis on which t_p is non-zero, an involution)."""
+    _, q = symmetry(tuple(-int(x) for x in p_t), order)
+    return q
+
+
+def compress_aca(kmat: np.ndarray, eps: float, q: np.ndarray):
+    """ACA followed by a truncated SVD (Sec. 5: the second compressor of the SA and IA variants):
+    A = U V^T from `aca` at tolerance ACA_REL_TOL * eps, made consistent with K^T = K[Q][:, Q]
+    as A_s[i, j] = (A[i, j] + A[Q(j), Q(i)]) / 2, then truncated as `compress` truncates K.
+    Returns U_r Sigma_r, V_r and the singular values of A_s."""
+    u, v = aca(kmat, ACA_REL_TOL * eps)
+    a = u @ v.T
+    a_sym = 0.5 * (a + a[np.ix_(q, q)].T)
+    uu, s, vt = np.linalg.svd(a_sym)
+    r = rank_of(s, eps)
+    return uu[:, :r] * s[:r], vt[:r].T.copy(), s
+
+
+def compressed_operator(t, width: float, order: int, kind: str, c: float, eps: float,
+                        compressor: str = "svd"):
+    """(U_t, V_t) with K_t ~ U_t V_t^T. "svd": truncated SVD of K_t itself. "aca": ACA + SVD of
+    the representative K_p (Eq. reduced_interaction_list), mapped to t by its permutation,
+    U_t = U_p[sigma_t], V_t = V_p[sigma_t] (ACA's pivots depend on the row order, so the
+    compressed family is defined on the 16 representatives, as the symmetric variants use it)."""
+    if compressor == "svd":
+        u, v, _ = compress(m2l_operator(t, width, order, kind, c), eps)
+        return u, v
+    if compressor != "aca":
+        raise ValueError(compressor)
+    p, sigma = symmetry(t, order)
+    u, v = _aca_representative(p, float(width), order, kind, float(c), float(eps))
+    return u[sigma], v[sigma]
+
+
+@functools.lru_cache(maxsize=256)
+def _aca_representative(p, width, order, kind, c, eps):
+    u, v, _ = compress_aca(m2l_operator(p, width, order, kind, c), eps, transpose_permutation(p, order))
+    return u, v
+
+
 # ----------------------------------------------------------------------------------------
 # Uniform octree (Sec. 3, Alg. SeparateNearAndFarField restricted to the smooth branch)
 # ----------------------------------------------------------------------------------------
@@ -372,10 +482,10 @@ def l2l(f_parent: np.ndarray, child_level: int, order: int, f_child: np.ndarray)
 
 
 def m2l_level(w: np.ndarray, level: int, width: float, order: int, kind: str, c: float,
-              eps: float, stats: Optional[dict] = None) -> np.ndarray:
+              eps: float, stats: Optional[dict] = None, compressor: str = "svd") -> np.ndarray:
     """F_X = sum over the interaction list of K_t W_Y, one directly formed K_t per t.
 
-    eps <= 0: full-rank K_t (NA); eps > 0: K_t ~ U_t V_t^T by truncated SVD (IA).
+    eps <= 0: full-rank K_t (NA); eps > 0: K_t ~ U_t V_t^T (IA) by `compressed_operator`.
     """
     f = np.zeros_like(w)
     wl = width / (1 << level)
@@ -384,7 +494,7 @@ def m2l_level(w: np.ndarray, level: int, width: float, order: int, kind: str, c:
         # all pairs sharing t as one product K_t [W_Y1, W_Y2, ...] (columns = pairs x rhs)
         cols = w[yi].transpose(1, 0, 2).reshape(w.shape[1], -1)
         if eps > 0:
-            u, v, _ = compress(kt, eps)
+            u, v = compressed_operator(t, wl, order, kind, c, eps, compressor)
             prod = u @ (v.T @ cols)
             if stats is not None:
                 stats.setdefault("ranks", {})[(level, t)] = u.shape[1]
@@ -474,7 +584,7 @@ class FMMResult:
 
 def fmm_apply(points: np.ndarray, q: np.ndarray, order: int, depth: int, kind: str = "inv_r",
               c: float = 0.0, eps: float = 0.0, lo=(0.0, 0.0, 0.0), width: float = 1.0,
-              p2p_loop: bool = False) -> FMMResult:
+              p2p_loop: bool = False, compressor: str = "svd") -> FMMResult:
     """phi = bbFMM approximation of Eq. (direct) on a uniform octree of leaf level `depth`."""
     points = np.ascontiguousarray(points, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
@@ -491,7 +601,7 @@ def fmm_apply(points: np.ndarray, q: np.ndarray, order: int, depth: int, kind: s
         for lev in range(depth - 1, 1, -1):
             mult[lev] = m2m(mult[lev + 1], lev + 1, order)
         for lev in range(2, depth + 1):
-            loc_m2l[lev] = m2l_level(mult[lev], lev, width, order, kind, c, eps, stats)
+            loc_m2l[lev] = m2l_level(mult[lev], lev, width, order, kind, c, eps, stats, compressor)
         loc[2] = loc_m2l[2].copy()
         for lev in range(3, depth + 1):
             loc[lev] = loc_m2l[lev].copy()
@@ -502,7 +612,7 @@ def fmm_apply(points: np.ndarray, q: np.ndarray, order: int, depth: int, kind: s
 
 
 def fmm_adjoint(points, g, order, depth, kind="inv_r", c=0.0, eps=0.0, lo=(0.0, 0.0, 0.0),
-                width=1.0) -> np.ndarray:
+                width=1.0, compressor: str = "svd") -> np.ndarray:
     """A^T g through the literally transposed chain: L2P^T, L2L^T, M2L^T (K_t^T), M2M^T, P2M^T, P2P^T."""
     points = np.ascontiguousarray(points, dtype=np.float64)
     g = np.asarray(g, dtype=np.float64)
@@ -511,7 +621,7 @@ def fmm_adjoint(points, g, order, depth, kind="inv_r", c=0.0, eps=0.0, lo=(0.0, 
     tree = UniformTree(points, depth, np.asarray(lo, dtype=np.float64), float(width))
     out = np.zeros_like(g)
     if depth >= 2:
-        wbar = _adjoint_leaf_locals(points, g, order, depth, kind, c, eps, lo, width)
+        wbar = _adjoint_leaf_locals(points, g, order, depth, kind, c, eps, lo, width, compressor)
         basis = tensor_basis(tree.local_coords(), order)
         out += np.einsum("nb,nbr->nr", basis, wbar[tree.leaf])       # P2M^T
     # P2P^T: sum_i K(x_i, x_j) g_i, the same near-field sum for a symmetric kernel
@@ -520,7 +630,7 @@ def fmm_adjoint(points, g, order, depth, kind="inv_r", c=0.0, eps=0.0, lo=(0.0, 
 
 
 def fmm_grad_points(points, q, g, order, depth, kind="inv_r", c=0.0, eps=0.0,
-                    lo=(0.0, 0.0, 0.0), width=1.0) -> np.ndarray:
+                    lo=(0.0, 0.0, 0.0), width=1.0, compressor: str = "svd") -> np.ndarray:
     """d/dx_i of L = sum_k g_k . phi_k(x) with the tree (cell membership and centres) fixed.
 
     Target role: g_i . grad L2P(F^(q))(x_i) + near-field grad; source role: q_i . grad of the
@@ -533,8 +643,9 @@ def fmm_grad_points(points, q, g, order, depth, kind="inv_r", c=0.0, eps=0.0,
     n = points.shape[0]
     out = np.zeros((n, 3))
     if depth >= 2:
-        fq = fmm_apply(points, q, order, depth, kind, c, eps, lo, width).locals[depth]
-        fg = _adjoint_leaf_locals(points, g, order, depth, kind, c, eps, lo, width)
+        fq = fmm_apply(points, q, order, depth, kind, c, eps, lo, width,
+                       compressor=compressor).locals[depth]
+        fg = _adjoint_leaf_locals(points, g, order, depth, kind, c, eps, lo, width, compressor)
         u = tree.local_coords()
         scale = 2.0 / tree.cell_width(depth)
         dbasis = tensor_basis_grad(u, order) * scale      # (n, l^3, 3)
@@ -561,7 +672,7 @@ def fmm_grad_points(points, q, g, order, depth, kind="inv_r", c=0.0, eps=0.0,
     return out
 
 
-def _adjoint_leaf_locals(points, g, order, depth, kind, c, eps, lo, width) -> np.ndarray:
+def _adjoint_leaf_locals(points, g, order, depth, kind, c, eps, lo, width, compressor="svd") -> np.ndarray:
     """Leaf-level adjoint locals: the transposed chain of P2M^T applied down to the leaves."""
     # For the adjoint, the multipole side of the chain becomes a local side: the leaf-level
     # quantity paired with the P2M basis of point i is (M2M^T ... M2L^T ... L2L^T L2P^T g)_leaf.
@@ -587,7 +698,7 @@ def _adjoint_leaf_locals(points, g, order, depth, kind, c, eps, lo, width) -> np
             kt = m2l_operator(t, wl, order, kind, c)
             cols = fbar[lev][xi].transpose(1, 0, 2).reshape(fbar[lev].shape[1], -1)
             if eps > 0:
-                u, v, _ = compress(kt, eps)
+                u, v = compressed_operator(t, wl, order, kind, c, eps, compressor)
                 prod = v @ (u.T @ cols)
             else:
                 prod = kt.T @ cols
