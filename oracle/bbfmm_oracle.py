@@ -40,7 +40,7 @@ Readings taken where the paper is silent, ambiguous or garbled:
  6. M2L runs on levels >= 2; a point belongs to leaf floor((x - lo) / w_leaf), clamped.
  7. ACA (the paper names it and cites Bebendorf, without details): partial pivoting starting at
     row 0, Bebendorf's stopping test ||u_k|| ||v_k|| <= tol ||S_k||_F with tol = 1e-2 eps, pivot
-    candidates within a relative 1e-12 of the largest taken as tied (first index wins). ACA's
+    candidates within 1e-12 max|K| of the largest taken as tied (first index wins). ACA's
     result depends on the row order, so it is run on the 16 representatives and mapped to each
     t by sigma_t; before the truncated SVD the approximation is made to satisfy the exact
     operator's K_p^T = K_p[Q][:, Q] (Q = sigma of -t_p), which keeps K_{-t} = K_t^T and with it
@@ -258,18 +258,21 @@ def compress(kmat: np.ndarray, eps: float):
     return u[:, :r] * s[:r], vt[:r].T.copy(), s
 
 
-# ACA tolerance relative to the truncation eps, and the relative window within which two pivot
-# candidates count as tied (the first index wins)
+# ACA tolerance relative to the truncation eps, and the window (relative to the matrix's largest
+# entry) within which two pivot candidates count as tied (the first index wins)
 ACA_REL_TOL = 1e-2
 PIVOT_TIE = 1e-12
 
 
-def _pivot(x: np.ndarray, allowed: np.ndarray) -> Tuple[int, float]:
-    """Index of the largest |x_i| over `allowed`; candidates within a relative PIVOT_TIE of the
-    largest are tied and the first of them is taken."""
+def _pivot(x: np.ndarray, allowed: np.ndarray, window: float) -> Tuple[int, float]:
+    """Index of the largest |x_i| over `allowed`; candidates within min(window, half the largest)
+    of the largest are tied and the first of them is taken. Mirror-image entries of the kernel
+    matrices are equal in exact arithmetic, and a residual carries rounding errors of the order
+    of the matrix's largest entry, not of its own size: the window makes the choice among them
+    independent of how the residual was rounded."""
     a = np.where(allowed, np.abs(x), -1.0)
     m = float(a.max())
-    return int(np.flatnonzero(a >= m * (1.0 - PIVOT_TIE))[0]), m
+    return int(np.flatnonzero(a >= m - min(window, 0.5 * m))[0]), m
 
 
 def aca(kmat: np.ndarray, tol: float):
@@ -281,12 +284,14 @@ def aca(kmat: np.ndarray, tol: float):
     by the pivot entry and u_k = the residual of column j_k; the next pivot row is the largest
     entry of u_k among rows not used yet. ||S_k||_F^2 of the sum so far is updated from the inner
     products of the crosses; the loop ends when ||u_k|| ||v_k|| <= tol ||S_k||_F, or when every
-    row has been used. A residual row that is exactly zero is skipped (next unused row).
+    row has been used. A residual row that is exactly zero is skipped (next unused row). Pivots
+    are taken by `_pivot` with a window of PIVOT_TIE times the largest |K_ij|.
     Returns U (m x k), V (n x k)."""
     m, n = kmat.shape
     us: List[np.ndarray] = []
     vs: List[np.ndarray] = []
     free = np.ones(m, dtype=bool)
+    window = PIVOT_TIE * float(np.abs(kmat).max()) if kmat.size else 0.0
     i = 0
     norm2 = 0.0
     while len(us) < min(m, n):
@@ -294,7 +299,7 @@ def aca(kmat: np.ndarray, tol: float):
         row = kmat[i].copy()
         for u, v in zip(us, vs):
             row -= u[i] * v
-        j, rmax = _pivot(row, np.ones(n, dtype=bool))
+        j, rmax = _pivot(row, np.ones(n, dtype=bool), window)
         if rmax == 0.0:
             if not free.any():
                 break
@@ -310,7 +315,7 @@ def aca(kmat: np.ndarray, tol: float):
         vs.append(v)
         if np.sqrt(float(u @ u) * float(v @ v)) <= tol * np.sqrt(norm2) or not free.any():
             break
-        i, _ = _pivot(u, free)
+        i, _ = _pivot(u, free, window)
     if not us:
         return np.zeros((m, 0)), np.zeros((n, 0))
     return np.stack(us, axis=1), np.stack(vs, axis=1)

@@ -11,9 +11,14 @@ REPS = sorted({O.symmetry(t, 3)[0] for t in O.far_transfer_vectors()})
 
 
 def test_pivot_ties_take_the_first_index():
-    assert O._pivot(np.array([1.0, -(1.0 - 1e-14), 0.5]), np.ones(3, bool))[0] == 0
-    assert O._pivot(np.array([0.5, 1.0 - 1e-9, -1.0]), np.ones(3, bool))[0] == 2
-    assert O._pivot(np.array([9.0, 1.0, 2.0]), np.array([False, True, True]))[0] == 2
+    ones = np.ones(3, bool)
+    assert O._pivot(np.array([1.0, -(1.0 - 1e-14), 0.5]), ones, 1e-12)[0] == 0
+    assert O._pivot(np.array([-(1.0 - 1e-14), 1.0, 0.5]), ones, 1e-12)[0] == 0
+    assert O._pivot(np.array([0.5, 1.0 - 1e-9, -1.0]), ones, 1e-12)[0] == 2
+    assert O._pivot(np.array([9.0, 1.0, 2.0]), np.array([False, True, True]), 1e-12)[0] == 2
+    # the window is absolute, but never more than half the largest candidate
+    assert O._pivot(np.array([1e-13, 3e-13, 0.0]), ones, 1e-12)[0] == 1
+    assert O._pivot(np.array([2e-13, 3e-13, 0.0]), ones, 1e-12)[0] == 0
 
 
 def test_aca_two_by_two_closed_form():
