@@ -82,6 +82,17 @@ typedef struct {
                                relative so that the top faces are inside */
 } bbfmm_tree_opts;
 
+/* Compressor of the low-rank operators (Sec. 5 studies both for the SA and IA variants). */
+typedef enum {
+  BBFMM_COMPRESS_SVD = 0, /* truncated SVD of each of the 16 operators (one-sided Jacobi) */
+  BBFMM_COMPRESS_ACA = 1  /* adaptive cross approximation with partial pivoting (Sec. 4.1) to
+                             1e-2 svd_eps, followed by a truncated SVD at svd_eps of the cross
+                             sum: linear in the operator size before the small SVD. The sum A is
+                             first replaced by (A + Q A^T Q^T) / 2 with Q the reflection that
+                             maps K_p to K_p^T, so that the operators of t and -t stay
+                             transposes (ACA's pivots depend on the row order) */
+} bbfmm_compressor;
+
 typedef struct {
   int32_t kernel;    /* bbfmm_kernel */
   double c;          /* regularisation of BBFMM_K_INV_SQRT_R2C2 (> 0), ignored otherwise */
@@ -90,6 +101,7 @@ typedef struct {
                         truncated to the singular values > svd_eps * sigma_1, extended over a
                         tied cluster at the cut (variant IAblk) */
   int32_t m2l_prec;  /* bbfmm_m2l_prec */
+  int32_t compressor; /* bbfmm_compressor, used when svd_eps > 0 (0 = truncated SVD) */
 } bbfmm_plan_opts;
 
 typedef struct {
@@ -139,11 +151,11 @@ bbfmm_status bbfmm_build_octree(const double* d_points, int64_t n, const bbfmm_t
 /* Precomputes the M2L operators of Sec. 3.1, Eq. (m2lmatrix) for the 16 transfer vectors of
  * T_sym (Eq. reduced_interaction_list) in FP64 on the host, at unit cell width for homogeneous
  * kernels (scaled per level, Sec. 3.2) or at every level's width otherwise; compresses each by
- * a truncated SVD when svd_eps > 0 (Eq. ialowrank); builds the per-octant interaction tables
+ * a truncated SVD, or ACA followed by a truncated SVD, when svd_eps > 0 (Eq. ialowrank); builds the per-octant interaction tables
  * (189 transfer vectors, their representative p(t) and permutation sigma_t, Eqs.
  * axial_permutation and diagonal_permutation) and the 1-D interpolation matrices of M2M/L2L;
  * uploads everything. `tree` is borrowed and must outlive the plan.
- * Errors: EINVAL (null, c <= 0 for INV_SQRT_R2C2, unknown kernel or precision),
+ * Errors: EINVAL (null, c <= 0 for INV_SQRT_R2C2, unknown kernel, precision or compressor),
  * EUNSUPPORTED (order outside [2, 8]). */
 bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts* opts,
                                   void* stream, bbfmm_plan** out);
@@ -266,11 +278,13 @@ bbfmm_status bbfmm_host_symmetry(int32_t order, const int32_t t[3], int32_t* out
 
 /* Host-only: the library's precomputed operator of representative `p` (0..15) at cell width
  * `width`: full matrix (l^3 x l^3 row-major) into out_k, and when svd_eps > 0 the factors
- * U (l^3 x r, = U_r Sigma_r) and V (l^3 x r) into out_u / out_v (each l^6 doubles capacity) with
- * the rank in *out_rank. */
+ * U (l^3 x r, = U_r Sigma_r) and V (l^3 x r) of `compressor` (bbfmm_compressor) into out_u /
+ * out_v (each l^6 doubles capacity) with the rank in *out_rank. Any out pointer may be null.
+ * Errors: EINVAL (unknown kernel or compressor, p outside [0, 16), width <= 0), EUNSUPPORTED
+ * (order outside [2, 8]). */
 bbfmm_status bbfmm_host_operator(int32_t kernel, double c, int32_t order, double width,
-                                 int32_t p, double svd_eps, double* out_k, double* out_u,
-                                 double* out_v, int32_t* out_rank);
+                                 int32_t p, double svd_eps, int32_t compressor, double* out_k,
+                                 double* out_u, double* out_v, int32_t* out_rank);
 
 /* Host-only: singular values of a row-major m x n matrix (m >= n) by the library's one-sided
  * Jacobi SVD, descending, into out_s (n doubles). */

@@ -11,6 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libbbfmm.so")
 
 KERNELS = {"inv_r": 0, "inv_sqrt_r2c2": 1, "r2": 100, "r4": 101}
+COMPRESSORS = {"svd": 0, "aca": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "split32": 2}
 PASS_NAMES = ("gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED", -5: "ESTATE"}
@@ -29,7 +30,7 @@ class TreeOpts(C.Structure):
 
 class PlanOpts(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("c", C.c_double), ("order", C.c_int32),
-                ("svd_eps", C.c_double), ("m2l_prec", C.c_int32)]
+                ("svd_eps", C.c_double), ("m2l_prec", C.c_int32), ("compressor", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -75,7 +76,7 @@ SIGNATURES = [
     ("bbfmm_debug_tree_order", C.c_int, [_P, _P, _P, _P]),
     ("bbfmm_host_symmetry", C.c_int, [C.c_int32, _P, _P, _P, _P]),
     ("bbfmm_host_operator", C.c_int, [C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_int32,
-                                      C.c_double, _P, _P, _P, _P]),
+                                      C.c_double, C.c_int32, _P, _P, _P, _P]),
     ("bbfmm_host_singular_values", C.c_int, [_P, C.c_int32, C.c_int32, _P]),
     ("bbfmm_m2l_unblocked", C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_int32, _P, _P]),
     ("bbfmm_adaptive_info_of", C.c_int, [_P, C.POINTER(AdaptiveInfo)]),
@@ -139,9 +140,10 @@ def build_octree(points, depth: int, root_lo=(0.0, 0.0, 0.0), root_width: float 
 
 
 def precompute_m2l(tree, kernel: str = "inv_r", order: int = 5, svd_eps: float = 0.0,
-                   m2l_prec: str = "fp64", c: float = 0.0, device=None):
+                   m2l_prec: str = "fp64", c: float = 0.0, device=None, compressor: str = "svd"):
     import torch
-    o = PlanOpts(KERNELS[kernel], float(c), int(order), float(svd_eps), PRECISIONS[m2l_prec])
+    o = PlanOpts(KERNELS[kernel], float(c), int(order), float(svd_eps), PRECISIONS[m2l_prec],
+                 COMPRESSORS[compressor])
     out = C.c_void_p()
     _check(lib().bbfmm_precompute_m2l(tree, C.byref(o), _P(_stream(torch, device)), C.byref(out)))
     return out
@@ -196,14 +198,15 @@ def host_symmetry(order: int, t):
     return reps, pidx.value, sig
 
 
-def host_operator(kernel: str, order: int, width: float, p: int, svd_eps: float = 0.0, c: float = 0.0):
+def host_operator(kernel: str, order: int, width: float, p: int, svd_eps: float = 0.0, c: float = 0.0,
+                  compressor: str = "svd"):
     nn = order ** 3
     k = np.zeros((nn, nn))
     u = np.zeros(nn * nn)
     v = np.zeros(nn * nn)
     r = C.c_int32()
     _check(lib().bbfmm_host_operator(KERNELS[kernel], float(c), order, float(width), p, float(svd_eps),
-                                     k.ctypes.data_as(_P), u.ctypes.data_as(_P), v.ctypes.data_as(_P),
+                                     COMPRESSORS[compressor], k.ctypes.data_as(_P), u.ctypes.data_as(_P), v.ctypes.data_as(_P),
                                      C.byref(r)))
     rr = r.value
     return k, u[:nn * rr].reshape(nn, rr), v[:nn * rr].reshape(nn, rr), rr
@@ -304,11 +307,11 @@ class Plan:
     """Owns a bbfmm_plan (operators + work buffers) on a tree."""
 
     def __init__(self, tree: Octree, kernel: str = "inv_r", order: int = 5, svd_eps: float = 0.0,
-                 m2l_prec: str = "fp64", c: float = 0.0):
+                 m2l_prec: str = "fp64", c: float = 0.0, compressor: str = "svd"):
         self.tree = tree            # keeps the tree alive
         self.order = order
         self.kernel = kernel
-        self.handle = precompute_m2l(tree.handle, kernel, order, svd_eps, m2l_prec, c, tree.device)
+        self.handle = precompute_m2l(tree.handle, kernel, order, svd_eps, m2l_prec, c, tree.device, compressor)
 
     def apply(self, q, out=None):
         return apply(self.handle, q, out)
@@ -366,10 +369,10 @@ class Plan:
 
 def fmm_apply(points, q, depth: int, order: int, kernel: str = "inv_r", svd_eps: float = 0.0,
               m2l_prec: str = "fp64", c: float = 0.0, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0,
-              max_leaf_points: int = 0):
+              max_leaf_points: int = 0, compressor: str = "svd"):
     """One-shot build_octree + precompute_m2l + apply."""
     tree = Octree(points, depth, root_lo, root_width, max_leaf_points)
-    plan = Plan(tree, kernel, order, svd_eps, m2l_prec, c)
+    plan = Plan(tree, kernel, order, svd_eps, m2l_prec, c, compressor)
     if q.dim() == 1:
         return plan.apply(q.reshape(-1, 1).contiguous()).reshape(-1)
     return plan.apply(q)

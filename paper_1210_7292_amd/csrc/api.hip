@@ -56,6 +56,20 @@ PassGeom geom_of(const bbfmm_plan* pl) {
 
 bool valid_kernel(int k) { return k == kInvR || k == kInvSqrtR2C2 || k == kR2 || k == kR4; }
 
+// Compressed factors of representative p's operator K (row-major l^3 x l^3) by the chosen
+// compressor; returns the rank.
+int compress_operator(const double* K, int order, int p, double eps, int compressor, std::vector<double>& uf,
+                      std::vector<double>& vf) {
+  const int nn = order * order * order;
+  if (compressor == BBFMM_COMPRESS_SVD) return compress_svd(K, nn, eps, uf, vf);
+  // Q with K_p^T = K_p[Q][:, Q]: the permutation of -t_p
+  const auto& t = representatives()[p];
+  const int mt[3] = {-t[0], -t[1], -t[2]};
+  std::vector<int32_t> q(nn);
+  sigma_table(order, symmetry_of(mt).perm_id, q.data());
+  return compress_aca(K, nn, q.data(), eps, uf, vf);
+}
+
 void free_buffers(bbfmm_plan* p) {
   dfree(p->W); p->W = nullptr;
   for (int s = 0; s < 2; ++s) {
@@ -628,6 +642,8 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
     return fail(BBFMM_EINVAL, "c must be finite and > 0 for 1/sqrt(r^2 + c^2)");
   if (opts->m2l_prec < 0 || opts->m2l_prec > 2) return fail(BBFMM_EINVAL, "unknown M2L precision");
   if (!std::isfinite(opts->svd_eps)) return fail(BBFMM_EINVAL, "svd_eps is not finite");
+  if (opts->compressor != BBFMM_COMPRESS_SVD && opts->compressor != BBFMM_COMPRESS_ACA)
+    return fail(BBFMM_EINVAL, "unknown compressor");
   if (opts->order < 2 || opts->order > kMaxOrder)
     return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
   if (tree->adaptive && tree->xs == nullptr)
@@ -662,20 +678,11 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
       K.resize((size_t)nn * nn);
       m2l_operator(p->kernel, p->c, L, wset, q, K.data());
       if (p->eps > 0) {
-        std::vector<double> U((size_t)nn * nn), S(nn), V((size_t)nn * nn);
-        jacobi_svd(K.data(), nn, nn, U.data(), S.data(), V.data());
-        const int r = truncation_rank(S.data(), nn, p->eps);
-        p->ranks[set * kNumSym + q] = r;
-        max_rank = std::max(max_rank, r);
         std::vector<double>& Uf = ufac[set * kNumSym + q];
         std::vector<double>& Vf = vfac[set * kNumSym + q];
-        Uf.assign((size_t)nn * r, 0.0);
-        Vf.assign((size_t)nn * r, 0.0);
-        for (int i = 0; i < nn; ++i)
-          for (int k = 0; k < r; ++k) {
-            Uf[(size_t)i * r + k] = U[(size_t)i * nn + k] * S[k];
-            Vf[(size_t)i * r + k] = V[(size_t)i * nn + k];
-          }
+        const int r = compress_operator(K.data(), L, q, p->eps, opts->compressor, Uf, Vf);
+        p->ranks[set * kNumSym + q] = r;
+        max_rank = std::max(max_rank, r);
         // truncated operator for the full-rank fallback
         for (int i = 0; i < nn; ++i)
           for (int jj = 0; jj < nn; ++jj) {
@@ -1265,26 +1272,24 @@ bbfmm_status bbfmm_host_symmetry(int32_t order, const int32_t t[3], int32_t* out
 }
 
 bbfmm_status bbfmm_host_operator(int32_t kernel, double c, int32_t order, double width, int32_t p,
-                                 double svd_eps, double* out_k, double* out_u, double* out_v,
-                                 int32_t* out_rank) {
+                                 double svd_eps, int32_t compressor, double* out_k, double* out_u,
+                                 double* out_v, int32_t* out_rank) {
   if (!valid_kernel(kernel)) return fail(BBFMM_EINVAL, "unknown kernel");
   if (order < 2 || order > kMaxOrder) return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
   if (p < 0 || p >= kNumSym) return fail(BBFMM_EINVAL, "p must be in [0, 16)");
   if (!(width > 0)) return fail(BBFMM_EINVAL, "width must be > 0");
+  if (compressor != BBFMM_COMPRESS_SVD && compressor != BBFMM_COMPRESS_ACA)
+    return fail(BBFMM_EINVAL, "unknown compressor");
   const int nn = order * order * order;
   std::vector<double> K((size_t)nn * nn);
   m2l_operator(kernel, c, order, width, p, K.data());
   if (out_k) std::memcpy(out_k, K.data(), K.size() * sizeof(double));
   if (svd_eps > 0) {
-    std::vector<double> U((size_t)nn * nn), S(nn), V((size_t)nn * nn);
-    jacobi_svd(K.data(), nn, nn, U.data(), S.data(), V.data());
-    const int r = truncation_rank(S.data(), nn, svd_eps);
+    std::vector<double> U, V;
+    const int r = compress_operator(K.data(), order, p, svd_eps, compressor, U, V);
     if (out_rank) *out_rank = r;
-    for (int i = 0; i < nn; ++i)
-      for (int k = 0; k < r; ++k) {
-        if (out_u) out_u[(size_t)i * r + k] = U[(size_t)i * nn + k] * S[k];
-        if (out_v) out_v[(size_t)i * r + k] = V[(size_t)i * nn + k];
-      }
+    if (out_u) std::memcpy(out_u, U.data(), U.size() * sizeof(double));
+    if (out_v) std::memcpy(out_v, V.data(), V.size() * sizeof(double));
   } else if (out_rank) {
     *out_rank = nn;
   }

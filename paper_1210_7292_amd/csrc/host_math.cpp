@@ -184,6 +184,193 @@ int truncation_rank(const double* s, int n, double eps) {
   return r;
 }
 
+void householder_qr(const double* a, int m, int n, double* q, double* r) {
+  // Column-major work copy; reflectors kept in the lower part, their scalars in beta.
+  std::vector<double> w((size_t)m * n), beta(n, 0.0), diag(n, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) w[(size_t)j * m + i] = a[(size_t)i * n + j];
+  for (int j = 0; j < n; ++j) {
+    double* col = &w[(size_t)j * m];
+    double norm2 = 0.0;
+    for (int i = j; i < m; ++i) norm2 += col[i] * col[i];
+    const double norm = std::sqrt(norm2);
+    if (norm == 0.0) {
+      diag[j] = 0.0;
+      continue;
+    }
+    const double alpha = col[j] >= 0.0 ? -norm : norm;
+    // v = x - alpha e_1 stored in col[j..m), H = I - beta v v^T
+    col[j] -= alpha;
+    const double vnorm2 = norm2 - 2.0 * alpha * (col[j] + alpha) + alpha * alpha;
+    beta[j] = vnorm2 > 0.0 ? 2.0 / vnorm2 : 0.0;
+    diag[j] = alpha;
+    for (int c = j + 1; c < n; ++c) {
+      double* cc = &w[(size_t)c * m];
+      double dot = 0.0;
+      for (int i = j; i < m; ++i) dot += col[i] * cc[i];
+      dot *= beta[j];
+      for (int i = j; i < m; ++i) cc[i] -= dot * col[i];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) r[(size_t)i * n + j] = j < i ? 0.0 : (j == i ? diag[i] : w[(size_t)j * m + i]);
+  // Q = H_0 H_1 ... H_{n-1} applied to the first n columns of the identity
+  std::vector<double> qc((size_t)m * n, 0.0);
+  for (int j = 0; j < n; ++j) qc[(size_t)j * m + j] = 1.0;
+  for (int h = n - 1; h >= 0; --h) {
+    if (beta[h] == 0.0) continue;
+    const double* v = &w[(size_t)h * m];
+    for (int c = 0; c < n; ++c) {
+      double* cc = &qc[(size_t)c * m];
+      double dot = 0.0;
+      for (int i = h; i < m; ++i) dot += v[i] * cc[i];
+      dot *= beta[h];
+      for (int i = h; i < m; ++i) cc[i] -= dot * v[i];
+    }
+  }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) q[(size_t)i * n + j] = qc[(size_t)j * m + i];
+}
+
+namespace {
+
+// First index among `allowed` whose |x| lies within min(window, m / 2) of the largest, m; -1 if
+// none. Mirror-image kernel entries are equal in exact arithmetic and a residual's rounding error
+// scales with the matrix's largest entry, so ties are judged on that scale (window).
+int tied_argmax(const double* x, int n, const std::vector<char>* allowed, double window, double* max_out) {
+  double m = -1.0;
+  for (int i = 0; i < n; ++i)
+    if (!allowed || (*allowed)[i]) m = std::max(m, std::fabs(x[i]));
+  *max_out = m;
+  if (m < 0.0) return -1;
+  const double cut = m - std::min(window, 0.5 * m);
+  for (int i = 0; i < n; ++i)
+    if ((!allowed || (*allowed)[i]) && std::fabs(x[i]) >= cut) return i;
+  return -1;
+}
+
+double dot(const double* a, const double* b, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+}  // namespace
+
+int aca_partial(const double* k, int n, double tol, std::vector<double>& u, std::vector<double>& v) {
+  u.clear();
+  v.clear();
+  std::vector<char> free_row(n, 1);
+  std::vector<double> row(n), col(n);
+  int nfree = n, i = 0, crosses = 0;
+  double norm2 = 0.0, kmax = 0.0;
+  for (size_t e = 0; e < (size_t)n * n; ++e) kmax = std::max(kmax, std::fabs(k[e]));
+  const double window = 1e-12 * kmax;
+  while (crosses < n) {
+    if (free_row[i]) {
+      free_row[i] = 0;
+      --nfree;
+    }
+    for (int j = 0; j < n; ++j) row[j] = k[(size_t)i * n + j];
+    for (int l = 0; l < crosses; ++l) {
+      const double ui = u[(size_t)l * n + i];
+      const double* vl = &v[(size_t)l * n];
+      for (int j = 0; j < n; ++j) row[j] -= ui * vl[j];
+    }
+    double rmax;
+    const int jp = tied_argmax(row.data(), n, nullptr, window, &rmax);
+    if (rmax == 0.0) {
+      if (nfree == 0) break;
+      i = (int)(std::find(free_row.begin(), free_row.end(), 1) - free_row.begin());
+      continue;
+    }
+    const double piv = row[jp];
+    for (int j = 0; j < n; ++j) row[j] /= piv;
+    for (int r = 0; r < n; ++r) col[r] = k[(size_t)r * n + jp];
+    for (int l = 0; l < crosses; ++l) {
+      const double vj = v[(size_t)l * n + jp];
+      const double* ul = &u[(size_t)l * n];
+      for (int r = 0; r < n; ++r) col[r] -= vj * ul[r];
+    }
+    const double uu = dot(col.data(), col.data(), n), vv = dot(row.data(), row.data(), n);
+    for (int l = 0; l < crosses; ++l)
+      norm2 += 2.0 * dot(col.data(), &u[(size_t)l * n], n) * dot(row.data(), &v[(size_t)l * n], n);
+    norm2 += uu * vv;
+    u.insert(u.end(), col.begin(), col.end());
+    v.insert(v.end(), row.begin(), row.end());
+    ++crosses;
+    if (std::sqrt(uu * vv) <= tol * std::sqrt(norm2) || nfree == 0) break;
+    double umax;
+    i = tied_argmax(col.data(), n, &free_row, window, &umax);
+  }
+  return crosses;
+}
+
+int compress_svd(const double* k, int n, double eps, std::vector<double>& uf, std::vector<double>& vf) {
+  std::vector<double> U((size_t)n * n), S(n), V((size_t)n * n);
+  jacobi_svd(k, n, n, U.data(), S.data(), V.data());
+  const int r = truncation_rank(S.data(), n, eps);
+  uf.assign((size_t)n * r, 0.0);
+  vf.assign((size_t)n * r, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < r; ++c) {
+      uf[(size_t)i * r + c] = U[(size_t)i * n + c] * S[c];
+      vf[(size_t)i * r + c] = V[(size_t)i * n + c];
+    }
+  return r;
+}
+
+int compress_aca(const double* k, int n, const int32_t* q, double eps, std::vector<double>& uf,
+                 std::vector<double>& vf) {
+  std::vector<double> cu, cv;
+  const int nc = aca_partial(k, n, kAcaRelTol * eps, cu, cv);
+  // A_s = 1/2 [U, V_Q] [V, U_Q]^T with U_Q[i] = U[Q(i)] (row-major n x 2nc factors)
+  const int m2 = 2 * nc;
+  if (m2 == 0) {
+    uf.clear();
+    vf.clear();
+    return 0;
+  }
+  std::vector<double> fa((size_t)n * m2), fb((size_t)n * m2);
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < nc; ++l) {
+      fa[(size_t)i * m2 + l] = cu[(size_t)l * n + i];
+      fa[(size_t)i * m2 + nc + l] = cv[(size_t)l * n + q[i]];
+      fb[(size_t)i * m2 + l] = 0.5 * cv[(size_t)l * n + i];
+      fb[(size_t)i * m2 + nc + l] = 0.5 * cu[(size_t)l * n + q[i]];
+    }
+  if (m2 >= n) {
+    // as many factor columns as rows: truncate the dense sum directly
+    std::vector<double> a((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) a[(size_t)i * n + j] = dot(&fa[(size_t)i * m2], &fb[(size_t)j * m2], m2);
+    return compress_svd(a.data(), n, eps, uf, vf);
+  }
+  std::vector<double> qa((size_t)n * m2), ra((size_t)m2 * m2), qb((size_t)n * m2), rb((size_t)m2 * m2);
+  householder_qr(fa.data(), n, m2, qa.data(), ra.data());
+  householder_qr(fb.data(), n, m2, qb.data(), rb.data());
+  // core C = Ra Rb^T, C = X Sigma Y^T, A_s = (Qa X) Sigma (Qb Y)^T
+  std::vector<double> core((size_t)m2 * m2);
+  for (int i = 0; i < m2; ++i)
+    for (int j = 0; j < m2; ++j) core[(size_t)i * m2 + j] = dot(&ra[(size_t)i * m2], &rb[(size_t)j * m2], m2);
+  std::vector<double> X((size_t)m2 * m2), S(m2), Y((size_t)m2 * m2);
+  jacobi_svd(core.data(), m2, m2, X.data(), S.data(), Y.data());
+  const int r = truncation_rank(S.data(), m2, eps);
+  uf.assign((size_t)n * r, 0.0);
+  vf.assign((size_t)n * r, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < r; ++c) {
+      double a = 0.0, b = 0.0;
+      for (int l = 0; l < m2; ++l) {
+        a += qa[(size_t)i * m2 + l] * X[(size_t)l * m2 + c];
+        b += qb[(size_t)i * m2 + l] * Y[(size_t)l * m2 + c];
+      }
+      uf[(size_t)i * r + c] = a * S[c];
+      vf[(size_t)i * r + c] = b;
+    }
+  return r;
+}
+
 void octant_table(int octant, int32_t* entries, int32_t* group_start) {
   const int o[3] = {octant & 1, (octant >> 1) & 1, (octant >> 2) & 1};
   struct E { int d[3]; int p; int perm; int order; };

@@ -55,6 +55,31 @@ void jacobi_svd(const double* a, int m, int n, double* u, double* s, double* v);
 // Rank rule: count of s_k > eps * s_0, extended over values within 1e-10 * s_0 of the last kept.
 int truncation_rank(const double* s, int n, double eps);
 
+// Householder QR of a row-major m x n matrix (m >= n): A = Q R with Q m x n (orthonormal
+// columns) and R n x n upper triangular, both row-major. Rank-deficient input is fine.
+void householder_qr(const double* a, int m, int n, double* q, double* r);
+
+// Adaptive cross approximation with partial pivoting of a row-major n x n matrix (Sec. 4.1 and
+// Sec. 5 name ACA as the faster replacement of the SVD): crosses u_k, v_k (each n doubles,
+// appended to u and v) with K ~ sum_k u_k v_k^T. Pivot row first 0, then the largest |u_k(i)|
+// over unused rows; pivot column the largest entry of the residual row; candidates within
+// 1e-12 max|K| (at most half the largest) of the largest count as tied and the first index wins.
+// Stops when
+// ||u_k|| ||v_k|| <= tol ||S_k||_F (S_k the sum so far) or when every row has been used; a
+// residual row that is exactly zero is skipped. Returns the number of crosses.
+int aca_partial(const double* k, int n, double tol, std::vector<double>& u, std::vector<double>& v);
+
+// Compressed operator K ~ Uf Vf^T (row-major n x r each, Uf = U_r Sigma_r, Vf = V_r); returns r.
+// Truncated SVD of K (Eq. ialowrank):
+int compress_svd(const double* k, int n, double eps, std::vector<double>& uf, std::vector<double>& vf);
+// ACA (tolerance 1e-2 eps) followed by a truncated SVD at eps. The ACA sum A is first made
+// consistent with the exact operator's K^T = K[Q][:, Q] (q: the involution Q, n entries) as
+// (A[i][j] + A[Q(j)][Q(i)]) / 2, so that the compressed operators of t and -t stay transposes;
+// the SVD of that rank-2k sum is taken from the QR factors of its two factor matrices.
+int compress_aca(const double* k, int n, const int32_t* q, double eps, std::vector<double>& uf,
+                 std::vector<double>& vf);
+constexpr double kAcaRelTol = 1e-2;
+
 // Far-field table of a target octant (x bit 0, y bit 1, z bit 2): the 189 source offsets
 // d = Y - X (cell units) whose source is a child of a neighbour of the target's parent and not a
 // neighbour of the target, sorted by representative (stable). Each entry packs

@@ -152,6 +152,49 @@ def test_apply_matches_oracle(name, n, nrhs, order, depth, kind, c, eps, prec, t
     assert err < tol
 
 
+ACA_CASES = [
+    # name, n, nrhs, order, depth, kernel, c, eps, prec, tol
+    ("aca_p5_d3", 4000, 2, 5, 3, "inv_r", 0.0, 1e-5, "fp64", 1e-12),
+    ("aca_p5_d5_split", 40000, 1, 5, 5, "inv_r", 0.0, 1e-5, "fp64", 1e-12),
+    ("aca_soft_p4_d4", 3000, 1, 4, 4, "inv_sqrt_r2c2", 1e-3, 1e-6, "fp64", 1e-12),
+    ("aca_p7_d3", 2000, 1, 7, 3, "inv_r", 0.0, 1e-7, "fp64", 1e-12),
+    ("aca_p5_d3_fp32", 4000, 1, 5, 3, "inv_r", 0.0, 1e-5, "fp32", 1e-6),
+]
+
+
+@pytest.mark.parametrize("name,n,nrhs,order,depth,kind,c,eps,prec,tol", ACA_CASES, ids=[x[0] for x in ACA_CASES])
+def test_apply_with_aca_compression_matches_oracle(name, n, nrhs, order, depth, kind, c, eps, prec, tol):
+    """ACA + truncated SVD operators (host precompute) against the oracle's ACA compressor."""
+    say("apply aca", name)
+    pts, q = cube(n, nrhs, zlib.crc32(name.encode()) % 1000)
+    tree = pk.Octree(dev(pts), depth)
+    plan = pk.Plan(tree, kind, order, eps, prec, c, "aca")
+    phi = host(plan.apply(dev(q)))
+    ref = O.fmm_apply(pts, q, order, depth, kind, c, eps, compressor="aca").phi
+    err = rel(phi, ref)
+    say("  rel err", err, "ranks", plan.stats()["rank"][:4])
+    assert err < tol
+    if prec == "fp64" and order <= 5:
+        svd = O.fmm_apply(pts, q, order, depth, kind, c, eps).phi
+        assert rel(phi, svd) < 10 * eps
+
+
+def test_aca_adjoint_and_gradient_match_oracle():
+    say("adjoint/grad aca")
+    rng = np.random.default_rng(14)
+    n, order, depth, eps = 1500, 4, 3, 1e-5
+    pts = rng.uniform(0.0, 1.0, (n, 3))
+    q, g = rng.uniform(-1, 1, (n, 1)), rng.uniform(-1, 1, (n, 1))
+    tree = pk.Octree(dev(pts), depth)
+    plan = pk.Plan(tree, "inv_r", order, eps, "fp64", 0.0, "aca")
+    dq, dg = dev(q), dev(g)
+    plan.apply(dq)
+    atg = host(plan.apply_adjoint(dg))
+    assert rel(atg, O.fmm_adjoint(pts, g, order, depth, eps=eps, compressor="aca")) < 1e-12
+    grad = host(plan.eval_grad(dq, dg, 3))
+    assert rel(grad, O.fmm_grad_points(pts, q, g, order, depth, eps=eps, compressor="aca")) < 1e-11
+
+
 def test_passes_match_oracle():
     say("passes")
     pts, q = cube(3000, 2, 5)

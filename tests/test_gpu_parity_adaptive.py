@@ -115,6 +115,17 @@ def test_adaptive_apply_matches_oracle(name, geo, n, m, order, kind, c, eps, pre
     assert err < tol
 
 
+def test_adaptive_apply_with_aca_compression_matches_oracle():
+    pts = points_of("clustered", 1500, 5)
+    q = np.random.default_rng(6).uniform(-1, 1, (1500, 2))
+    ref, _ = A.fmm_apply(pts, q, 5, 16, "inv_r", 0.0, eps=1e-5, compressor="aca")
+    tree = pk.Octree(dev(pts), -1, root_width=0.0, max_leaf_points=16)
+    plan = pk.Plan(tree, "inv_r", 5, 1e-5, "fp64", 0.0, "aca")
+    err = rel(host(plan.apply(dev(q))), ref)
+    say("  adaptive aca rel err vs oracle", err)
+    assert err < 1e-12
+
+
 @pytest.mark.parametrize("kind,order", [("r2", 3), ("r4", 5)])
 def test_adaptive_polynomial_kernel_equals_brute_force(kind, order):
     pts = points_of("clustered", 1200, 8)

@@ -65,6 +65,41 @@ def test_host_compression_matches_oracle(order, eps):
         assert np.max(np.abs(u @ v.T - uo @ vo.T)) <= 1e-13 * so[0]
 
 
+@pytest.mark.parametrize("order,eps,kind,c,width", [(3, 1e-3, "inv_r", 0.0, 1.0), (5, 1e-5, "inv_r", 0.0, 1.0),
+                                                    (6, 1e-7, "inv_r", 0.0, 1.0),
+                                                    (4, 1e-5, "inv_sqrt_r2c2", 1e-3, 1 / 64),
+                                                    (8, 1e-5, "inv_r", 0.0, 1.0)])
+def test_host_aca_compression_matches_oracle(order, eps, kind, c, width):
+    """ACA + truncated SVD of the library (QR recompression) against the oracle's (dense SVD of
+    the symmetrised cross sum): same pivots, same rank, same truncated operator."""
+    reps, _, _ = pk.host_symmetry(order, (2, 0, 0))
+    for p, t in enumerate(reps[:4] if order == 8 else reps):
+        k, u, v, r = pk.host_operator(kind, order, width, p, eps, c, "aca")
+        q = O.transpose_permutation(t, order)
+        uo, vo, so = O.compress_aca(O.m2l_operator(t, width, order, kind, c), eps, q)
+        assert r == uo.shape[1], (t, r, uo.shape[1])
+        a = u @ v.T
+        assert np.max(np.abs(a - uo @ vo.T)) <= 1e-13 * so[0]
+        # the transposition the recompression keeps, and the distance to the plain SVD's operator
+        assert np.max(np.abs(a.T - a[np.ix_(q, q)])) <= 1e-14 * so[0]
+        if order == 8 and p > 0:
+            continue        # the plain SVD takes seconds per operator at order 8
+        _, us, vs, rs = pk.host_operator(kind, order, width, p, eps, c, "svd")
+        assert rs == r
+        assert np.linalg.norm(a - us @ vs.T) <= 0.5 * eps * np.linalg.norm(k)
+
+
+def test_host_qr_handles_rank_deficient_factors():
+    # the symmetrised cross sum has nearly dependent factor columns; QR must stay orthonormal:
+    # checked through the compression of an exactly rank-1 operator-like matrix
+    lib = pk.lib()
+    assert lib is not None
+    k, u, v, r = pk.host_operator("r2", 3, 1.0, 0, 1e-8, 0.0, "aca")
+    # r^2 = |x|^2 - 2 x.y + |y|^2 has rank 5 as a bilinear form
+    assert r == 5
+    assert np.max(np.abs(u @ v.T - k)) <= 1e-12 * np.abs(k).max()
+
+
 def test_jacobi_svd_against_lapack():
     rng = np.random.default_rng(0)
     for m, n in [(7, 7), (40, 25), (125, 125)]:
@@ -95,5 +130,7 @@ def test_validation_without_gpu():
     t = (C.c_int32 * 3)(1, 0, 0)
     assert lib.bbfmm_host_symmetry(4, t, None, None, None) == -1      # near-field vector
     k = np.zeros(64 * 64)
-    assert lib.bbfmm_host_operator(7, 0.0, 4, 1.0, 0, 0.0, k.ctypes.data_as(C.c_void_p), None, None, None) == -1
-    assert lib.bbfmm_host_operator(0, 0.0, 4, 1.0, 16, 0.0, k.ctypes.data_as(C.c_void_p), None, None, None) == -1
+    assert lib.bbfmm_host_operator(7, 0.0, 4, 1.0, 0, 0.0, 0, k.ctypes.data_as(C.c_void_p), None, None, None) == -1
+    assert lib.bbfmm_host_operator(0, 0.0, 4, 1.0, 16, 0.0, 0, k.ctypes.data_as(C.c_void_p), None, None, None) == -1
+    assert lib.bbfmm_host_operator(0, 0.0, 4, 1.0, 0, 1e-5, 2, k.ctypes.data_as(C.c_void_p), None, None, None) == -1
+    assert b"compressor" in lib.bbfmm_last_error()
