@@ -131,7 +131,7 @@ def run_ablation(torch, np, pk, tree, plan, w, level, stream, reps=3):
     return res
 
 
-def cpu_baseline(w, inp, sample_n, grad_mode=False):
+def cpu_baseline(w, inp, sample_n, grad_mode=False, compressor="svd"):
     """The oracle (as it stands) on a bounded sample of the same workload, on the host cores."""
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -143,10 +143,11 @@ def cpu_baseline(w, inp, sample_n, grad_mode=False):
     pts = inp.points[:n]
     q = inp.q[:n]
     t0 = time.perf_counter()
-    O.fmm_apply(pts, q, w.order, depth, w.kernel, w.c, w.svd_eps)
+    O.fmm_apply(pts, q, w.order, depth, w.kernel, w.c, w.svd_eps, compressor=compressor)
     if grad_mode:
-        O.fmm_adjoint(pts, inp.g[:n], w.order, depth, w.kernel, w.c, w.svd_eps)
-        O.fmm_grad_points(pts, q, inp.g[:n], w.order, depth, w.kernel, w.c, w.svd_eps)
+        O.fmm_adjoint(pts, inp.g[:n], w.order, depth, w.kernel, w.c, w.svd_eps, compressor=compressor)
+        O.fmm_grad_points(pts, q, inp.g[:n], w.order, depth, w.kernel, w.c, w.svd_eps,
+                          compressor=compressor)
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     return {"value": n / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
@@ -154,7 +155,7 @@ def cpu_baseline(w, inp, sample_n, grad_mode=False):
                       f"one oracle {'apply + adjoint + gradient' if grad_mode else 'fmm_apply'} in {dt:.2f} s"}
 
 
-def cpu_baseline_adaptive(w, inp, sample_n):
+def cpu_baseline_adaptive(w, inp, sample_n, compressor="svd"):
     """The adaptive oracle on an evenly strided sample of the workload's points (both parts of
     the cloud), same order, leaf size, kernel and right-hand sides."""
     import numpy as np
@@ -165,7 +166,8 @@ def cpu_baseline_adaptive(w, inp, sample_n):
     pts = inp.points[::stride][:sample_n]
     q = inp.q[::stride][:sample_n]
     t0 = time.perf_counter()
-    _, tree = A.fmm_apply(pts, q, w.order, w.max_leaf_points, w.kernel, w.c, eps=w.svd_eps)
+    _, tree = A.fmm_apply(pts, q, w.order, w.max_leaf_points, w.kernel, w.c, eps=w.svd_eps,
+                          compressor=compressor)
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     n = pts.shape[0]
@@ -187,6 +189,8 @@ def main():
                     help="also time the other M2L precisions and report their errors vs this one")
     ap.add_argument("--ablation", type=int, default=0, metavar="LEVEL",
                     help="also time the M2L of LEVEL with the unblocked variants (NA, NAsym, IA, IAsym)")
+    ap.add_argument("--compressor", default="svd", choices=("svd", "aca"),
+                    help="compressor of the operators when the workload compresses them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -231,7 +235,7 @@ def main():
         tree = pk.Octree(pts, w.depth)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
-    plan = pk.Plan(tree, w.kernel, w.order, w.svd_eps, prec, w.c)
+    plan = pk.Plan(tree, w.kernel, w.order, w.svd_eps, prec, w.c, args.compressor)
     st = plan.stats()
     log(f"[bench] tree {build_ms:.1f} ms, precompute {st['precompute_seconds']:.2f} s, ranks {st['rank']}")
     tree_info = tree.arrays()["info"] if adaptive else None
@@ -311,7 +315,7 @@ def main():
         for other in ("fp64", "fp32", "split32"):
             if other == prec:
                 continue
-            p2 = pk.Plan(tree, w.kernel, w.order, w.svd_eps, other, w.c)
+            p2 = pk.Plan(tree, w.kernel, w.order, w.svd_eps, other, w.c, args.compressor)
             o2 = torch.empty_like(q)
             p2.apply(q, o2)
             torch.cuda.synchronize()
@@ -346,11 +350,11 @@ def main():
         if adaptive:
             n_cpu = args.cpu_sample or 5_000
             log(f"[bench] adaptive oracle on {n_cpu} points (host cores)")
-            cpu = cpu_baseline_adaptive(w, inp, n_cpu)
+            cpu = cpu_baseline_adaptive(w, inp, n_cpu, args.compressor)
         else:
             n_cpu = args.cpu_sample or (20_000 if w.order >= 7 else 100_000)
             log(f"[bench] oracle on {n_cpu} points (host cores)")
-            cpu = cpu_baseline(w, inp, n_cpu, grad_mode)
+            cpu = cpu_baseline(w, inp, n_cpu, grad_mode, args.compressor)
         log(f"[bench] oracle: {cpu['value']:.3e} points/s")
 
     # HBM traffic of the M2L launch from the committed rocprofv3 counters, only while the kernel
@@ -383,7 +387,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_points": w.n, "kernel": KERNEL_NAMES[w.kernel], "c": w.c,
                    "order": w.order, "depth": w.depth, "nrhs": w.nrhs, "svd_eps": w.svd_eps,
-                   "m2l_prec": prec, "m2l_variant": variant},
+                   "m2l_prec": prec, "m2l_variant": variant,
+                   "compressor": args.compressor if w.svd_eps > 0 else None},
         "m2l_gflops": achieved * 1e3,
         "rel_l2_err_vs_direct": err,
         "passes_ms_per_call": per,
