@@ -19,6 +19,9 @@ interpolation based fast multipole method"):
 * Sec. 4.2, Eq. (ialowrank): individual truncated-SVD low rank K_t ~ U_t V_t^T — `compress`.
 * Sec. 4.1 and Sec. 5 (the compressors of SA and IA): adaptive cross approximation followed by a
   truncated SVD — `aca`, `compress_aca`, `compressed_operator(..., "aca")`.
+* Sec. 4.1, Eqs. (2bigsvds), (ucb_no_compression), (recompression): the single low-rank
+  approximation SA and its recompressed form SArcmp — `sa_basis`, `sa_operator`,
+  `compressed_operator(..., "sa" | "sarcmp")`.
 * Sec. 4.2.1, Eqs. (axial_permutation), (diagonal_permutation), (permutations): the
   symmetry tables, used only by the invariant tests — `symmetry`.
 
@@ -45,6 +48,9 @@ Readings taken where the paper is silent, ambiguous or garbled:
     t by sigma_t; before the truncated SVD the approximation is made to satisfy the exact
     operator's K_p^T = K_p[Q][:, Q] (Q = sigma of -t_p), which keeps K_{-t} = K_t^T and with it
     A^T = A.
+ 8. SA / SArcmp: B = U (K^(col)'s right singular vectors span K^(row)'s left ones for the
+    symmetric kernels here); C_t = U^T K_t U; the recompression truncates each C_t by the rule
+    of 5 relative to C_t's own largest singular value and is kept only when r_t < r/2.
 """
 from __future__ import annotations
 
@@ -346,7 +352,11 @@ def compressed_operator(t, width: float, order: int, kind: str, c: float, eps: f
     """(U_t, V_t) with K_t ~ U_t V_t^T. "svd": truncated SVD of K_t itself. "aca": ACA + SVD of
     the representative K_p (Eq. reduced_interaction_list), mapped to t by its permutation,
     U_t = U_p[sigma_t], V_t = V_p[sigma_t] (ACA's pivots depend on the row order, so the
-    compressed family is defined on the 16 representatives, as the symmetric variants use it)."""
+    compressed family is defined on the 16 representatives, as the symmetric variants use it).
+    "sa" / "sarcmp": the single low-rank approximation of Sec. 4.1, without / with the
+    recompression of each C_t (`sa_operator`)."""
+    if compressor in ("sa", "sarcmp"):
+        return sa_operator(t, width, order, kind, c, eps, compressor == "sarcmp")
     if compressor == "svd":
         u, v, _ = compress(m2l_operator(t, width, order, kind, c), eps)
         return u, v
@@ -355,6 +365,32 @@ def compressed_operator(t, width: float, order: int, kind: str, c: float, eps: f
     p, sigma = symmetry(t, order)
     u, v = _aca_representative(p, float(width), order, kind, float(c), float(eps))
     return u[sigma], v[sigma]
+
+
+@functools.lru_cache(maxsize=32)
+def sa_basis(width: float, order: int, kind: str, c: float, eps: float) -> np.ndarray:
+    """SA (Sec. 4.1, Eq. 2bigsvds): U from the truncated SVD of K^(row) = [K_1, ..., K_|T|] over
+    the 316 far-field transfer vectors of a level. For the symmetric kernels here K_{-t} = K_t^T
+    and T = -T, so K^(col)^T K^(col) = K^(row) K^(row)^T and K^(col)'s right singular vectors B
+    span the same space: B = U."""
+    krow = np.concatenate([m2l_operator(t, width, order, kind, c) for t in far_transfer_vectors()], axis=1)
+    u, s, _ = np.linalg.svd(krow, full_matrices=False)
+    return u[:, :rank_of(s, eps)].copy()
+
+
+def sa_operator(t, width: float, order: int, kind: str, c: float, eps: float, recompress: bool):
+    """(U_t, V_t) with K_t ~ U_t V_t^T for SA and SArcmp: K_t ~ U C_t U^T with
+    C_t = U^T K_t U (Eq. ucb_no_compression, B = U); SArcmp replaces C_t by its truncated SVD
+    Ubar_t Vbar_t^T when that rank r_t satisfies r_t < r/2 (Eq. recompression; the truncation
+    rule is `rank_of` relative to C_t's largest singular value)."""
+    u = sa_basis(float(width), order, kind, float(c), float(eps))
+    core = u.T @ m2l_operator(t, width, order, kind, c) @ u
+    if recompress:
+        uc, sc, vct = np.linalg.svd(core)
+        rt = rank_of(sc, eps)
+        if rt < core.shape[0] / 2:
+            return u @ (uc[:, :rt] * sc[:rt]), u @ vct[:rt].T
+    return u @ core, u.copy()
 
 
 @functools.lru_cache(maxsize=256)
