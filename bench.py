@@ -191,6 +191,9 @@ def main():
                     help="also time the M2L of LEVEL with the unblocked variants (NA, NAsym, IA, IAsym)")
     ap.add_argument("--compressor", default="svd", choices=("svd", "aca"),
                     help="compressor of the operators when the workload compresses them")
+    ap.add_argument("--variant", default="blocked", choices=("blocked", "sa", "sarcmp"),
+                    help="M2L variant: symmetry-blocked (default), or SA / SArcmp (compressed "
+                         "uniform workloads, FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -235,7 +238,7 @@ def main():
         tree = pk.Octree(pts, w.depth)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
-    plan = pk.Plan(tree, w.kernel, w.order, w.svd_eps, prec, w.c, args.compressor)
+    plan = pk.Plan(tree, w.kernel, w.order, w.svd_eps, prec, w.c, args.compressor, args.variant)
     st = plan.stats()
     log(f"[bench] tree {build_ms:.1f} ms, precompute {st['precompute_seconds']:.2f} s, ranks {st['rank']}")
     tree_info = tree.arrays()["info"] if adaptive else None
@@ -354,7 +357,8 @@ def main():
         else:
             n_cpu = args.cpu_sample or (20_000 if w.order >= 7 else 100_000)
             log(f"[bench] oracle on {n_cpu} points (host cores)")
-            cpu = cpu_baseline(w, inp, n_cpu, grad_mode, args.compressor)
+            cpu = cpu_baseline(w, inp, n_cpu, grad_mode,
+                               args.variant if args.variant != "blocked" else args.compressor)
         log(f"[bench] oracle: {cpu['value']:.3e} points/s")
 
     # HBM traffic of the M2L launch from the committed rocprofv3 counters, only while the kernel
@@ -365,12 +369,12 @@ def main():
         t = json.load(open(os.path.join(ROOT, "profiles", "m2l_traffic.json")))
         src = open(os.path.join(ROOT, t["source"]), "rb").read()
         if (hashlib.sha256(src).hexdigest() == t["sha256"] and t["workload"] == w.name
-                and prec == "fp64"):
+                and prec == "fp64" and args.variant == "blocked"):
             traffic = t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         traffic = None
 
-    variant = ("IAblk" if w.svd_eps > 0 else "NAblk")
+    variant = {"sa": "SA", "sarcmp": "SArcmp"}.get(args.variant, "IAblk" if w.svd_eps > 0 else "NAblk")
     line = {
         "metric": "FMM points/sec of one apply (bbFMM, symmetry-blocked M2L), with M2L TFLOP/s vs "
                   "MFMA peak and rel. L2 error",

@@ -93,6 +93,20 @@ typedef enum {
                              transposes (ACA's pivots depend on the row order) */
 } bbfmm_compressor;
 
+/* How the far-field operators are stored and applied (Sec. 4 and Sec. 5's variant list). */
+typedef enum {
+  BBFMM_VARIANT_BLOCKED = 0, /* the 16 operators of T_sym, applied blocked by representative
+                                (Alg. BlockedM2L): NAblk for svd_eps <= 0, IAblk otherwise */
+  BBFMM_VARIANT_SA = 1,      /* single low-rank approximation (Sec. 4.1, Eq. ucb_no_compression):
+                                one basis U per operator set from the truncated SVD of
+                                [K_1, ..., K_316] at svd_eps, K_t ~ U C_t U^T with the 316 r x r
+                                cores C_t = U^T K_t U; per level What = U^T W, Fhat = sum C_t What,
+                                F = U Fhat. For these symmetric kernels K^(col)'s basis B equals U */
+  BBFMM_VARIANT_SARCMP = 2   /* SA with each C_t replaced by its truncated SVD at svd_eps (relative
+                                to C_t's largest singular value) when that rank r_t < r/2
+                                (Eq. recompression) */
+} bbfmm_variant;
+
 typedef struct {
   int32_t kernel;    /* bbfmm_kernel */
   double c;          /* regularisation of BBFMM_K_INV_SQRT_R2C2 (> 0), ignored otherwise */
@@ -101,7 +115,12 @@ typedef struct {
                         truncated to the singular values > svd_eps * sigma_1, extended over a
                         tied cluster at the cut (variant IAblk) */
   int32_t m2l_prec;  /* bbfmm_m2l_prec */
-  int32_t compressor; /* bbfmm_compressor, used when svd_eps > 0 (0 = truncated SVD) */
+  int32_t compressor; /* bbfmm_compressor, used when svd_eps > 0 (0 = truncated SVD); the SA
+                         variants always take their basis from an SVD */
+  int32_t variant;    /* a bbfmm_variant, 0 = blocked. The SA variants need svd_eps > 0, a uniform
+                         tree and FP64 M2L (EINVAL / EUNSUPPORTED otherwise) and a basis rank of
+                         at most 192; their precompute stacks the 316 operators (Householder QR of
+                         316 l^3 x l^3 values, seconds at order 5-6) */
 } bbfmm_plan_opts;
 
 typedef struct {
@@ -114,10 +133,15 @@ typedef struct {
                                            (adaptive: the V-list pairs) */
   int64_t pairs_nonempty;               /* ... of which both cells hold points (plan_stats only) */
   double m2l_flops_algorithmic;         /* per right-hand side: sum over non-empty pairs of
-                                           2 l^6 (full) or 4 l^3 r_p (compressed) */
+                                           2 l^6 (full) or 4 l^3 r_p (compressed); SA variants:
+                                           over all in-box pairs, 2 r^2 (core kept) or 4 r r_t,
+                                           plus 4 l^3 r per cell (projection, expansion) */
   double m2l_flops_issued;              /* per right-hand side, MFMA work including padding */
   double precompute_seconds;            /* host time of bbfmm_precompute_m2l */
   int64_t device_bytes;                 /* device memory held by tree + plan */
+  int32_t variant;                      /* bbfmm_variant of the plan */
+  int32_t sa_rank;                      /* SA variants: rank r of the basis (first operator set) */
+  double sa_mean_core_rank;             /* SA variants: mean rank of the 316 cores (r where kept) */
 } bbfmm_stats;
 
 typedef struct bbfmm_tree bbfmm_tree;
@@ -285,6 +309,17 @@ bbfmm_status bbfmm_host_symmetry(int32_t order, const int32_t t[3], int32_t* out
 bbfmm_status bbfmm_host_operator(int32_t kernel, double c, int32_t order, double width,
                                  int32_t p, double svd_eps, int32_t compressor, double* out_k,
                                  double* out_u, double* out_v, int32_t* out_rank);
+
+/* Host-only: the library's SA (recompress = 0) or SArcmp (recompress != 0) operator of the far-field
+ * transfer vector t (|t_i| <= 3, max |t_i| >= 2) at cell width `width`, as full-space factors
+ * K_t ~ U_t V_t^T: U_t = U C_t and V_t = U when the core is kept (r_t = r), U_t = U Ubar_t and
+ * V_t = U Vbar_t when recompressed. out_u, out_v: l^3 x r_t row-major (capacity l^3 x l^3 each,
+ * may be null); *out_rank_t = r_t, *out_r = r (may be null). Recomputes the whole basis per call.
+ * Errors: EINVAL (unknown kernel, width or svd_eps <= 0, t null or not far-field), EUNSUPPORTED
+ * (order outside [2, 8]). */
+bbfmm_status bbfmm_host_sa_operator(int32_t kernel, double c, int32_t order, double width, double svd_eps,
+                                    int32_t recompress, const int32_t t[3], double* out_u, double* out_v,
+                                    int32_t* out_rank_t, int32_t* out_r);
 
 /* Host-only: singular values of a row-major m x n matrix (m >= n) by the library's one-sided
  * Jacobi SVD, descending, into out_s (n doubles). */

@@ -9,8 +9,10 @@ from __future__ import annotations
 
 from .binding import (  # noqa: F401
     BBFMMError,
+    COMPRESSORS,
     KERNELS,
     PRECISIONS,
+    VARIANTS,
     Octree,
     Plan,
     apply,
@@ -19,6 +21,7 @@ from .binding import (  # noqa: F401
     eval_grad,
     fmm_apply,
     host_operator,
+    host_sa_operator,
     host_singular_values,
     host_symmetry,
     lib,

@@ -12,6 +12,7 @@ _LIB_PATH = os.path.join(_HERE, "libbbfmm.so")
 
 KERNELS = {"inv_r": 0, "inv_sqrt_r2c2": 1, "r2": 100, "r4": 101}
 COMPRESSORS = {"svd": 0, "aca": 1}
+VARIANTS = {"blocked": 0, "sa": 1, "sarcmp": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "split32": 2}
 PASS_NAMES = ("gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED", -5: "ESTATE"}
@@ -30,7 +31,8 @@ class TreeOpts(C.Structure):
 
 class PlanOpts(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("c", C.c_double), ("order", C.c_int32),
-                ("svd_eps", C.c_double), ("m2l_prec", C.c_int32), ("compressor", C.c_int32)]
+                ("svd_eps", C.c_double), ("m2l_prec", C.c_int32), ("compressor", C.c_int32),
+                ("variant", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -39,7 +41,8 @@ class Stats(C.Structure):
                 ("rank", C.c_int32 * 16), ("root_lo", C.c_double * 3), ("root_width", C.c_double),
                 ("pairs_total", C.c_int64), ("pairs_nonempty", C.c_int64),
                 ("m2l_flops_algorithmic", C.c_double), ("m2l_flops_issued", C.c_double),
-                ("precompute_seconds", C.c_double), ("device_bytes", C.c_int64)]
+                ("precompute_seconds", C.c_double), ("device_bytes", C.c_int64),
+                ("variant", C.c_int32), ("sa_rank", C.c_int32), ("sa_mean_core_rank", C.c_double)]
 
 
 class AdaptiveInfo(C.Structure):
@@ -78,6 +81,8 @@ SIGNATURES = [
     ("bbfmm_host_operator", C.c_int, [C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_int32,
                                       C.c_double, C.c_int32, _P, _P, _P, _P]),
     ("bbfmm_host_singular_values", C.c_int, [_P, C.c_int32, C.c_int32, _P]),
+    ("bbfmm_host_sa_operator", C.c_int, [C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                         _P, _P, _P, _P, _P]),
     ("bbfmm_m2l_unblocked", C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_int32, _P, _P]),
     ("bbfmm_adaptive_info_of", C.c_int, [_P, C.POINTER(AdaptiveInfo)]),
     ("bbfmm_adaptive_array", C.c_int, [_P, C.c_int32, _P]),
@@ -140,10 +145,11 @@ def build_octree(points, depth: int, root_lo=(0.0, 0.0, 0.0), root_width: float 
 
 
 def precompute_m2l(tree, kernel: str = "inv_r", order: int = 5, svd_eps: float = 0.0,
-                   m2l_prec: str = "fp64", c: float = 0.0, device=None, compressor: str = "svd"):
+                   m2l_prec: str = "fp64", c: float = 0.0, device=None, compressor: str = "svd",
+                   variant: str = "blocked"):
     import torch
     o = PlanOpts(KERNELS[kernel], float(c), int(order), float(svd_eps), PRECISIONS[m2l_prec],
-                 COMPRESSORS[compressor])
+                 COMPRESSORS[compressor], VARIANTS[variant])
     out = C.c_void_p()
     _check(lib().bbfmm_precompute_m2l(tree, C.byref(o), _P(_stream(torch, device)), C.byref(out)))
     return out
@@ -210,6 +216,20 @@ def host_operator(kernel: str, order: int, width: float, p: int, svd_eps: float 
                                      C.byref(r)))
     rr = r.value
     return k, u[:nn * rr].reshape(nn, rr), v[:nn * rr].reshape(nn, rr), rr
+
+
+def host_sa_operator(kernel: str, order: int, width: float, svd_eps: float, recompress: bool, t, c: float = 0.0):
+    """(U_t, V_t, r_t, r) of the library's SA / SArcmp operator of transfer vector t."""
+    nn = order ** 3
+    u = np.zeros(nn * nn)
+    v = np.zeros(nn * nn)
+    rt, r = C.c_int32(), C.c_int32()
+    tt = (C.c_int32 * 3)(*[int(x) for x in t])
+    _check(lib().bbfmm_host_sa_operator(KERNELS[kernel], float(c), order, float(width), float(svd_eps),
+                                        1 if recompress else 0, tt, u.ctypes.data_as(_P), v.ctypes.data_as(_P),
+                                        C.byref(rt), C.byref(r)))
+    k = rt.value
+    return u[:nn * k].reshape(nn, k), v[:nn * k].reshape(nn, k), k, r.value
 
 
 def host_singular_values(a: np.ndarray) -> np.ndarray:
@@ -307,11 +327,12 @@ class Plan:
     """Owns a bbfmm_plan (operators + work buffers) on a tree."""
 
     def __init__(self, tree: Octree, kernel: str = "inv_r", order: int = 5, svd_eps: float = 0.0,
-                 m2l_prec: str = "fp64", c: float = 0.0, compressor: str = "svd"):
+                 m2l_prec: str = "fp64", c: float = 0.0, compressor: str = "svd", variant: str = "blocked"):
         self.tree = tree            # keeps the tree alive
         self.order = order
         self.kernel = kernel
-        self.handle = precompute_m2l(tree.handle, kernel, order, svd_eps, m2l_prec, c, tree.device, compressor)
+        self.handle = precompute_m2l(tree.handle, kernel, order, svd_eps, m2l_prec, c, tree.device, compressor,
+                                     variant)
 
     def apply(self, q, out=None):
         return apply(self.handle, q, out)
@@ -369,10 +390,10 @@ class Plan:
 
 def fmm_apply(points, q, depth: int, order: int, kernel: str = "inv_r", svd_eps: float = 0.0,
               m2l_prec: str = "fp64", c: float = 0.0, root_lo=(0.0, 0.0, 0.0), root_width: float = 1.0,
-              max_leaf_points: int = 0, compressor: str = "svd"):
+              max_leaf_points: int = 0, compressor: str = "svd", variant: str = "blocked"):
     """One-shot build_octree + precompute_m2l + apply."""
     tree = Octree(points, depth, root_lo, root_width, max_leaf_points)
-    plan = Plan(tree, kernel, order, svd_eps, m2l_prec, c, compressor)
+    plan = Plan(tree, kernel, order, svd_eps, m2l_prec, c, compressor, variant)
     if q.dim() == 1:
         return plan.apply(q.reshape(-1, 1).contiguous()).reshape(-1)
     return plan.apply(q)

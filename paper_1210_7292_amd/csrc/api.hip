@@ -78,6 +78,8 @@ void free_buffers(bbfmm_plan* p) {
     p->slot_nrhs[s] = 0;
   }
   dfree(p->phis); p->phis = nullptr;
+  dfree(p->d_what); p->d_what = nullptr;
+  dfree(p->d_fhat); p->d_fhat = nullptr;
   p->nrhs_cap = 0;
   p->buffer_bytes = 0;
 }
@@ -91,6 +93,12 @@ bbfmm_status ensure_buffers(bbfmm_plan* p, int nrhs, int slot) {
       BBFMM_HIP_TRY(dmalloc(&p->W, (size_t)p->exp_elems * nrhs, &bytes));
       BBFMM_HIP_TRY(dmalloc(&p->F[0], (size_t)p->exp_elems * nrhs, &bytes));
       BBFMM_HIP_TRY(dmalloc(&p->phis, (size_t)t->n * nrhs, &bytes));
+      if (p->variant != 0) {
+        const int rp = *std::max_element(p->sa_rp.begin(), p->sa_rp.end());
+        const size_t elems = ((size_t)1 << (3 * t->depth)) * rp * nrhs;
+        BBFMM_HIP_TRY(dmalloc(&p->d_what, elems, &bytes));
+        BBFMM_HIP_TRY(dmalloc(&p->d_fhat, elems, &bytes));
+      }
     }
     BBFMM_HIP_TRY(dmalloc(&p->qs[0], (size_t)t->n * nrhs, &bytes));
     p->nrhs_cap = nrhs;
@@ -102,6 +110,25 @@ bbfmm_status ensure_buffers(bbfmm_plan* p, int nrhs, int slot) {
     BBFMM_HIP_TRY(dmalloc(&p->qs[1], (size_t)t->n * p->nrhs_cap, &bytes));
     p->buffer_bytes += bytes;
   }
+  return BBFMM_OK;
+}
+
+// One level of the SA / SArcmp M2L: F = M2L(W) for the level's multipoles W and locals F.
+bbfmm_status sa_level(const bbfmm_plan* p, int l, int nrhs, const double* W, double* F, hipStream_t s) {
+  const int set = p->set_of_level[l];
+  SALevelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.W = W; a.F = F;
+  a.what = p->d_what; a.fhat = p->d_fhat;
+  a.u = p->d_sa + p->sa_u_off[set];
+  a.ut = p->d_sa + p->sa_ut_off[set];
+  a.ops = p->d_sa;
+  a.off = p->d_sa_off + (size_t)set * 512;
+  a.rank = p->d_sa_rank + (size_t)set * 512;
+  a.tab = p->d_tab;
+  a.level = l; a.n = p->nn; a.r = p->sa_r[set]; a.rp = p->sa_rp[set]; a.nrhs = nrhs;
+  a.scale = p->scale_of_level[l];
+  BBFMM_HIP_TRY(launch_sa_level(a, s));
   return BBFMM_OK;
 }
 
@@ -286,7 +313,12 @@ bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, i
     for (int l = d - 1; l >= 2; --l)
       BBFMM_HIP_TRY(launch_m2m(g, l, W + p->level_off[l + 1] * nrhs, W + p->level_off[l] * nrhs, nrhs, s));
     BBFMM_HIP_TRY(mark(p, kM2M, s));
-    if (p->sparse_m2l) {
+    if (p->variant != 0) {
+      for (int l = 2; l <= d; ++l) {
+        const bbfmm_status st2 = sa_level(p, l, nrhs, W + p->level_off[l] * nrhs, F + p->level_off[l] * nrhs, s);
+        if (st2 != BBFMM_OK) return st2;
+      }
+    } else if (p->sparse_m2l) {
       // only targets holding points are computed: the locals of empty cells start at zero
       bbfmm_status st2 = adaptive_segments(p, nrhs, s);
       if (st2 != BBFMM_OK) return st2;
@@ -644,8 +676,16 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
   if (!std::isfinite(opts->svd_eps)) return fail(BBFMM_EINVAL, "svd_eps is not finite");
   if (opts->compressor != BBFMM_COMPRESS_SVD && opts->compressor != BBFMM_COMPRESS_ACA)
     return fail(BBFMM_EINVAL, "unknown compressor");
+  if (opts->variant != BBFMM_VARIANT_BLOCKED && opts->variant != BBFMM_VARIANT_SA &&
+      opts->variant != BBFMM_VARIANT_SARCMP)
+    return fail(BBFMM_EINVAL, "unknown M2L variant");
   if (opts->order < 2 || opts->order > kMaxOrder)
     return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
+  if (opts->variant != BBFMM_VARIANT_BLOCKED) {
+    if (!(opts->svd_eps > 0)) return fail(BBFMM_EINVAL, "the SA variants need svd_eps > 0");
+    if (tree->adaptive) return fail(BBFMM_EUNSUPPORTED, "the SA variants run on uniform trees");
+    if (opts->m2l_prec != BBFMM_M2L_FP64) return fail(BBFMM_EUNSUPPORTED, "the SA variants run in FP64");
+  }
   if (tree->adaptive && tree->xs == nullptr)
     return fail(BBFMM_ESTATE, "a host-only tree cannot be used for a plan");
   const auto t0 = std::chrono::steady_clock::now();
@@ -655,6 +695,7 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
   p->tree = tree;
   p->kernel = opts->kernel; p->c = opts->c; p->order = opts->order; p->eps = opts->svd_eps;
   p->prec = opts->m2l_prec;
+  p->variant = opts->variant;
   const int L = p->order, nn = L * L * L, np = (nn + 15) / 16 * 16;
   p->nn = nn; p->np = np;
   const int depth = tree->depth;
@@ -677,7 +718,7 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
       std::vector<double>& K = kfull[set * kNumSym + q];
       K.resize((size_t)nn * nn);
       m2l_operator(p->kernel, p->c, L, wset, q, K.data());
-      if (p->eps > 0) {
+      if (p->eps > 0 && p->variant == BBFMM_VARIANT_BLOCKED) {
         std::vector<double>& Uf = ufac[set * kNumSym + q];
         std::vector<double>& Vf = vfac[set * kNumSym + q];
         const int r = compress_operator(K.data(), L, q, p->eps, opts->compressor, Uf, Vf);
@@ -693,7 +734,50 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
       }
     }
   }
-  p->lowrank = p->eps > 0 && nsets > 0 && L >= 3 && max_rank <= m2l_ia_rank_limit(L);
+  p->lowrank = p->eps > 0 && p->variant == BBFMM_VARIANT_BLOCKED && nsets > 0 && L >= 3 &&
+               max_rank <= m2l_ia_rank_limit(L);
+  // SA / SArcmp: basis and cores of every operator set ([n][rp] basis, [r][n] transposed,
+  // then the cores by offset code)
+  std::vector<double> sblob;
+  std::vector<long long> sa_off;
+  if (p->variant != BBFMM_VARIANT_BLOCKED) {
+    sa_off.assign((size_t)nsets * 512, 0);
+    p->sa_rank_h.assign((size_t)nsets * 512, 0);
+    for (int set = 0; set < nsets; ++set) {
+      const double wset = homog ? 1.0 : tree->width / (double)(1 << (set + 2));
+      SAOperators op;
+      sa_operators(p->kernel, p->c, L, wset, p->eps, p->variant == BBFMM_VARIANT_SARCMP, op);
+      const int r = op.r, rp = 16 * ((r + 15) / 16);
+      if (r < 1 || r > kSAMaxRank) return fail(BBFMM_EUNSUPPORTED, "SA basis rank outside [1, 192]");
+      p->sa_r.push_back(r);
+      p->sa_rp.push_back(rp);
+      p->sa_u_off.push_back((long long)sblob.size());
+      for (int i = 0; i < nn; ++i)
+        for (int k = 0; k < rp; ++k) sblob.push_back(k < r ? op.u[(size_t)i * r + k] : 0.0);
+      p->sa_ut_off.push_back((long long)sblob.size());
+      for (int k = 0; k < r; ++k)
+        for (int i = 0; i < nn; ++i) sblob.push_back(op.u[(size_t)i * r + k]);
+      for (int code = 0; code < 512; ++code) {
+        const int rt = op.rank[code];
+        p->sa_rank_h[(size_t)set * 512 + code] = rt;
+        if (rt == 0) continue;
+        sa_off[(size_t)set * 512 + code] = (long long)sblob.size();
+        if (rt == r) {
+          const std::vector<double>& C = op.core[code];     // C_t^T, [rp][rp]
+          for (int k = 0; k < rp; ++k)
+            for (int i = 0; i < rp; ++i) sblob.push_back(k < r && i < r ? C[(size_t)i * r + k] : 0.0);
+        } else {
+          const int rt16 = 16 * ((rt + 15) / 16);
+          const std::vector<double>& ub = op.ubar[code];
+          const std::vector<double>& vb = op.vbar[code];
+          for (int k = 0; k < rp; ++k)                       // Vbar, [rp][rt16]
+            for (int q = 0; q < rt16; ++q) sblob.push_back(k < r && q < rt ? vb[(size_t)k * rt + q] : 0.0);
+          for (int q = 0; q < rt16; ++q)                     // Ubar^T, [rt16][rp]
+            for (int i = 0; i < rp; ++i) sblob.push_back(i < r && q < rt ? ub[(size_t)i * rt + q] : 0.0);
+        }
+      }
+    }
+  }
   p->h_k = kfull;
   p->h_u = ufac;
   p->h_v = vfac;
@@ -753,7 +837,7 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
   auto destroy_partial = [&]() {
     dfree(p->ops_hi); dfree(p->ops_lo); dfree(p->d_op_off); dfree(p->d_op_rank); dfree(p->d_tab);
     dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
-    dfree(p->d_zeros);
+    dfree(p->d_zeros); dfree(p->d_sa); dfree(p->d_sa_off); dfree(p->d_sa_rank);
   };
   hipError_t e = hipSuccess;
   std::vector<float> hi, lo;
@@ -779,6 +863,11 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
   if (e == hipSuccess) e = up((void**)&p->d_m2m, m2m.data(), m2m.size() * sizeof(double));
   const std::vector<double> zeros((size_t)nn * kMaxRhs, 0.0);
   if (e == hipSuccess) e = up((void**)&p->d_zeros, zeros.data(), zeros.size() * sizeof(double));
+  if (e == hipSuccess && p->variant != BBFMM_VARIANT_BLOCKED) {
+    e = up((void**)&p->d_sa, sblob.data(), sblob.size() * sizeof(double));
+    if (e == hipSuccess) e = up((void**)&p->d_sa_off, sa_off.data(), sa_off.size() * sizeof(long long));
+    if (e == hipSuccess) e = up((void**)&p->d_sa_rank, p->sa_rank_h.data(), p->sa_rank_h.size() * sizeof(int));
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     destroy_partial();
@@ -843,7 +932,7 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
       }
     }
     // full-rank operators: M2L over the targets that hold points only
-    if (!p->lowrank && depth >= 2) {
+    if (!p->lowrank && p->variant == BBFMM_VARIANT_BLOCKED && depth >= 2) {
       const bbfmm_status st = build_sparse_uniform(p.get(), s, &bytes);
       if (st != BBFMM_OK) {
         destroy_partial();
@@ -867,6 +956,7 @@ void bbfmm_plan_destroy(bbfmm_plan* p) {
   dfree(p->d_zeros); dfree(p->d_segs); dfree(p->d_utgt); dfree(p->d_uvsrc);
   dfree(p->d_split); dfree(p->d_tcount);
   dfree(p->d_abl_ops); dfree(p->d_abl_off); dfree(p->d_abl_rank);
+  dfree(p->d_sa); dfree(p->d_sa_off); dfree(p->d_sa_rank);
   delete p;
 }
 
@@ -952,6 +1042,18 @@ bbfmm_status bbfmm_plan_stats(const bbfmm_plan* p, bbfmm_stats* out) {
   out->n_levels_m2l = t->depth >= 2 ? t->depth - 1 : 0;
   out->n_operator_sets = p->nsets;
   for (int q = 0; q < kNumSym; ++q) out->rank[q] = p->eps > 0 ? p->ranks[q] : p->nn;
+  out->variant = p->variant;
+  if (p->variant != BBFMM_VARIANT_BLOCKED && !p->sa_r.empty()) {
+    out->sa_rank = p->sa_r[0];
+    double sum = 0.0;
+    int cnt = 0;
+    for (int code = 0; code < 512; ++code)
+      if (p->sa_rank_h[code] > 0) {
+        sum += p->sa_rank_h[code];
+        ++cnt;
+      }
+    out->sa_mean_core_rank = cnt ? sum / cnt : 0.0;
+  }
   for (int r = 0; r < 3; ++r) out->root_lo[r] = t->lo[r];
   out->root_width = t->width;
   out->precompute_seconds = p->precompute_seconds;
@@ -1010,6 +1112,37 @@ bbfmm_status bbfmm_plan_stats(const bbfmm_plan* p, bbfmm_stats* out) {
     const long long s = 1LL << l;
     out->pairs_total += (6 * s - 8) * (6 * s - 8) * (6 * s - 8) - (3 * s - 2) * (3 * s - 2) * (3 * s - 2);
     const int set = p->set_of_level[l];
+    if (p->variant != BBFMM_VARIANT_BLOCKED) {
+      // SA: every in-box pair at its core's cost, plus projection and expansion of every cell
+      for (int q = 0; q < kNumSym; ++q) out->pairs_nonempty += (long long)counts[16 * (l - 2) + q];
+      const int r = p->sa_r[set], rp = p->sa_rp[set];
+      const double ncell = (double)(1LL << (3 * l));
+      out->m2l_flops_algorithmic += ncell * 4.0 * nn * r;
+      out->m2l_flops_issued += ncell * 2.0 * nn * (rp + r);
+      for (int o = 0; o < 8; ++o) {
+        const double tiles = (double)(1LL << (3 * (l - 1))) / 64.0;
+        for (int e = 0; e < kFarPerOctant; ++e) {
+          const int code = p->h_tab[o * kFarPerOctant + e] & 511;
+          double cnt = 1.0;
+          for (int ax = 0; ax < 3; ++ax) {
+            const int d = ((code >> (3 * ax)) & 7) - 3, bit = (o >> ax) & 1;
+            long long c = 0;
+            for (long long x = bit; x < s; x += 2) c += (x + d >= 0 && x + d < s) ? 1 : 0;
+            cnt *= (double)c;
+          }
+          const int rt = p->sa_rank_h[(size_t)set * 512 + code];
+          out->m2l_flops_algorithmic += cnt * (rt == r ? 2.0 * r * r : 4.0 * r * rt);
+          double mfma = 0.0;
+          if (rt == r) {
+            mfma = (rp / 4.0) * (rp / 16);
+          } else {
+            for (int b2 = 0; 16 * b2 < rt; ++b2) mfma += rp / 4.0 + std::min(4, (rt - 16 * b2 + 3) / 4) * (rp / 16);
+          }
+          out->m2l_flops_issued += tiles * 4.0 * mfma * 2048.0;
+        }
+      }
+      continue;
+    }
     for (int q = 0; q < kNumSym; ++q) {
       const double c = (double)counts[16 * (l - 2) + q];
       out->pairs_nonempty += (long long)c;
@@ -1065,6 +1198,11 @@ bbfmm_status bbfmm_debug_m2l_level(bbfmm_plan* p, int32_t level, const double* d
   if (p->tree->adaptive) return fail(BBFMM_EUNSUPPORTED, "uniform trees only");
   if (level < 2 || level > p->tree->depth) return fail(BBFMM_EINVAL, "level must be in [2, depth]");
   if (nrhs < 1 || nrhs > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64]");
+  if (p->variant != BBFMM_VARIANT_BLOCKED) {
+    bbfmm_status st = ensure_buffers(p, nrhs, 0);
+    if (st != BBFMM_OK) return st;
+    return sa_level(p, level, nrhs, d_w, d_f, (hipStream_t)stream);
+  }
   const M2LArgs a = m2l_args(p, nrhs, d_w, d_f, level);
   BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, (hipStream_t)stream));
   return BBFMM_OK;
@@ -1293,6 +1431,42 @@ bbfmm_status bbfmm_host_operator(int32_t kernel, double c, int32_t order, double
   } else if (out_rank) {
     *out_rank = nn;
   }
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_host_sa_operator(int32_t kernel, double c, int32_t order, double width, double svd_eps,
+                                    int32_t recompress, const int32_t t[3], double* out_u, double* out_v,
+                                    int32_t* out_rank_t, int32_t* out_r) {
+  if (!valid_kernel(kernel)) return fail(BBFMM_EINVAL, "unknown kernel");
+  if (order < 2 || order > kMaxOrder) return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
+  if (!(width > 0) || !(svd_eps > 0) || !t) return fail(BBFMM_EINVAL, "width and svd_eps must be > 0, t non-null");
+  if (std::max({std::abs(t[0]), std::abs(t[1]), std::abs(t[2])}) < 2 ||
+      std::max({std::abs(t[0]), std::abs(t[1]), std::abs(t[2])}) > 3)
+    return fail(BBFMM_EINVAL, "t is not a far-field transfer vector");
+  SAOperators op;
+  sa_operators(kernel, c, order, width, svd_eps, recompress != 0, op);
+  const int n = op.n, r = op.r;
+  const int code = (3 - t[0]) | (3 - t[1]) << 3 | (3 - t[2]) << 6;   // d = -t
+  const int rt = op.rank[code];
+  if (out_r) *out_r = r;
+  if (out_rank_t) *out_rank_t = rt;
+  // full-space factors: U_t = U C_t, V_t = U (core kept) or U_t = U Ubar, V_t = U Vbar
+  for (int i = 0; i < n; ++i)
+    for (int q = 0; q < rt; ++q) {
+      double a = 0.0, b = 0.0;
+      for (int k = 0; k < r; ++k) {
+        const double uik = op.u[(size_t)i * r + k];
+        if (rt == r) {
+          a += uik * op.core[code][(size_t)k * r + q];
+          b = op.u[(size_t)i * r + q];
+        } else {
+          a += uik * op.ubar[code][(size_t)k * rt + q];
+          b += uik * op.vbar[code][(size_t)k * rt + q];
+        }
+      }
+      if (out_u) out_u[(size_t)i * rt + q] = a;
+      if (out_v) out_v[(size_t)i * rt + q] = b;
+    }
   return BBFMM_OK;
 }
 

@@ -184,15 +184,15 @@ int truncation_rank(const double* s, int n, double eps) {
   return r;
 }
 
-void householder_qr(const double* a, int m, int n, double* q, double* r) {
+void householder_qr(const double* a, long long m, int n, double* q, double* r) {
   // Column-major work copy; reflectors kept in the lower part, their scalars in beta.
   std::vector<double> w((size_t)m * n), beta(n, 0.0), diag(n, 0.0);
-  for (int i = 0; i < m; ++i)
+  for (long long i = 0; i < m; ++i)
     for (int j = 0; j < n; ++j) w[(size_t)j * m + i] = a[(size_t)i * n + j];
   for (int j = 0; j < n; ++j) {
     double* col = &w[(size_t)j * m];
     double norm2 = 0.0;
-    for (int i = j; i < m; ++i) norm2 += col[i] * col[i];
+    for (long long i = j; i < m; ++i) norm2 += col[i] * col[i];
     const double norm = std::sqrt(norm2);
     if (norm == 0.0) {
       diag[j] = 0.0;
@@ -207,13 +207,14 @@ void householder_qr(const double* a, int m, int n, double* q, double* r) {
     for (int c = j + 1; c < n; ++c) {
       double* cc = &w[(size_t)c * m];
       double dot = 0.0;
-      for (int i = j; i < m; ++i) dot += col[i] * cc[i];
+      for (long long i = j; i < m; ++i) dot += col[i] * cc[i];
       dot *= beta[j];
-      for (int i = j; i < m; ++i) cc[i] -= dot * col[i];
+      for (long long i = j; i < m; ++i) cc[i] -= dot * col[i];
     }
   }
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) r[(size_t)i * n + j] = j < i ? 0.0 : (j == i ? diag[i] : w[(size_t)j * m + i]);
+  if (!q) return;
   // Q = H_0 H_1 ... H_{n-1} applied to the first n columns of the identity
   std::vector<double> qc((size_t)m * n, 0.0);
   for (int j = 0; j < n; ++j) qc[(size_t)j * m + j] = 1.0;
@@ -223,12 +224,12 @@ void householder_qr(const double* a, int m, int n, double* q, double* r) {
     for (int c = 0; c < n; ++c) {
       double* cc = &qc[(size_t)c * m];
       double dot = 0.0;
-      for (int i = h; i < m; ++i) dot += v[i] * cc[i];
+      for (long long i = h; i < m; ++i) dot += v[i] * cc[i];
       dot *= beta[h];
-      for (int i = h; i < m; ++i) cc[i] -= dot * v[i];
+      for (long long i = h; i < m; ++i) cc[i] -= dot * v[i];
     }
   }
-  for (int i = 0; i < m; ++i)
+  for (long long i = 0; i < m; ++i)
     for (int j = 0; j < n; ++j) q[(size_t)i * n + j] = qc[(size_t)j * m + i];
 }
 
@@ -369,6 +370,95 @@ int compress_aca(const double* k, int n, const int32_t* q, double eps, std::vect
       vf[(size_t)i * r + c] = b;
     }
   return r;
+}
+
+void sa_operators(int kind, double c, int order, double width, double eps, bool recompress, SAOperators& out) {
+  const int n = order * order * order;
+  out = SAOperators();
+  out.n = n;
+  std::vector<std::vector<double>> kp(kNumSym, std::vector<double>((size_t)n * n));
+  for (int p = 0; p < kNumSym; ++p) m2l_operator(kind, c, order, width, p, kp[p].data());
+  // the 316 codes and their operators K_t[i][j] = K_p[sigma(i)][sigma(j)], t = -d
+  std::vector<int> codes;
+  for (int code = 0; code < 512; ++code) {
+    const int f[3] = {code & 7, (code >> 3) & 7, (code >> 6) & 7};
+    if (f[0] > 6 || f[1] > 6 || f[2] > 6) continue;
+    if (std::max({std::abs(f[0] - 3), std::abs(f[1] - 3), std::abs(f[2] - 3)}) < 2) continue;
+    codes.push_back(code);
+  }
+  auto operator_of = [&](int code, std::vector<double>& kt, std::vector<int32_t>& sg) {
+    const int t[3] = {3 - (code & 7), 3 - ((code >> 3) & 7), 3 - ((code >> 6) & 7)};
+    const SymInfo si = symmetry_of(t);
+    sigma_table(order, si.perm_id, sg.data());
+    const std::vector<double>& k = kp[si.p];
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) kt[(size_t)i * n + j] = k[(size_t)sg[i] * n + sg[j]];
+  };
+  // stacked K_t^T: (316 n) x n, row-major
+  const long long m = (long long)codes.size() * n;
+  std::vector<double> stack((size_t)m * n), kt((size_t)n * n);
+  std::vector<int32_t> sg(n);
+  for (size_t b = 0; b < codes.size(); ++b) {
+    operator_of(codes[b], kt, sg);
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) stack[((size_t)b * n + j) * n + i] = kt[(size_t)i * n + j];
+  }
+  std::vector<double> R((size_t)n * n);
+  householder_qr(stack.data(), m, n, nullptr, R.data());
+  std::vector<double>().swap(stack);
+  // K^(row) K^(row)^T = R^T R: U = the right singular vectors of R
+  std::vector<double> ur((size_t)n * n), vr((size_t)n * n);
+  out.sigma.assign(n, 0.0);
+  jacobi_svd(R.data(), n, n, ur.data(), out.sigma.data(), vr.data());
+  const int r = truncation_rank(out.sigma.data(), n, eps);
+  out.r = r;
+  out.u.assign((size_t)n * r, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < r; ++k) out.u[(size_t)i * r + k] = vr[(size_t)i * n + k];
+  out.core.assign(512, {});
+  out.ubar.assign(512, {});
+  out.vbar.assign(512, {});
+  std::vector<double> ku((size_t)n * r), C((size_t)r * r);
+  std::vector<double> X((size_t)r * r), S(r), Y((size_t)r * r);
+  for (int code : codes) {
+    operator_of(code, kt, sg);
+    // C_t = U^T (K_t U), loops ordered for unit-stride inner products
+    std::fill(ku.begin(), ku.end(), 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double kij = kt[(size_t)i * n + j];
+        const double* uj = &out.u[(size_t)j * r];
+        double* ki = &ku[(size_t)i * r];
+        for (int k = 0; k < r; ++k) ki[k] += kij * uj[k];
+      }
+    std::fill(C.begin(), C.end(), 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < r; ++a) {
+        const double uia = out.u[(size_t)i * r + a];
+        const double* ki = &ku[(size_t)i * r];
+        double* ca = &C[(size_t)a * r];
+        for (int b = 0; b < r; ++b) ca[b] += uia * ki[b];
+      }
+    out.rank[code] = r;
+    if (recompress) {
+      jacobi_svd(C.data(), r, r, X.data(), S.data(), Y.data());
+      const int rt = truncation_rank(S.data(), r, eps);
+      if (2 * rt < r) {
+        out.rank[code] = rt;
+        std::vector<double>& ub = out.ubar[code];
+        std::vector<double>& vb = out.vbar[code];
+        ub.assign((size_t)r * rt, 0.0);
+        vb.assign((size_t)r * rt, 0.0);
+        for (int a = 0; a < r; ++a)
+          for (int q = 0; q < rt; ++q) {
+            ub[(size_t)a * rt + q] = X[(size_t)a * r + q] * S[q];
+            vb[(size_t)a * rt + q] = Y[(size_t)a * r + q];
+          }
+        continue;
+      }
+    }
+    out.core[code] = C;
+  }
 }
 
 void octant_table(int octant, int32_t* entries, int32_t* group_start) {

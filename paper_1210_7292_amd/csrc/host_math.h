@@ -56,8 +56,9 @@ void jacobi_svd(const double* a, int m, int n, double* u, double* s, double* v);
 int truncation_rank(const double* s, int n, double eps);
 
 // Householder QR of a row-major m x n matrix (m >= n): A = Q R with Q m x n (orthonormal
-// columns) and R n x n upper triangular, both row-major. Rank-deficient input is fine.
-void householder_qr(const double* a, int m, int n, double* q, double* r);
+// columns) and R n x n upper triangular, both row-major. Rank-deficient input is fine. q may be
+// null (R only).
+void householder_qr(const double* a, long long m, int n, double* q, double* r);
 
 // Adaptive cross approximation with partial pivoting of a row-major n x n matrix (Sec. 4.1 and
 // Sec. 5 name ACA as the faster replacement of the SVD): crosses u_k, v_k (each n doubles,
@@ -79,6 +80,25 @@ int compress_svd(const double* k, int n, double eps, std::vector<double>& uf, st
 int compress_aca(const double* k, int n, const int32_t* q, double eps, std::vector<double>& uf,
                  std::vector<double>& vf);
 constexpr double kAcaRelTol = 1e-2;
+
+// Single low-rank approximation (SA) of the 316 far-field operators of one cell width and its
+// recompressed form (SArcmp), Sec. 4.1: U = the left singular vectors of K^(row) = [K_1, ...,
+// K_316] truncated by `truncation_rank` at eps (rank r); for the symmetric kernels here the
+// right singular vectors B of K^(col) span the same space, so B = U and each operator is
+// K_t ~ U C_t U^T with C_t = U^T K_t U (Eq. ucb_no_compression). With recompression, C_t is
+// replaced by its truncated SVD Ubar_t Vbar_t^T (rank r_t by `truncation_rank` relative to C_t's
+// largest singular value) when r_t < r/2 (Eq. recompression). U is taken from a Householder QR
+// of the stacked K_t^T (316 l^3 x l^3) and a Jacobi SVD of its R factor.
+// Operators are indexed by the offset code of d = Y - X = -t: (dx+3) | (dy+3) << 3 | (dz+3) << 6.
+struct SAOperators {
+  int n = 0, r = 0;
+  std::vector<double> u;                     // n x r, row-major
+  std::vector<double> sigma;                 // singular values of K^(row), descending (n)
+  std::array<int, 512> rank{};               // 0: not a far-field code; r: C_t kept; else r_t
+  std::vector<std::vector<double>> core;     // per code, rank == r: C_t (r x r, row-major)
+  std::vector<std::vector<double>> ubar, vbar;  // per code, rank < r: r x r_t each, row-major
+};
+void sa_operators(int kind, double c, int order, double width, double eps, bool recompress, SAOperators& out);
 
 // Far-field table of a target octant (x bit 0, y bit 1, z bit 2): the 189 source offsets
 // d = Y - X (cell units) whose source is a child of a neighbour of the target's parent and not a

@@ -157,6 +157,28 @@ struct AblationArgs {
 };
 hipError_t launch_m2l_unblocked(int order, const AblationArgs& a, hipStream_t s);
 
+// ---- SA / SArcmp M2L (one basis per operator set, cores per transfer vector) ---------------
+// Per level: What = U^T W (projection), Fhat = sum_t C_t What_{X-t} in the r-dimensional core
+// space (C_t kept, or Ubar_t (Vbar_t^T What) when recompressed), F = scale U Fhat (expansion).
+// The core space is padded to rp = 16 ceil(r / 16) rows with zeros.
+struct SALevelArgs {
+  const double* W;             // multipoles of one uniform level, [cell][n][nrhs], Morton cells
+  double* F;                   // locals of the level, [cell][n][nrhs], overwritten
+  double* what;                // work: [cell][rp][nrhs]
+  double* fhat;                // work: [cell][rp][nrhs]
+  const double* u;             // basis, [n][rp] (columns r..rp zero)
+  const double* ut;            // basis transposed, [r][n]
+  const double* ops;           // core operators of the set
+  const long long* off;        // [512] by offset code: C_t^T [rp][rp] (rank == r), or
+                               // Vbar [rp][rt16] followed by Ubar^T [rt16][rp] (rank < r)
+  const int* rank;             // [512] r, r_t < r, or 0 (not a far-field code)
+  const int* tab;              // [8][189] octant tables (offset code in the low 9 bits)
+  int level, n, r, rp, nrhs;
+  double scale;                // homogeneity factor of the level
+};
+constexpr int kSAMaxRank = 192;
+hipError_t launch_sa_level(const SALevelArgs& a, hipStream_t s);
+
 // ---- adaptive tree build ------------------------------------------------------------------
 hipError_t launch_keys64(const double* pts, long long n, const double lo[3], double width,
                          unsigned long long* keys, int* idx, hipStream_t s);
@@ -306,6 +328,16 @@ struct bbfmm_plan {
   int slot_nrhs[2] = {0, 0};                       // nrhs of the last forward / adjoint run
   long long buffer_bytes = 0;
   long long op_bytes = 0;
+  // SA / SArcmp (variant 1 / 2): one basis per operator set, cores per offset code
+  int variant = 0;
+  std::vector<int> sa_r, sa_rp;                    // [set] basis rank, padded to 16
+  std::vector<long long> sa_u_off, sa_ut_off;      // [set] offsets of U [n][rp] and U^T [r][n]
+  std::vector<int> sa_rank_h;                      // [set][512] core ranks (host copy)
+  double* d_sa = nullptr;                          // bases and cores of all sets
+  long long* d_sa_off = nullptr;                   // [set][512] core offsets into d_sa
+  int* d_sa_rank = nullptr;                        // [set][512]
+  double* d_what = nullptr;                        // [cells of the leaf level][rp][nrhs_cap]
+  double* d_fhat = nullptr;
   // per-pass tracing: events recorded in order, each tagged with the pass it closes (-1 = start)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;

@@ -100,6 +100,22 @@ def test_host_qr_handles_rank_deficient_factors():
     assert np.max(np.abs(u @ v.T - k)) <= 1e-12 * np.abs(k).max()
 
 
+@pytest.mark.parametrize("recompress", [False, True])
+@pytest.mark.parametrize("order,eps,kind,c,width", [(4, 1e-4, "inv_r", 0.0, 1.0),
+                                                    (3, 1e-6, "inv_sqrt_r2c2", 1e-3, 1 / 32)])
+def test_host_sa_operators_match_oracle(recompress, order, eps, kind, c, width):
+    """SA / SArcmp precompute of the library (basis from a QR of the stacked operators) against
+    the oracle's (dense SVD of K^(row)): same basis rank, same core ranks, same operators."""
+    r_o = O.sa_basis(width, order, kind, c, eps).shape[1]
+    for t in [(2, 0, 0), (-3, 2, 1), (0, -2, 3), (3, 3, 3), (-2, -2, -3)]:
+        u, v, rt, r = pk.host_sa_operator(kind, order, width, eps, recompress, t, c)
+        uo, vo = O.sa_operator(t, width, order, kind, c, eps, recompress)
+        assert r == r_o
+        assert rt == uo.shape[1], (t, rt, uo.shape[1])
+        k = O.m2l_operator(t, width, order, kind, c)
+        assert np.max(np.abs(u @ v.T - uo @ vo.T)) <= 1e-12 * np.abs(k).max()
+
+
 def test_jacobi_svd_against_lapack():
     rng = np.random.default_rng(0)
     for m, n in [(7, 7), (40, 25), (125, 125)]:
