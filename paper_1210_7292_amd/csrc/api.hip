@@ -94,8 +94,11 @@ bbfmm_status ensure_buffers(bbfmm_plan* p, int nrhs, int slot) {
       BBFMM_HIP_TRY(dmalloc(&p->F[0], (size_t)p->exp_elems * nrhs, &bytes));
       BBFMM_HIP_TRY(dmalloc(&p->phis, (size_t)t->n * nrhs, &bytes));
       if (p->variant != 0) {
+        // What / Fhat of every M2L level side by side
         const int rp = *std::max_element(p->sa_rp.begin(), p->sa_rp.end());
-        const size_t elems = ((size_t)1 << (3 * t->depth)) * rp * nrhs;
+        size_t cells = 0;
+        for (int l = 2; l <= t->depth; ++l) cells += (size_t)1 << (3 * l);
+        const size_t elems = cells * rp * nrhs;
         BBFMM_HIP_TRY(dmalloc(&p->d_what, elems, &bytes));
         BBFMM_HIP_TRY(dmalloc(&p->d_fhat, elems, &bytes));
       }
@@ -113,22 +116,41 @@ bbfmm_status ensure_buffers(bbfmm_plan* p, int nrhs, int slot) {
   return BBFMM_OK;
 }
 
-// One level of the SA / SArcmp M2L: F = M2L(W) for the level's multipoles W and locals F.
-bbfmm_status sa_level(const bbfmm_plan* p, int l, int nrhs, const double* W, double* F, hipStream_t s) {
-  const int set = p->set_of_level[l];
-  SALevelArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.W = W; a.F = F;
-  a.what = p->d_what; a.fhat = p->d_fhat;
-  a.u = p->d_sa + p->sa_u_off[set];
-  a.ut = p->d_sa + p->sa_ut_off[set];
-  a.ops = p->d_sa;
-  a.off = p->d_sa_off + (size_t)set * 512;
-  a.rank = p->d_sa_rank + (size_t)set * 512;
-  a.tab = p->d_tab;
-  a.level = l; a.n = p->nn; a.r = p->sa_r[set]; a.rp = p->sa_rp[set]; a.nrhs = nrhs;
-  a.scale = p->scale_of_level[l];
-  BBFMM_HIP_TRY(launch_sa_level(a, s));
+// SA / SArcmp M2L of levels 2..depth (only_level < 0, W and F the whole expansion arrays) or of
+// one level (W and F that level's arrays). Each level gets its own What / Fhat region.
+bbfmm_status sa_levels(const bbfmm_plan* p, int nrhs, const double* W, double* F, int only_level, hipStream_t s) {
+  SALevelArgs lv[kSAMaxLevels];
+  int nlev = 0;
+  const int rp_max = *std::max_element(p->sa_rp.begin(), p->sa_rp.end());
+  long long cell_off = 0;
+  for (int l = 2; l <= p->tree->depth; ++l) {
+    const long long cells = 1LL << (3 * l);
+    if (only_level >= 0 && l != only_level) {
+      cell_off += cells;
+      continue;
+    }
+    if (nlev == kSAMaxLevels) return fail(BBFMM_EUNSUPPORTED, "too many SA levels");
+    const int set = p->set_of_level[l];
+    SALevelArgs& a = lv[nlev++];
+    std::memset(&a, 0, sizeof(a));
+    a.W = only_level >= 0 ? W : W + p->level_off[l] * nrhs;
+    a.F = only_level >= 0 ? F : F + p->level_off[l] * nrhs;
+    a.what = p->d_what + cell_off * rp_max * nrhs;
+    a.fhat = p->d_fhat + cell_off * rp_max * nrhs;
+    a.u = p->d_sa + p->sa_u_off[set];
+    a.ut = p->d_sa + p->sa_ut_off[set];
+    a.ops = p->d_sa;
+    a.off = p->d_sa_off + (size_t)set * 512;
+    a.rank = p->d_sa_rank + (size_t)set * 512;
+    a.tab = p->d_tab;
+    a.level = l; a.n = p->nn; a.r = p->sa_r[set]; a.rp = p->sa_rp[set]; a.nrhs = nrhs;
+    a.max_op_doubles = p->sa_max_op[set];
+    a.stage_ops = p->variant == BBFMM_VARIANT_SA ? 1 : 0;
+    a.scale = p->scale_of_level[l];
+    cell_off += cells;
+  }
+  if (nlev == 0) return BBFMM_OK;
+  BBFMM_HIP_TRY(launch_sa_levels(lv, nlev, s));
   return BBFMM_OK;
 }
 
@@ -314,10 +336,8 @@ bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, i
       BBFMM_HIP_TRY(launch_m2m(g, l, W + p->level_off[l + 1] * nrhs, W + p->level_off[l] * nrhs, nrhs, s));
     BBFMM_HIP_TRY(mark(p, kM2M, s));
     if (p->variant != 0) {
-      for (int l = 2; l <= d; ++l) {
-        const bbfmm_status st2 = sa_level(p, l, nrhs, W + p->level_off[l] * nrhs, F + p->level_off[l] * nrhs, s);
-        if (st2 != BBFMM_OK) return st2;
-      }
+      const bbfmm_status st2 = sa_levels(p, nrhs, W, F, -1, s);
+      if (st2 != BBFMM_OK) return st2;
     } else if (p->sparse_m2l) {
       // only targets holding points are computed: the locals of empty cells start at zero
       bbfmm_status st2 = adaptive_segments(p, nrhs, s);
@@ -757,10 +777,12 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
       p->sa_ut_off.push_back((long long)sblob.size());
       for (int k = 0; k < r; ++k)
         for (int i = 0; i < nn; ++i) sblob.push_back(op.u[(size_t)i * r + k]);
+      int max_op = 0;
       for (int code = 0; code < 512; ++code) {
         const int rt = op.rank[code];
         p->sa_rank_h[(size_t)set * 512 + code] = rt;
-        if (rt == 0) continue;
+        if (op.core[code].empty() && op.ubar[code].empty()) continue;
+        max_op = std::max(max_op, rt == r ? rp * rp : 2 * rp * (16 * ((rt + 15) / 16)));
         sa_off[(size_t)set * 512 + code] = (long long)sblob.size();
         if (rt == r) {
           const std::vector<double>& C = op.core[code];     // C_t^T, [rp][rp]
@@ -776,6 +798,7 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
             for (int i = 0; i < rp; ++i) sblob.push_back(i < r && q < rt ? ub[(size_t)i * rt + q] : 0.0);
         }
       }
+      p->sa_max_op.push_back(max_op);
     }
   }
   p->h_k = kfull;
@@ -1201,7 +1224,7 @@ bbfmm_status bbfmm_debug_m2l_level(bbfmm_plan* p, int32_t level, const double* d
   if (p->variant != BBFMM_VARIANT_BLOCKED) {
     bbfmm_status st = ensure_buffers(p, nrhs, 0);
     if (st != BBFMM_OK) return st;
-    return sa_level(p, level, nrhs, d_w, d_f, (hipStream_t)stream);
+    return sa_levels(p, nrhs, d_w, d_f, level, (hipStream_t)stream);
   }
   const M2LArgs a = m2l_args(p, nrhs, d_w, d_f, level);
   BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, (hipStream_t)stream));

@@ -174,10 +174,16 @@ struct SALevelArgs {
   const int* rank;             // [512] r, r_t < r, or 0 (not a far-field code)
   const int* tab;              // [8][189] octant tables (offset code in the low 9 bits)
   int level, n, r, rp, nrhs;
+  int max_op_doubles;          // largest core of the set, in doubles
+  int stage_ops;               // stage the cores in LDS (when they fit)
   double scale;                // homogeneity factor of the level
 };
 constexpr int kSAMaxRank = 192;
-hipError_t launch_sa_level(const SALevelArgs& a, hipStream_t s);
+constexpr int kSAMaxLevels = 8;
+// M2L of `nlev` levels (<= kSAMaxLevels, each with its own What / Fhat region): the projections,
+// then one core launch per distinct rp covering all its levels (so that the short work of the
+// coarse levels overlaps the deepest one), then the expansions.
+hipError_t launch_sa_levels(const SALevelArgs* lv, int nlev, hipStream_t s);
 
 // ---- adaptive tree build ------------------------------------------------------------------
 hipError_t launch_keys64(const double* pts, long long n, const double lo[3], double width,
@@ -331,6 +337,7 @@ struct bbfmm_plan {
   // SA / SArcmp (variant 1 / 2): one basis per operator set, cores per offset code
   int variant = 0;
   std::vector<int> sa_r, sa_rp;                    // [set] basis rank, padded to 16
+  std::vector<int> sa_max_op;                      // [set] largest core, in doubles
   std::vector<long long> sa_u_off, sa_ut_off;      // [set] offsets of U [n][rp] and U^T [r][n]
   std::vector<int> sa_rank_h;                      // [set][512] core ranks (host copy)
   double* d_sa = nullptr;                          // bases and cores of all sets
