@@ -8,6 +8,9 @@ What it follows (Messner, Bramas, Coulaud, Darve, "Optimized M2L kernels for the
 interpolation based fast multipole method"):
 
 * Sec. 2, Eq. (direct): f_i = sum_j K(x_i, y_j) w_j — `brute_force`.
+* Sec. 5, Eq. (kernel_functions): the Laplace kernel and the Helmholtz kernel e^{ikr}/r (the
+  latter as its real and imaginary parts, each a real bbFMM kernel) — `kernel_of_r`,
+  `brute_force_helmholtz`.
 * Sec. 2.1, Eqs. (chebinter1d), (interpolop3d): Chebyshev roots and the tensor-product
   interpolation operator S_l — `cheb_roots`, `lagrange_basis`, `tensor_basis`.
 * Sec. 2.1.1, Eqs. (m2m_bbfmm), (m2l_bbfmm), (l2l_bbfmm): the three-stage scheme
@@ -51,6 +54,9 @@ Readings taken where the paper is silent, ambiguous or garbled:
  8. SA / SArcmp: B = U (K^(col)'s right singular vectors span K^(row)'s left ones for the
     symmetric kernels here); C_t = U^T K_t U; the recompression truncates each C_t by the rule
     of 5 relative to C_t's own largest singular value and is kept only when r_t < r/2.
+ 9. Helmholtz: e^{ikr}/r = cos(kr)/r + i sin(kr)/r; each part is a radial, symmetric, real
+    kernel, so the bbFMM (whose interpolation is real) applies to each, and a complex potential
+    is their sum. Only the low-frequency regime is meant: cells a fraction of a wavelength wide.
 """
 from __future__ import annotations
 
@@ -79,6 +85,14 @@ def kernel_of_r(kind: str, r: np.ndarray, c: float = 0.0) -> np.ndarray:
         return r * r
     if kind == "r4":
         return (r * r) ** 2
+    # Helmholtz e^{ikr}/r of Eq. kernel_functions (4 pi dropped), wavenumber k = c, split into its
+    # real part cos(kr)/r (0 at r = 0, like 1/r) and its smooth imaginary part sin(kr)/r (k at 0)
+    if kind == "helm_cos":
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(r > 0.0, np.cos(c * r) / np.where(r > 0.0, r, 1.0), 0.0)
+    if kind == "helm_sin":
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(r > 0.0, np.sin(c * r) / np.where(r > 0.0, r, 1.0), c)
     raise ValueError(kind)
 
 
@@ -101,9 +115,41 @@ def kernel_grad_x(kind: str, x: np.ndarray, y: np.ndarray, c: float = 0.0) -> np
         f = 2.0 * np.ones_like(r2)
     elif kind == "r4":
         f = 4.0 * r2
+    elif kind in ("helm_cos", "helm_sin"):
+        # f = (1/r) dK/dr
+        r = np.sqrt(r2)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            rs = np.where(r > 0.0, r, 1.0)
+            kr = c * rs
+            if kind == "helm_cos":
+                f = np.where(r > 0.0, -(kr * np.sin(kr) + np.cos(kr)) / rs ** 3, 0.0)
+            else:
+                exact = (kr * np.cos(kr) - np.sin(kr)) / rs ** 3
+                # below kr = 0.05 the difference cancels: its Taylor series instead
+                series = -c ** 3 / 3.0 + c ** 5 * r2 / 30.0 - c ** 7 * r2 * r2 / 840.0
+                f = np.where(c * r < 0.05, series, exact)
     else:
         raise ValueError(kind)
     return f[..., None] * d
+
+
+def brute_force_helmholtz(points: np.ndarray, q: np.ndarray, k: float, targets=None) -> np.ndarray:
+    """phi_i = sum_{j != i} e^{ik|x_i - x_j|} / |x_i - x_j| q_j (complex; coincident distinct
+    points contribute k i q_j, the limit of the smooth part)."""
+    points = np.asarray(points, dtype=np.float64)
+    tgt = np.arange(points.shape[0]) if targets is None else np.asarray(targets)
+    qq = np.asarray(q)
+    qq = qq[:, None] if qq.ndim == 1 else qq
+    out = np.zeros((tgt.size, qq.shape[1]), dtype=np.complex128)
+    for s in range(0, tgt.size, 256):
+        idx = tgt[s:s + 256]
+        d = points[idx, None, :] - points[None, :, :]
+        r = np.sqrt(np.sum(d * d, axis=-1))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            kmat = np.where(r > 0.0, np.exp(1j * k * r) / np.where(r > 0.0, r, 1.0), 1j * k)
+        kmat[np.arange(idx.size), idx] = 0.0
+        out[s:s + 256] = kmat @ qq
+    return out
 
 
 # ----------------------------------------------------------------------------------------
