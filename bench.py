@@ -176,6 +176,68 @@ def cpu_baseline_adaptive(w, inp, sample_n, compressor="svd"):
                       f"{w.nrhs} right-hand sides), one adaptive-oracle fmm_apply in {dt:.2f} s"}
 
 
+def run_helmholtz(args):
+    """Complex Helmholtz potential e^{ikr}/r (low-frequency bbFMM: the cos(kr)/r and sin(kr)/r
+    plans on one tree) on the selected uniform workload's points and densities; prints one JSON
+    line with points/s of the complex apply and the error against the direct complex sum."""
+    import numpy as np
+    import torch
+
+    import paper_1210_7292_amd as pk
+    from workloads import WORKLOADS, make_inputs
+
+    w = WORKLOADS[args.config]
+    if w.depth < 0:
+        raise SystemExit("--helmholtz runs on the uniform workloads")
+    k = float(args.helmholtz)
+    dev = torch.device("cuda:0")
+    inp = make_inputs(w)
+    pts = torch.from_numpy(inp.points).to(dev)
+    q = torch.from_numpy(inp.q).to(dev)
+    tree = pk.Octree(pts, w.depth)
+    t0 = time.perf_counter()
+    hp = pk.HelmholtzPlan(tree, k, w.order, w.svd_eps, "fp64", args.compressor)
+    pre_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        hp.apply(q)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        phi = hp.apply(q)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    # direct complex sum at seeded targets, FP64 on the device (measurement only)
+    tg = inp.sample_targets[:256]
+    tgt = torch.from_numpy(tg.astype(np.int64)).to(dev)
+    x = pts[tgt]
+    direct = torch.zeros((tg.size, w.nrhs), dtype=torch.complex128, device=dev)
+    for s0 in range(0, w.n, 1 << 18):
+        y = pts[s0:s0 + (1 << 18)]
+        r = ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1).sqrt()
+        kr = torch.where(r > 0, torch.exp(1j * k * r) / torch.where(r > 0, r, torch.ones_like(r)),
+                         torch.zeros_like(r, dtype=torch.complex128))
+        direct += kr @ q[s0:s0 + (1 << 18)].to(torch.complex128)
+    direct = direct.cpu().numpy()
+    got = phi.cpu().numpy()[tg]
+    err = float(np.linalg.norm(got - direct) / np.linalg.norm(direct))
+    wl = 2 * np.pi / k
+    line = {
+        "metric": "Helmholtz FMM points/sec of one complex apply (two real bbFMM applies)",
+        "value": w.n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_points": w.n, "kernel": "e^{ikr}/r", "wavenumber": k,
+                   "order": w.order, "depth": w.depth, "svd_eps": w.svd_eps, "compressor": args.compressor,
+                   "leaf_width_in_wavelengths": 1.0 / (1 << w.depth) / wl},
+        "rel_l2_err_vs_direct": err, "error_sample": f"{tg.size} seeded targets",
+        "precompute_s": pre_s,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +256,9 @@ def main():
     ap.add_argument("--variant", default="blocked", choices=("blocked", "sa", "sarcmp"),
                     help="M2L variant: symmetry-blocked (default), or SA / SArcmp (compressed "
                          "uniform workloads, FP64)")
+    ap.add_argument("--helmholtz", type=float, default=None, metavar="K",
+                    help="instead: the complex Helmholtz apply e^{ikr}/r with wavenumber K on the "
+                         "workload's points")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -208,6 +273,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 3}))
+        return
+    if args.helmholtz is not None and args.gpus == 1:
+        run_helmholtz(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "

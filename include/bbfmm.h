@@ -54,6 +54,15 @@ typedef enum {
 typedef enum {
   BBFMM_K_INV_R = 0,            /* 1/r, 0 at r = 0; homogeneous of degree -1 */
   BBFMM_K_INV_SQRT_R2C2 = 1,    /* 1/sqrt(r^2 + c^2); not homogeneous: operators per level */
+  BBFMM_K_HELM_COS = 2,         /* cos(kr)/r, 0 at r = 0, wavenumber k = c >= 0: the real part of
+                                   the Helmholtz kernel e^{ikr}/r of Sec. 5, Eq. kernel_functions
+                                   (4 pi dropped); operators per level */
+  BBFMM_K_HELM_SIN = 3,         /* sin(kr)/r, k at r = 0: its imaginary part. A complex Helmholtz
+                                   potential is the apply of the first plus i times the apply of
+                                   the second (real densities) on the same tree. The bbFMM is
+                                   meant for the low-frequency regime (cells a fraction of a
+                                   wavelength wide); the directional expansions of the paper's
+                                   high-frequency dFMM are not implemented */
   BBFMM_K_R2 = 100,             /* r^2; homogeneous of degree 2 */
   BBFMM_K_R4 = 101              /* r^4; homogeneous of degree 4 */
 } bbfmm_kernel;
@@ -109,7 +118,8 @@ typedef enum {
 
 typedef struct {
   int32_t kernel;    /* bbfmm_kernel */
-  double c;          /* regularisation of BBFMM_K_INV_SQRT_R2C2 (> 0), ignored otherwise */
+  double c;          /* regularisation of BBFMM_K_INV_SQRT_R2C2 (> 0), wavenumber of the
+                        Helmholtz parts (>= 0), ignored otherwise */
   int32_t order;     /* Chebyshev order l in [2, 8]; l^3 interpolation points per cell */
   double svd_eps;    /* <= 0: full-rank operators (variant NAblk); > 0: each of the 16 operators
                         truncated to the singular values > svd_eps * sigma_1, extended over a
@@ -179,7 +189,8 @@ bbfmm_status bbfmm_build_octree(const double* d_points, int64_t n, const bbfmm_t
  * (189 transfer vectors, their representative p(t) and permutation sigma_t, Eqs.
  * axial_permutation and diagonal_permutation) and the 1-D interpolation matrices of M2M/L2L;
  * uploads everything. `tree` is borrowed and must outlive the plan.
- * Errors: EINVAL (null, c <= 0 for INV_SQRT_R2C2, unknown kernel, precision or compressor),
+ * Errors: EINVAL (null, c <= 0 for INV_SQRT_R2C2, c < 0 for the Helmholtz parts, unknown kernel,
+ * precision, compressor or variant),
  * EUNSUPPORTED (order outside [2, 8]). */
 bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts* opts,
                                   void* stream, bbfmm_plan** out);

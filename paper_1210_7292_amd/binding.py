@@ -10,7 +10,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libbbfmm.so")
 
-KERNELS = {"inv_r": 0, "inv_sqrt_r2c2": 1, "r2": 100, "r4": 101}
+KERNELS = {"inv_r": 0, "inv_sqrt_r2c2": 1, "helm_cos": 2, "helm_sin": 3, "r2": 100, "r4": 101}
 COMPRESSORS = {"svd": 0, "aca": 1}
 VARIANTS = {"blocked": 0, "sa": 1, "sarcmp": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "split32": 2}
@@ -386,6 +386,29 @@ class Plan:
         if h is not None and _lib is not None:
             _lib.bbfmm_plan_destroy(h)
             self.handle = None
+
+
+class HelmholtzPlan:
+    """The Helmholtz potential phi_i = sum_j e^{ik|x_i - x_j|} / |x_i - x_j| q_j (4 pi dropped) as
+    two plans on one tree, for the real part cos(kr)/r and the imaginary part sin(kr)/r. Real q:
+    phi = A_cos q + i A_sin q. Complex q: both parts applied to [Re q, Im q] as 2 nrhs columns.
+    Low-frequency regime only (cells a fraction of a wavelength wide)."""
+
+    def __init__(self, tree: Octree, k: float, order: int = 5, svd_eps: float = 0.0, m2l_prec: str = "fp64",
+                 compressor: str = "svd"):
+        self.tree = tree
+        self.k = float(k)
+        self.re = Plan(tree, "helm_cos", order, svd_eps, m2l_prec, self.k, compressor)
+        self.im = Plan(tree, "helm_sin", order, svd_eps, m2l_prec, self.k, compressor)
+
+    def apply(self, q):
+        import torch
+        if torch.is_complex(q):
+            nr = q.shape[1]
+            both = torch.cat([q.real, q.imag], dim=1).contiguous()
+            a, b = self.re.apply(both), self.im.apply(both)
+            return torch.complex(a[:, :nr] - b[:, nr:], a[:, nr:] + b[:, :nr])
+        return torch.complex(self.re.apply(q), self.im.apply(q))
 
 
 def fmm_apply(points, q, depth: int, order: int, kernel: str = "inv_r", svd_eps: float = 0.0,

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kAdP2LThreads) void ad_p2l_kernel(AdaptiveGeom g, c
   const int k = blockIdx.x;
   const int C = x_node[k];
   const double* cp = g.cen + 4LL * C;
-  const double c2 = g.c * g.c;
+  const double c2 = kernel_param<KIND>(g.c);
   double xa[PER][3];
   bool va[PER];
   double acc[PER][RC];
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kAdM2PThreads) void ad_m2p_kernel(AdaptiveGeom g, c
   const int tid = threadIdx.x;
   const int b = leaves[lp];
   const int s = g.start[b], e = g.end[b];
-  const double c2 = g.c * g.c;
+  const double c2 = kernel_param<KIND>(g.c);
   for (int i0 = s; i0 < e; i0 += kAdM2PThreads) {
     const int i = i0 + tid;
     const bool vi = i < e;
@@ -389,7 +389,7 @@ __global__ void ad_p2p_kernel(AdaptiveGeom g, const int* __restrict__ leaf_pos, 
   if (i >= g.n) return;
   const int lp = leaf_pos[g.leaf_of[i]];
   const double xi = g.xs[i], yi = g.ys[i], zi = g.zs[i];
-  const double c2 = g.c * g.c;
+  const double c2 = kernel_param<KIND>(g.c);
   double acc[RC];
 #pragma unroll
   for (int r = 0; r < RC; ++r) acc[r] = 0.0;
@@ -438,6 +438,8 @@ hipError_t ad_kind(int kind, Args... args) {
   switch (kind) {
     case kInvR: return Fn<kInvR>::run(args...);
     case kInvSqrtR2C2: return Fn<kInvSqrtR2C2>::run(args...);
+    case kHelmCos: return Fn<kHelmCos>::run(args...);
+    case kHelmSin: return Fn<kHelmSin>::run(args...);
     case kR2: return Fn<kR2>::run(args...);
     case kR4: return Fn<kR4>::run(args...);
     default: return hipErrorInvalidValue;

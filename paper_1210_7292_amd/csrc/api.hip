@@ -54,7 +54,9 @@ PassGeom geom_of(const bbfmm_plan* pl) {
   return g;
 }
 
-bool valid_kernel(int k) { return k == kInvR || k == kInvSqrtR2C2 || k == kR2 || k == kR4; }
+bool valid_kernel(int k) {
+  return k == kInvR || k == kInvSqrtR2C2 || k == kHelmCos || k == kHelmSin || k == kR2 || k == kR4;
+}
 
 // Compressed factors of representative p's operator K (row-major l^3 x l^3) by the chosen
 // compressor; returns the rank.
@@ -692,6 +694,8 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
   if (!valid_kernel(opts->kernel)) return fail(BBFMM_EINVAL, "unknown kernel");
   if (opts->kernel == kInvSqrtR2C2 && !(opts->c > 0.0 && std::isfinite(opts->c)))
     return fail(BBFMM_EINVAL, "c must be finite and > 0 for 1/sqrt(r^2 + c^2)");
+  if ((opts->kernel == kHelmCos || opts->kernel == kHelmSin) && !(opts->c >= 0.0 && std::isfinite(opts->c)))
+    return fail(BBFMM_EINVAL, "the wavenumber c must be finite and >= 0");
   if (opts->m2l_prec < 0 || opts->m2l_prec > 2) return fail(BBFMM_EINVAL, "unknown M2L precision");
   if (!std::isfinite(opts->svd_eps)) return fail(BBFMM_EINVAL, "svd_eps is not finite");
   if (opts->compressor != BBFMM_COMPRESS_SVD && opts->compressor != BBFMM_COMPRESS_ACA)

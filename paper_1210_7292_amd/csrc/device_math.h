@@ -42,25 +42,53 @@ __device__ inline void cheb_basis_deriv_all(double u, const double* tk, double* 
   }
 }
 
+// The kernel's parameter as kern / kern_dr take it: c^2 for 1/sqrt(r^2 + c^2), the wavenumber k
+// for the Helmholtz parts.
 template <int KIND>
-__device__ inline double kern(double r2, double c2) {
+__host__ __device__ inline double kernel_param(double c) {
+  return KIND == kInvSqrtR2C2 ? c * c : c;
+}
+
+template <int KIND>
+__device__ inline double kern(double r2, double kp) {
   if (KIND == kInvR) return r2 > 0.0 ? rsqrt(r2) : 0.0;
-  if (KIND == kInvSqrtR2C2) return rsqrt(r2 + c2);
+  if (KIND == kInvSqrtR2C2) return rsqrt(r2 + kp);
+  if (KIND == kHelmCos || KIND == kHelmSin) {
+    // cos(kr)/r (0 at r = 0) and sin(kr)/r (k at r = 0): the parts of e^{ikr}/r
+    if (!(r2 > 0.0)) return KIND == kHelmSin ? kp : 0.0;
+    const double r = sqrt(r2);
+    double sn, cs;
+    sincos(kp * r, &sn, &cs);
+    return (KIND == kHelmCos ? cs : sn) / r;
+  }
   if (KIND == kR2) return r2;
   return r2 * r2;
 }
 
 // (1/r) dK/dr, so that grad_x K(x, y) = kern_dr(r2) * (x - y).
 template <int KIND>
-__device__ inline double kern_dr(double r2, double c2) {
+__device__ inline double kern_dr(double r2, double kp) {
   if (KIND == kInvR) {
     if (!(r2 > 0.0)) return 0.0;
     const double ir = rsqrt(r2);
     return -ir * ir * ir;
   }
   if (KIND == kInvSqrtR2C2) {
-    const double ir = rsqrt(r2 + c2);
+    const double ir = rsqrt(r2 + kp);
     return -ir * ir * ir;
+  }
+  if (KIND == kHelmCos || KIND == kHelmSin) {
+    const double r = sqrt(r2), kr = kp * r;
+    if (KIND == kHelmSin && kr < 0.05) {
+      // (k r cos(kr) - sin(kr)) / r^3 cancels for small kr: its Taylor series
+      const double k2 = kp * kp;
+      return kp * k2 * (-1.0 / 3.0 + k2 * r2 * (1.0 / 30.0 - k2 * r2 / 840.0));
+    }
+    if (!(r2 > 0.0)) return 0.0;
+    double sn, cs;
+    sincos(kr, &sn, &cs);
+    const double ir3 = 1.0 / (r2 * r);
+    return (KIND == kHelmCos ? -(kr * sn + cs) : (kr * cs - sn)) * ir3;
   }
   if (KIND == kR2) return 2.0;
   return 4.0 * r2;

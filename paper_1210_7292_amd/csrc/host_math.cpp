@@ -30,6 +30,8 @@ double kernel_value(int kind, double c, double r) {
   switch (kind) {
     case kInvR: return r > 0.0 ? 1.0 / r : 0.0;
     case kInvSqrtR2C2: return 1.0 / std::sqrt(r * r + c * c);
+    case kHelmCos: return r > 0.0 ? std::cos(c * r) / r : 0.0;
+    case kHelmSin: return r > 0.0 ? std::sin(c * r) / r : c;
     case kR2: return r * r;
     case kR4: return (r * r) * (r * r);
     default: return 0.0;

@@ -14,7 +14,7 @@ constexpr int kNumSym = 16;      // |T_sym| (Eq. reduced_interaction_list)
 constexpr int kNumPerms = 48;    // 8 axial reflections x 6 axis orders
 constexpr int kFarPerOctant = 189;
 
-enum KernelKind : int32_t { kInvR = 0, kInvSqrtR2C2 = 1, kR2 = 100, kR4 = 101 };
+enum KernelKind : int32_t { kInvR = 0, kInvSqrtR2C2 = 1, kHelmCos = 2, kHelmSin = 3, kR2 = 100, kR4 = 101 };
 
 // Chebyshev roots of T_l, ascending (Sec. 2.1; T_l(x) = cos(l arccos x)).
 std::vector<double> cheb_nodes(int order);
@@ -22,7 +22,8 @@ std::vector<double> cheb_nodes(int order);
 // S_l(u, xbar_m) in the Chebyshev-sum form 1/l + 2/l sum_{k=1}^{l-1} T_k(u) T_k(xbar_m).
 double cheb_basis(int order, double u, int m);
 
-// Kernel value at distance r.
+// Kernel value at distance r (c: the regularisation of kInvSqrtR2C2, the wavenumber of the
+// Helmholtz parts).
 double kernel_value(int kind, double c, double r);
 bool kernel_is_homogeneous(int kind, double* degree);
 

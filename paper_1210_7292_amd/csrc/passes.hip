@@ -282,7 +282,7 @@ __global__ void p2p_kernel(PassGeom g, const double* __restrict__ qs,
   int lx, ly, lz;
   demorton3((unsigned)g.leaf_of[i], lx, ly, lz);
   const double xi = g.xs[i], yi = g.ys[i], zi = g.zs[i];
-  const double c2 = g.c * g.c;
+  const double c2 = kernel_param<KIND>(g.c);
   double acc[RC];
 #pragma unroll
   for (int r = 0; r < RC; ++r) acc[r] = 0.0;
@@ -357,7 +357,7 @@ __global__ void grad_kernel(PassGeom g, const double* __restrict__ qs, const dou
   const int side = 1 << g.depth;
   int lx, ly, lz;
   demorton3(leaf, lx, ly, lz);
-  const double c2 = g.c * g.c;
+  const double c2 = kernel_param<KIND>(g.c);
   for (int dz = -1; dz <= 1; ++dz) {
     const int nz = lz + dz;
     if (nz < 0 || nz >= side) continue;
@@ -554,6 +554,8 @@ hipError_t launch_p2p_scatter(const PassGeom& g, const double* qs, const double*
   switch (g.kernel) {
     case kInvR: return p2p_kind<kInvR>(g, qs, phis_far, nrhs, phi_out, s);
     case kInvSqrtR2C2: return p2p_kind<kInvSqrtR2C2>(g, qs, phis_far, nrhs, phi_out, s);
+    case kHelmCos: return p2p_kind<kHelmCos>(g, qs, phis_far, nrhs, phi_out, s);
+    case kHelmSin: return p2p_kind<kHelmSin>(g, qs, phis_far, nrhs, phi_out, s);
     case kR2: return p2p_kind<kR2>(g, qs, phis_far, nrhs, phi_out, s);
     case kR4: return p2p_kind<kR4>(g, qs, phis_far, nrhs, phi_out, s);
     default: return hipErrorInvalidValue;
@@ -567,6 +569,10 @@ hipError_t launch_grad(const PassGeom& g, const double* qs, const double* gs, co
       return dispatch_order<GradAtKind<kInvR>::Run>(g.order, g, qs, gs, Fq, Fg, nrhs, roles, out, s);
     case kInvSqrtR2C2:
       return dispatch_order<GradAtKind<kInvSqrtR2C2>::Run>(g.order, g, qs, gs, Fq, Fg, nrhs, roles, out, s);
+    case kHelmCos:
+      return dispatch_order<GradAtKind<kHelmCos>::Run>(g.order, g, qs, gs, Fq, Fg, nrhs, roles, out, s);
+    case kHelmSin:
+      return dispatch_order<GradAtKind<kHelmSin>::Run>(g.order, g, qs, gs, Fq, Fg, nrhs, roles, out, s);
     case kR2:
       return dispatch_order<GradAtKind<kR2>::Run>(g.order, g, qs, gs, Fq, Fg, nrhs, roles, out, s);
     case kR4:
