@@ -68,7 +68,8 @@ def test_host_compression_matches_oracle(order, eps):
         assert np.max(np.abs(u @ v.T - uo @ vo.T)) <= 1e-13 * so[0]
 
 
-@pytest.mark.parametrize("order,eps,kind,c,width", [(3, 1e-3, "inv_r", 0.0, 1.0), (5, 1e-5, "inv_r", 0.0, 1.0),
+@pytest.mark.parametrize("order,eps,kind,c,width", [(2, 1e-3, "inv_r", 0.0, 1.0), (2, 1e-12, "inv_r", 0.0, 1.0),
+                                                    (3, 1e-3, "inv_r", 0.0, 1.0), (5, 1e-5, "inv_r", 0.0, 1.0),
                                                     (6, 1e-7, "inv_r", 0.0, 1.0),
                                                     (4, 1e-5, "inv_sqrt_r2c2", 1e-3, 1 / 64),
                                                     (8, 1e-5, "inv_r", 0.0, 1.0)])
@@ -105,7 +106,8 @@ def test_host_qr_handles_rank_deficient_factors():
 
 @pytest.mark.parametrize("recompress", [False, True])
 @pytest.mark.parametrize("order,eps,kind,c,width", [(4, 1e-4, "inv_r", 0.0, 1.0),
-                                                    (3, 1e-6, "inv_sqrt_r2c2", 1e-3, 1 / 32)])
+                                                    (3, 1e-6, "inv_sqrt_r2c2", 1e-3, 1 / 32),
+                                                    (2, 1e-3, "helm_sin", 2.0, 0.25)])
 def test_host_sa_operators_match_oracle(recompress, order, eps, kind, c, width):
     """SA / SArcmp precompute of the library (basis from a QR of the stacked operators) against
     the oracle's (dense SVD of K^(row)): same basis rank, same core ranks, same operators."""
