@@ -51,7 +51,11 @@ __host__ __device__ inline double kernel_param(double c) {
 
 template <int KIND>
 __device__ inline double kern(double r2, double kp) {
-  if (KIND == kInvR) return r2 > 0.0 ? rsqrt(r2) : 0.0;
+  if (KIND == kInvR) {
+    // branch-free: rsqrt of a safe argument, then the select for r = 0
+    const double ir = rsqrt(r2 > 0.0 ? r2 : 1.0);
+    return r2 > 0.0 ? ir : 0.0;
+  }
   if (KIND == kInvSqrtR2C2) return rsqrt(r2 + kp);
   if (KIND == kHelmCos || KIND == kHelmSin) {
     // cos(kr)/r (0 at r = 0) and sin(kr)/r (k at r = 0): the parts of e^{ikr}/r

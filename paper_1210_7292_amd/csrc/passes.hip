@@ -37,281 +37,472 @@ __global__ void gather_rows_kernel(const double* __restrict__ in, const int* __r
 }
 
 // ---- P2M: W[leaf][b][r] = sum_{j in leaf} S(y_j, ybar_b) q_j[r] ----------------------------
-// One wave per leaf (four leaves per block). The 1-D basis values of a batch of the leaf's points
-// go to the wave's own LDS slice; only wave-level ordering is needed between writing and reading.
-constexpr int kP2MWaves = 4;
-constexpr int kP2MBatch = 16;
-constexpr int kP2MOut = 8;       // outputs per lane per pass
+// One workgroup per group of G consecutive leaves (a contiguous range of sorted points). The 1-D
+// basis values of a batch of the group's points are computed once per point into LDS. A work
+// unit is (leaf, a1, a2, rhs): it accumulates the L outputs a0 = 0..L-1 of that line over the
+// leaf's points in the batch, so one product S_y S_z q serves L outputs. Each thread owns up to
+// kP2MUnits units of a pass; G is chosen so that one pass covers the group.
+constexpr int kP2MThreads = 256;
+constexpr int kP2MBatch = 128;
+constexpr int kP2MUnits = 2;
 
-template <int L>
-__global__ __launch_bounds__(64 * kP2MWaves) void p2m_kernel(PassGeom g, const double* __restrict__ qs,
-                                                             int nrhs, double* __restrict__ W) {
-  constexpr int NN = L * L * L;
-  __shared__ double sb[kP2MWaves][kP2MBatch][3][L];
+template <int L, int RC>
+__global__ __launch_bounds__(kP2MThreads) void p2m_kernel(PassGeom g, const double* __restrict__ qs,
+                                                          int nrhs, int r0, int G,
+                                                          double* __restrict__ W) {
+  constexpr int NN = L * L * L, LL = L * L, PASS = kP2MThreads * kP2MUnits;
   __shared__ double stk[L * L];
-  for (int i = threadIdx.x; i < L * L; i += blockDim.x) stk[i] = g.tk[i];
-  __syncthreads();
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  __shared__ double sb[kP2MBatch][3][L];
+  __shared__ double sq[kP2MBatch * RC];
+  __shared__ int sls[PASS + 1];   // the group's leaf starts (G <= PASS)
+  const int tid = threadIdx.x;
+  for (int i = tid; i < L * L; i += kP2MThreads) stk[i] = g.tk[i];
   const unsigned nleaf = 1u << (3 * g.depth);
-  const int nout = NN * nrhs;
-  for (unsigned leaf = blockIdx.x * kP2MWaves + wave; leaf < nleaf; leaf += gridDim.x * kP2MWaves) {
-    const int s = g.leaf_start[leaf], e = g.leaf_start[leaf + 1];
-    double* Wl = W + (long long)leaf * nout;
-    if (s == e) {
-      for (int o = lane; o < nout; o += 64) Wl[o] = 0.0;
-      continue;
-    }
-    double c[3], half;
-    cell_center(g, g.depth, leaf, c, &half);
-    const double inv_half = 1.0 / half;
-    for (int o0 = 0; o0 < nout; o0 += 64 * kP2MOut) {
-      double acc[kP2MOut];
+  const int rc = min(RC, nrhs - r0);
+  const int units = G * LL * RC;
+  for (unsigned leaf0 = blockIdx.x * (unsigned)G; leaf0 < nleaf; leaf0 += gridDim.x * (unsigned)G) {
+    const int ng = (int)min((unsigned)G, nleaf - leaf0);
+    __syncthreads();
+    for (int k = tid; k <= ng; k += kP2MThreads) sls[k] = g.leaf_start[leaf0 + k];
+    __syncthreads();
+    const int ps = sls[0], pe = sls[ng];
+    for (int u0 = 0; u0 < units; u0 += PASS) {
+      int lg[kP2MUnits], a1[kP2MUnits], a2[kP2MUnits], rr[kP2MUnits], ls[kP2MUnits], le[kP2MUnits];
+      bool ok[kP2MUnits];
+      double acc[kP2MUnits][L];
 #pragma unroll
-      for (int u = 0; u < kP2MOut; ++u) acc[u] = 0.0;
-      for (int b0 = s; b0 < e; b0 += kP2MBatch) {
-        const int nb = min(kP2MBatch, e - b0);
-        if (lane < nb * 3) {
-          const int jj = lane / 3, ax = lane % 3;
-          const double x = (ax == 0 ? g.xs : ax == 1 ? g.ys : g.zs)[b0 + jj];
-          cheb_basis_all<L>((x - c[ax]) * inv_half, stk, sb[wave][jj][ax]);
+      for (int v = 0; v < kP2MUnits; ++v) {
+        const int u = u0 + tid + v * kP2MThreads;
+        lg[v] = u / (LL * RC);
+        const int rem = u - lg[v] * LL * RC, m = rem / RC;
+        rr[v] = rem - m * RC;
+        a1[v] = m % L;
+        a2[v] = m / L;
+        ok[v] = u < units && lg[v] < ng && rr[v] < rc;
+        ls[v] = ok[v] ? sls[lg[v]] : 0;
+        le[v] = ok[v] ? sls[lg[v] + 1] : 0;
+#pragma unroll
+        for (int a0 = 0; a0 < L; ++a0) acc[v][a0] = 0.0;
+      }
+      for (int b0 = ps; b0 < pe; b0 += kP2MBatch) {
+        const int nb = min(kP2MBatch, pe - b0);
+        __syncthreads();
+        if (tid < nb) {
+          const int j = b0 + tid;
+          double c[3], half;
+          cell_center(g, g.depth, (unsigned)g.leaf_of[j], c, &half);
+          const double inv_half = 1.0 / half;
+          cheb_basis_all<L>((g.xs[j] - c[0]) * inv_half, stk, sb[tid][0]);
+          cheb_basis_all<L>((g.ys[j] - c[1]) * inv_half, stk, sb[tid][1]);
+          cheb_basis_all<L>((g.zs[j] - c[2]) * inv_half, stk, sb[tid][2]);
         }
-        // the wave's LDS writes complete before its lanes read each other's values
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        for (int t = tid; t < nb * RC; t += kP2MThreads) {
+          const int jj = t / RC, r = t - jj * RC;
+          sq[t] = r < rc ? qs[(long long)(b0 + jj) * nrhs + r0 + r] : 0.0;
+        }
+        __syncthreads();
 #pragma unroll
-        for (int u = 0; u < kP2MOut; ++u) {
-          const int o = o0 + lane + 64 * u;
-          if (o < nout) {
-            const int beta = o / nrhs, r = o - beta * nrhs;
-            const int a0 = beta % L, a1 = (beta / L) % L, a2 = beta / (L * L);
-            double t = 0.0;
-            for (int jj = 0; jj < nb; ++jj)
-              t += sb[wave][jj][0][a0] * sb[wave][jj][1][a1] * sb[wave][jj][2][a2] *
-                   qs[(long long)(b0 + jj) * nrhs + r];
-            acc[u] += t;
+        for (int v = 0; v < kP2MUnits; ++v) {
+          const int j0 = max(ls[v], b0) - b0, j1 = min(le[v], b0 + nb) - b0;
+          for (int jj = j0; jj < j1; ++jj) {
+            const double w = sb[jj][1][a1[v]] * sb[jj][2][a2[v]] * sq[jj * RC + rr[v]];
+#pragma unroll
+            for (int a0 = 0; a0 < L; ++a0) acc[v][a0] += w * sb[jj][0][a0];
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       }
 #pragma unroll
-      for (int u = 0; u < kP2MOut; ++u) {
-        const int o = o0 + lane + 64 * u;
-        if (o < nout) Wl[o] = acc[u];
+      for (int v = 0; v < kP2MUnits; ++v) {
+        if (!ok[v]) continue;
+        double* Wl = W + ((long long)(leaf0 + lg[v]) * NN + L * (a1[v] + L * a2[v])) * nrhs + r0 + rr[v];
+#pragma unroll
+        for (int a0 = 0; a0 < L; ++a0) Wl[(long long)a0 * nrhs] = acc[v][a0];
       }
     }
   }
 }
 
-// ---- M2M / L2L: three 1-D contractions per child (separable tensor interpolation) ---------
-constexpr int kM2MThreads = 128;
-constexpr int kM2MBuf = 2048;      // doubles per LDS stage buffer
+// ---- M2M / L2L: separable interpolation between a parent and its eight children ----------
+// W_P[B] = sum_c sum_b S(b0 of c, B0) S(b1 of c, B1) S(b2 of c, B2) W_c[b] (Eq. m2m_bbfmm): the
+// 1-D contractions run one axis at a time, and each also sums the two children that differ only
+// along its axis, so the arrays go 8 -> 4 -> 2 -> 1 (sum factorisation). L2L (Eq. l2l_bbfmm)
+// runs the same chain transposed, 1 -> 2 -> 4 -> 8, and adds into the children's locals. A
+// workgroup takes NV vectors (parent, right-hand side) at once; their children's expansions
+// are read (M2M) or read and updated (L2L) in one batch of coalesced accesses per thread.
+constexpr int kM2MThreads = 256;
+template <int L> constexpr int m2m_nv() {
+  return (2048 / (8 * L * L * L)) < 1 ? 1 : (2048 / (8 * L * L * L)) > 32 ? 32 : 2048 / (8 * L * L * L);
+}
 
-template <int L, int RC>
+template <int L>
 __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(PassGeom g, int parent_level,
                                                           const double* __restrict__ Wc,
                                                           double* __restrict__ Wp, int nrhs) {
-  constexpr int NN = L * L * L;
-  constexpr int OUT = (NN * RC + kM2MThreads - 1) / kM2MThreads;
-  __shared__ double sM[2 * L * L];
-  __shared__ double bufA[NN * RC], bufB[NN * RC], bufC[NN * RC];
-  for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) sM[i] = g.m2m[i];
-  __syncthreads();
-  const unsigned npar = 1u << (3 * parent_level);
-  for (unsigned P = blockIdx.x; P < npar; P += gridDim.x) {
-    for (int r0 = 0; r0 < nrhs; r0 += RC) {
-      const int rc = min(RC, nrhs - r0);
-      const int tot = NN * rc;
-      double acc[OUT];
+  constexpr int NN = L * L * L, NV = m2m_nv<L>(), TOT = NV * 8 * NN;
+  constexpr int PER = (TOT + kM2MThreads - 1) / kM2MThreads;
+  __shared__ double sM[2 * L * L];   // [bit][child node b][parent node B]
+  __shared__ double X[TOT];          // children [v][c][b]; later the y stage [v][cz][..]
+  __shared__ double T[NV * 4 * NN];  // x stage [v][cy + 2 cz][B0 + L b1 + L^2 b2]
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * L * L; i += kM2MThreads) sM[i] = g.m2m[i];
+  const long long nvec = (long long)(1u << (3 * parent_level)) * nrhs;   // v = P * nrhs + r
+  for (long long v0 = (long long)blockIdx.x * NV; v0 < nvec; v0 += (long long)gridDim.x * NV) {
+    const int nv = (int)min((long long)NV, nvec - v0);
+    double t[PER];
 #pragma unroll
-      for (int u = 0; u < OUT; ++u) acc[u] = 0.0;
-      for (int ch = 0; ch < 8; ++ch) {
-        const int cx = ch & 1, cy = (ch >> 1) & 1, cz = (ch >> 2) & 1;
-        const double* src = Wc + ((long long)P * 8 + ch) * NN * nrhs;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          bufA[idx] = src[beta * nrhs + r0 + rr];
-        }
-        __syncthreads();
-        const double* M0 = sM + cx * L * L;   // [b'][B]
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          const int B0 = beta % L, rest = beta / L;
-          double s = 0.0;
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + u * kM2MThreads;
+      const int vl = idx / (8 * NN), rest = idx - vl * 8 * NN;
+      const long long v = v0 + vl, P = v / nrhs;
+      const int r = (int)(v - P * nrhs);
+      t[u] = (idx < TOT && vl < nv) ? Wc[(P * 8 * NN + rest) * nrhs + r] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll
-          for (int b0 = 0; b0 < L; ++b0) s += M0[b0 * L + B0] * bufA[(b0 + L * rest) * rc + rr];
-          bufB[idx] = s;
-        }
-        __syncthreads();
-        const double* M1 = sM + cy * L * L;
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          const int B0 = beta % L, B1 = (beta / L) % L, b2 = beta / (L * L);
-          double s = 0.0;
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + u * kM2MThreads;
+      if (idx < TOT) X[idx] = t[u];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NV * 4 * NN; idx += kM2MThreads) {
+      const int v = idx / (4 * NN), rem = idx - v * 4 * NN, cyz = rem / NN, beta = rem - cyz * NN;
+      const int B0 = beta % L, rest = beta / L;
+      double a = 0.0;
 #pragma unroll
-          for (int b1 = 0; b1 < L; ++b1) s += M1[b1 * L + B1] * bufB[(B0 + L * b1 + L * L * b2) * rc + rr];
-          bufC[idx] = s;
-        }
-        __syncthreads();
-        const double* M2 = sM + cz * L * L;
+      for (int cx = 0; cx < 2; ++cx) {
+        const double* src = X + (v * 8 + cx + 2 * cyz) * NN + L * rest;
+        const double* M = sM + cx * L * L;
 #pragma unroll
-        for (int u = 0; u < OUT; ++u) {
-          const int idx = threadIdx.x + u * kM2MThreads;
-          if (idx < tot) {
-            const int beta = idx / rc, rr = idx - beta * rc;
-            const int B0 = beta % L, B1 = (beta / L) % L, B2 = beta / (L * L);
-            double s = 0.0;
-#pragma unroll
-            for (int b2 = 0; b2 < L; ++b2) s += M2[b2 * L + B2] * bufC[(B0 + L * B1 + L * L * b2) * rc + rr];
-            acc[u] += s;
-          }
-        }
+        for (int b0 = 0; b0 < L; ++b0) a += M[b0 * L + B0] * src[b0];
       }
-      double* dst = Wp + (long long)P * NN * nrhs;
+      T[idx] = a;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NV * 2 * NN; idx += kM2MThreads) {
+      const int v = idx / (2 * NN), rem = idx - v * 2 * NN, cz = rem / NN, beta = rem - cz * NN;
+      const int B0 = beta % L, B1 = (beta / L) % L, b2 = beta / (L * L);
+      double a = 0.0;
 #pragma unroll
-      for (int u = 0; u < OUT; ++u) {
-        const int idx = threadIdx.x + u * kM2MThreads;
-        if (idx < tot) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          dst[beta * nrhs + r0 + rr] = acc[u];
-        }
+      for (int cy = 0; cy < 2; ++cy) {
+        const double* src = T + (v * 4 + cy + 2 * cz) * NN + B0 + L * L * b2;
+        const double* M = sM + cy * L * L;
+#pragma unroll
+        for (int b1 = 0; b1 < L; ++b1) a += M[b1 * L + B1] * src[L * b1];
       }
+      X[idx] = a;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nv * NN; idx += kM2MThreads) {
+      const int v = idx / NN, beta = idx - v * NN;
+      const int B0 = beta % L, B1 = (beta / L) % L, B2 = beta / (L * L);
+      double a = 0.0;
+#pragma unroll
+      for (int cz = 0; cz < 2; ++cz) {
+        const double* src = X + (v * 2 + cz) * NN + B0 + L * B1;
+        const double* M = sM + cz * L * L;
+#pragma unroll
+        for (int b2 = 0; b2 < L; ++b2) a += M[b2 * L + B2] * src[L * L * b2];
+      }
+      const long long vv = v0 + v, P = vv / nrhs;
+      Wp[(P * NN + beta) * nrhs + (vv - P * nrhs)] = a;
     }
   }
 }
 
-template <int L, int RC>
+template <int L>
 __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(PassGeom g, int parent_level,
                                                           const double* __restrict__ Fp,
                                                           double* __restrict__ Fc, int nrhs) {
-  constexpr int NN = L * L * L;
+  constexpr int NN = L * L * L, NV = m2m_nv<L>(), TOT = NV * 8 * NN;
+  constexpr int PER = (TOT + kM2MThreads - 1) / kM2MThreads;
   __shared__ double sM[2 * L * L];
-  __shared__ double bufA[NN * RC], bufB[NN * RC], bufC[NN * RC];
-  for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) sM[i] = g.m2m[i];
-  __syncthreads();
-  const unsigned npar = 1u << (3 * parent_level);
-  for (unsigned P = blockIdx.x; P < npar; P += gridDim.x) {
-    for (int r0 = 0; r0 < nrhs; r0 += RC) {
-      const int rc = min(RC, nrhs - r0);
-      const int tot = NN * rc;
-      const double* src = Fp + (long long)P * NN * nrhs;
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int beta = idx / rc, rr = idx - beta * rc;
-        bufA[idx] = src[beta * nrhs + r0 + rr];
-      }
-      for (int ch = 0; ch < 8; ++ch) {
-        const int cx = ch & 1, cy = (ch >> 1) & 1, cz = (ch >> 2) & 1;
-        __syncthreads();
-        const double* M0 = sM + cx * L * L;
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          const int b0 = beta % L, rest = beta / L;     // (b0, B1, B2)
-          double s = 0.0;
+  __shared__ double A[NV * NN];        // parents [v][B]
+  __shared__ double T2[NV * 2 * NN];   // z stage [v][cz][B0 + L B1 + L^2 b2]
+  __shared__ double T1[NV * 4 * NN];   // y stage [v][cy + 2 cz][B0 + L b1 + L^2 b2]
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * L * L; i += kM2MThreads) sM[i] = g.m2m[i];
+  const long long nvec = (long long)(1u << (3 * parent_level)) * nrhs;
+  for (long long v0 = (long long)blockIdx.x * NV; v0 < nvec; v0 += (long long)gridDim.x * NV) {
+    const int nv = (int)min((long long)NV, nvec - v0);
+    // the children's current locals (the M2L result), in flight during the contractions
+    double old[PER];
+    long long addr[PER];
 #pragma unroll
-          for (int B0 = 0; B0 < L; ++B0) s += M0[b0 * L + B0] * bufA[(B0 + L * rest) * rc + rr];
-          bufB[idx] = s;
-        }
-        __syncthreads();
-        const double* M1 = sM + cy * L * L;
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          const int b0 = beta % L, b1 = (beta / L) % L, B2 = beta / (L * L);
-          double s = 0.0;
-#pragma unroll
-          for (int B1 = 0; B1 < L; ++B1) s += M1[b1 * L + B1] * bufB[(b0 + L * B1 + L * L * B2) * rc + rr];
-          bufC[idx] = s;
-        }
-        __syncthreads();
-        const double* M2 = sM + cz * L * L;
-        double* dst = Fc + ((long long)P * 8 + ch) * NN * nrhs;
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          const int b0 = beta % L, b1 = (beta / L) % L, b2 = beta / (L * L);
-          double s = 0.0;
-#pragma unroll
-          for (int B2 = 0; B2 < L; ++B2) s += M2[b2 * L + B2] * bufC[(b0 + L * b1 + L * L * B2) * rc + rr];
-          dst[beta * nrhs + r0 + rr] += s;
-        }
-      }
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + u * kM2MThreads;
+      const int vl = idx / (8 * NN), rest = idx - vl * 8 * NN;
+      const long long v = v0 + vl, P = v / nrhs;
+      addr[u] = (idx < TOT && vl < nv) ? (P * 8 * NN + rest) * nrhs + (v - P * nrhs) : -1;
+      old[u] = addr[u] >= 0 ? Fc[addr[u]] : 0.0;
     }
+    __syncthreads();
+    for (int idx = tid; idx < nv * NN; idx += kM2MThreads) {
+      const int v = idx / NN, beta = idx - v * NN;
+      const long long vv = v0 + v, P = vv / nrhs;
+      A[idx] = Fp[(P * NN + beta) * nrhs + (vv - P * nrhs)];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NV * 2 * NN; idx += kM2MThreads) {
+      const int v = idx / (2 * NN), rem = idx - v * 2 * NN, cz = rem / NN, beta = rem - cz * NN;
+      const int B0 = beta % L, B1 = (beta / L) % L, b2 = beta / (L * L);
+      const double* src = A + v * NN + B0 + L * B1;
+      const double* M = sM + cz * L * L + b2 * L;
+      double a = 0.0;
+#pragma unroll
+      for (int B2 = 0; B2 < L; ++B2) a += M[B2] * src[L * L * B2];
+      T2[idx] = a;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NV * 4 * NN; idx += kM2MThreads) {
+      const int v = idx / (4 * NN), rem = idx - v * 4 * NN, cyz = rem / NN, beta = rem - cyz * NN;
+      const int cy = cyz & 1, cz = cyz >> 1;
+      const int B0 = beta % L, b1 = (beta / L) % L, b2 = beta / (L * L);
+      const double* src = T2 + (v * 2 + cz) * NN + B0 + L * L * b2;
+      const double* M = sM + cy * L * L + b1 * L;
+      double a = 0.0;
+#pragma unroll
+      for (int B1 = 0; B1 < L; ++B1) a += M[B1] * src[L * B1];
+      T1[idx] = a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + u * kM2MThreads;
+      if (addr[u] < 0) continue;
+      const int v = idx / (8 * NN), rem = idx - v * 8 * NN, c = rem / NN, beta = rem - c * NN;
+      const int cx = c & 1, cyz = c >> 1;
+      const int b0 = beta % L, rest = beta / L;
+      const double* src = T1 + (v * 4 + cyz) * NN + L * rest;
+      const double* M = sM + cx * L * L + b0 * L;
+      double a = 0.0;
+#pragma unroll
+      for (int B0 = 0; B0 < L; ++B0) a += M[B0] * src[B0];
+      Fc[addr[u]] = old[u] + a;
+    }
+    __syncthreads();
   }
 }
 
 // ---- L2P: phi_far[i][r] = sum_a S(x_i, xbar_a) F_leaf[a][r] -------------------------------
-template <int L>
-__global__ void l2p_kernel(PassGeom g, const double* __restrict__ F, int nrhs,
-                           double* __restrict__ phis) {
+// One wave per group of G consecutive leaves: their local expansions (RC right-hand sides from
+// r0) are read into LDS once, coalesced, and each lane evaluates points of the group from there.
+constexpr int kL2PThreads = 64;
+constexpr int kL2PLds = 32 * 1024;   // bytes of local expansions staged per wave
+
+template <int L, int RC>
+__global__ __launch_bounds__(kL2PThreads) void l2p_kernel(PassGeom g, const double* __restrict__ F,
+                                                          int nrhs, int r0, int G,
+                                                          double* __restrict__ phis) {
   constexpr int NN = L * L * L;
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
-  const unsigned leaf = (unsigned)g.leaf_of[i];
-  double c[3], half;
-  cell_center(g, g.depth, leaf, c, &half);
-  double sx[L], sy[L], sz[L];
-  cheb_basis_all<L>((g.xs[i] - c[0]) / half, g.tk, sx);
-  cheb_basis_all<L>((g.ys[i] - c[1]) / half, g.tk, sy);
-  cheb_basis_all<L>((g.zs[i] - c[2]) / half, g.tk, sz);
-  const double* Fl = F + (long long)leaf * NN * nrhs;
-  for (int r = 0; r < nrhs; ++r) {
-    double acc = 0.0;
+  __shared__ double stk[L * L];
+  extern __shared__ double sF[];   // [G][NN][RC]
+  const int tid = threadIdx.x;
+  for (int i = tid; i < L * L; i += kL2PThreads) stk[i] = g.tk[i];
+  const unsigned nleaf = 1u << (3 * g.depth);
+  const int rc = min(RC, nrhs - r0);
+  const unsigned leaf0 = blockIdx.x * (unsigned)G;
+  const int ng = (int)min((unsigned)G, nleaf - leaf0);
+  const double* Fg = F + (long long)leaf0 * NN * nrhs + r0;
+  // batches of 8 loads per lane in flight before their LDS stores
+  const int tot = ng * NN * RC;
+  for (int base = 0; base < tot; base += 8 * kL2PThreads) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * kL2PThreads + tid;
+      const int row = idx / RC, r = idx - row * RC;
+      t[u] = (idx < tot && r < rc) ? Fg[(long long)row * nrhs + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * kL2PThreads + tid;
+      if (idx < tot) sF[idx] = t[u];
+    }
+  }
+  __syncthreads();
+  const int ps = g.leaf_start[leaf0], pe = g.leaf_start[leaf0 + ng];
+  for (int i = ps + tid; i < pe; i += kL2PThreads) {
+    const unsigned leaf = (unsigned)g.leaf_of[i];
+    double c[3], half;
+    cell_center(g, g.depth, leaf, c, &half);
+    const double inv_half = 1.0 / half;
+    double sx[L], sy[L], sz[L];
+    cheb_basis_all<L>((g.xs[i] - c[0]) * inv_half, stk, sx);
+    cheb_basis_all<L>((g.ys[i] - c[1]) * inv_half, stk, sy);
+    cheb_basis_all<L>((g.zs[i] - c[2]) * inv_half, stk, sz);
+    const double* Fl = sF + (long long)(leaf - leaf0) * NN * RC;
+    double acc[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[r] = 0.0;
 #pragma unroll
     for (int a2 = 0; a2 < L; ++a2)
 #pragma unroll
       for (int a1 = 0; a1 < L; ++a1) {
-        double s = 0.0;
+        double s[RC];
 #pragma unroll
-        for (int a0 = 0; a0 < L; ++a0) s += sx[a0] * Fl[(a0 + L * a1 + L * L * a2) * nrhs + r];
-        acc += sy[a1] * sz[a2] * s;
+        for (int r = 0; r < RC; ++r) s[r] = 0.0;
+#pragma unroll
+        for (int a0 = 0; a0 < L; ++a0)
+#pragma unroll
+          for (int r = 0; r < RC; ++r) s[r] += sx[a0] * Fl[(a0 + L * a1 + L * L * a2) * RC + r];
+        const double w = sy[a1] * sz[a2];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) acc[r] += w * s[r];
       }
-    phis[i * nrhs + r] = acc;
+#pragma unroll
+    for (int r = 0; r < RC; ++r)
+      if (r < rc) phis[(long long)i * nrhs + r0 + r] = acc[r];
   }
 }
 
 // ---- near field + scatter to the caller's order ------------------------------------------
-template <int KIND, int RC>
-__global__ void p2p_kernel(PassGeom g, const double* __restrict__ qs,
-                           const double* __restrict__ far, int nrhs, int r0,
-                           double* __restrict__ out) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
+// One workgroup per aligned B x B x B block of leaves, a contiguous Morton range and so a
+// contiguous range of (sorted) target points. The points of the (B+2)^3 leaves around the block
+// are staged in LDS in row-major leaf order (x fastest), so the three leaves of each of a
+// target's nine neighbour rows form one contiguous segment; each thread walks its target's nine
+// segments as one flattened loop, so the lanes of a wave run about the same number of steps.
+// Regions holding more points than the LDS stage are processed in chunks of it.
+constexpr int kP2PThreads = 256;
+template <int RC> constexpr int p2p_cap() { return RC == 1 ? 1024 : RC == 4 ? 768 : 256; }
+
+// Exclusive prefix sum over the block's threads (one value each); `total` gets the sum.
+__device__ inline int block_exclusive_scan(int v, int* swave, int& total) {
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nw = blockDim.x / 64;
+  int incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d *= 2) {
+    const int o = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += o;
+  }
+  if (lane == 63) swave[wave] = incl;
+  __syncthreads();
+  int before = 0;
+  total = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int t = swave[w];
+    if (w < wave) before += t;
+    total += t;
+  }
+  return before + incl - v;
+}
+
+template <int KIND, int RC, int B>
+__global__ __launch_bounds__(kP2PThreads) void p2p_kernel(PassGeom g, const double* __restrict__ qs,
+                                                          const double* __restrict__ far, int nrhs,
+                                                          int r0, double* __restrict__ out) {
+  constexpr int R = B + 2, NR = R * R * R, CAP = p2p_cap<RC>();
+  static_assert(NR <= kP2PThreads, "one region leaf per thread");
+  __shared__ int soff[NR + 1];      // first staged position of each region leaf
+  __shared__ int sstart[NR];        // its first sorted point
+  __shared__ int swave[kP2PThreads / 64];
+  __shared__ double4 sp[CAP];       // x, y, z and, with one right-hand side, the density
+  __shared__ double sq[RC > 1 ? CAP * RC : 1];
+  const int tid = threadIdx.x;
   const int side = 1 << g.depth;
-  int lx, ly, lz;
-  demorton3((unsigned)g.leaf_of[i], lx, ly, lz);
-  const double xi = g.xs[i], yi = g.ys[i], zi = g.zs[i];
+  int bx, by, bz;
+  demorton3(blockIdx.x, bx, by, bz);
+  bx *= B;
+  by *= B;
+  bz *= B;
+  int cnt = 0, st = 0;
+  if (tid < NR) {
+    const int gx = bx - 1 + tid % R, gy = by - 1 + (tid / R) % R, gz = bz - 1 + tid / (R * R);
+    if (gx >= 0 && gy >= 0 && gz >= 0 && gx < side && gy < side && gz < side) {
+      const unsigned m = morton3(gx, gy, gz);
+      st = g.leaf_start[m];
+      cnt = g.leaf_start[m + 1] - st;
+    }
+    sstart[tid] = st;
+  }
+  int total;
+  const int ex = block_exclusive_scan(cnt, swave, total);
+  if (tid < NR) soff[tid] = ex;
+  if (tid == 0) soff[NR] = total;
+  __syncthreads();
+
+  const int tb = g.leaf_start[blockIdx.x * B * B * B], te = g.leaf_start[(blockIdx.x + 1) * B * B * B];
+  const int nch = (total + CAP - 1) / CAP;
   const double c2 = kernel_param<KIND>(g.c);
-  double acc[RC];
+  for (int t0 = tb; t0 < te; t0 += kP2PThreads) {
+    const int i = t0 + tid;
+    const bool valid = i < te;
+    int ebase = 0, fi = -1;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    if (valid) {
+      int lx, ly, lz;
+      demorton3((unsigned)g.leaf_of[i], lx, ly, lz);
+      const int ox = lx - bx + 1, oy = ly - by + 1, oz = lz - bz + 1;
+      const int eo = ox + R * oy + R * R * oz;
+      fi = soff[eo] + (i - sstart[eo]);          // the target's own staged position
+      ebase = (ox - 1) + R * (oy - 1) + R * R * (oz - 1);
+      xi = g.xs[i];
+      yi = g.ys[i];
+      zi = g.zs[i];
+    }
+    double acc[RC];
 #pragma unroll
-  for (int r = 0; r < RC; ++r) acc[r] = 0.0;
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int nz = lz + dz;
-    if (nz < 0 || nz >= side) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int ny = ly + dy;
-      if (ny < 0 || ny >= side) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int nx = lx + dx;
-        if (nx < 0 || nx >= side) continue;
-        const unsigned nl = morton3(nx, ny, nz);
-        const int s = g.leaf_start[nl], e = g.leaf_start[nl + 1];
-        for (int j = s; j < e; ++j) {
-          if (j == i) continue;
-          const double ddx = xi - g.xs[j], ddy = yi - g.ys[j], ddz = zi - g.zs[j];
-          const double k = kern<KIND>(ddx * ddx + ddy * ddy + ddz * ddz, c2);
+    for (int r = 0; r < RC; ++r) acc[r] = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int c0 = ch * CAP, c1 = min(total, c0 + CAP);
+      if (nch > 1 || t0 == tb) {
+        __syncthreads();
+        for (int u = tid; u < c1 - c0; u += kP2PThreads) {
+          const int f = c0 + u;
+          int lo = 0, hi = NR;   // soff[lo] <= f < soff[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (soff[mid] <= f) lo = mid;
+            else hi = mid;
+          }
+          const long long j = sstart[lo] + (f - soff[lo]);
+          const double* qj = qs + j * nrhs + r0;
+          sp[u] = make_double4(g.xs[j], g.ys[j], g.zs[j], RC == 1 ? qj[0] : 0.0);
+          if (RC > 1) {
 #pragma unroll
-          for (int r = 0; r < RC; ++r) acc[r] += k * qs[(long long)j * nrhs + r0 + r];
+            for (int r = 0; r < RC; ++r) sq[u * RC + r] = qj[r];
+          }
+        }
+        __syncthreads();
+      }
+      if (!valid) continue;
+      // rows (dy, dz) in turn; f runs over the current row's staged points in this chunk
+      int row = 0, f = 0, fe = 0;
+      auto seg = [&](int rw) {
+        const int e0 = ebase + R * (rw % 3) + R * R * (rw / 3);
+        f = max(soff[e0], c0);
+        fe = min(soff[e0 + 3], c1);
+      };
+      seg(0);
+      while (f >= fe && ++row < 9) seg(row);
+      while (row < 9) {
+        {
+          const double4 s = sp[f - c0];
+          const double ddx = xi - s.x, ddy = yi - s.y, ddz = zi - s.z;
+          double k = kern<KIND>(ddx * ddx + ddy * ddy + ddz * ddz, c2);
+          k = f != fi ? k : 0.0;   // self-interaction excluded
+          if (RC == 1) {
+            acc[0] += k * s.w;
+          } else {
+#pragma unroll
+            for (int r = 0; r < RC; ++r) acc[r] += k * sq[(f - c0) * RC + r];
+          }
+        }
+        if (++f >= fe) {
+          while (++row < 9) {
+            seg(row);
+            if (f < fe) break;
+          }
         }
       }
     }
-  }
-  const long long dst = (long long)g.perm[i] * nrhs + r0;
+    if (valid) {
+      const long long dst = (long long)g.perm[i] * nrhs + r0;
 #pragma unroll
-  for (int r = 0; r < RC; ++r) {
-    const double f = far ? far[i * nrhs + r0 + r] : 0.0;
-    out[dst + r] = f + acc[r];
+      for (int r = 0; r < RC; ++r) {
+        const double fv = far ? far[(long long)i * nrhs + r0 + r] : 0.0;
+        out[dst + r] = fv + acc[r];
+      }
+    }
   }
 }
 
@@ -436,74 +627,113 @@ hipError_t dispatch_order(int order, Args... args) {
   }
 }
 
+// Leaves per P2M workgroup: the most whose work units fit one pass of the block.
+inline int p2m_group(int order, int rc) {
+  const int per_leaf = order * order * rc, pass = kP2MThreads * kP2MUnits;
+  return per_leaf >= pass ? 1 : pass / per_leaf;
+}
+
 template <int L> struct P2MRun {
-  static hipError_t run(const PassGeom& g, const double* qs, int nrhs, double* W, hipStream_t s) {
+  template <int RC>
+  static void go(const PassGeom& g, const double* qs, int nrhs, int r0, double* W, hipStream_t s) {
     const unsigned nleaf = 1u << (3 * g.depth);
-    const unsigned blocks = (nleaf + kP2MWaves - 1) / kP2MWaves;
-    hipLaunchKernelGGL(p2m_kernel<L>, dim3(blocks), dim3(64 * kP2MWaves), 0, s, g, qs, nrhs, W);
-    return hipGetLastError();
+    const int G = p2m_group(L, RC);
+    const unsigned blocks = (nleaf + G - 1) / G;
+    hipLaunchKernelGGL((p2m_kernel<L, RC>), dim3(blocks), dim3(kP2MThreads), 0, s, g, qs, nrhs, r0, G, W);
+  }
+  static hipError_t run(const PassGeom& g, const double* qs, int nrhs, double* W, hipStream_t s) {
+    for (int r0 = 0; r0 < nrhs;) {
+      const int left = nrhs - r0;
+      if (left >= 16) { go<16>(g, qs, nrhs, r0, W, s); r0 += 16; }
+      else if (left >= 4) { go<4>(g, qs, nrhs, r0, W, s); r0 += 4; }
+      else if (left >= 2) { go<2>(g, qs, nrhs, r0, W, s); r0 += 2; }
+      else { go<1>(g, qs, nrhs, r0, W, s); r0 += 1; }
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
 };
-// right-hand sides per LDS pass: the smallest power of two covering nrhs, capped by the buffer
-template <int L> constexpr int rc_cap() { return (kM2MBuf / (L * L * L)) >= 16 ? 16 : (kM2MBuf / (L * L * L)) >= 8 ? 8 : (kM2MBuf / (L * L * L)) >= 4 ? 4 : (kM2MBuf / (L * L * L)) >= 2 ? 2 : 1; }
-inline int rc_for(int nrhs, int cap) { int rc = 1; while (rc < nrhs && rc < cap) rc *= 2; return rc; }
-
 template <int L> struct M2MRun {
-  template <int RC>
-  static void go(const PassGeom& g, int pl, const double* Wc, double* Wp, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL((m2m_kernel<L, RC>), dim3(1u << (3 * pl)), dim3(kM2MThreads), 0, s, g, pl, Wc, Wp, nrhs);
-  }
   static hipError_t run(const PassGeom& g, int pl, const double* Wc, double* Wp, int nrhs, hipStream_t s) {
-    constexpr int cap = rc_cap<L>();
-    switch (rc_for(nrhs, cap)) {
-      case 1: go<1>(g, pl, Wc, Wp, nrhs, s); break;
-      case 2: go<(cap >= 2 ? 2 : 1)>(g, pl, Wc, Wp, nrhs, s); break;
-      case 4: go<(cap >= 4 ? 4 : 1)>(g, pl, Wc, Wp, nrhs, s); break;
-      case 8: go<(cap >= 8 ? 8 : 1)>(g, pl, Wc, Wp, nrhs, s); break;
-      default: go<cap>(g, pl, Wc, Wp, nrhs, s); break;
-    }
+    const long long nvec = (long long)(1u << (3 * pl)) * nrhs;
+    const unsigned blocks = (unsigned)std::min<long long>((nvec + m2m_nv<L>() - 1) / m2m_nv<L>(), 1 << 20);
+    hipLaunchKernelGGL((m2m_kernel<L>), dim3(blocks), dim3(kM2MThreads), 0, s, g, pl, Wc, Wp, nrhs);
     return hipGetLastError();
   }
 };
 template <int L> struct L2LRun {
-  template <int RC>
-  static void go(const PassGeom& g, int pl, const double* Fp, double* Fc, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL((l2l_kernel<L, RC>), dim3(1u << (3 * pl)), dim3(kM2MThreads), 0, s, g, pl, Fp, Fc, nrhs);
-  }
   static hipError_t run(const PassGeom& g, int pl, const double* Fp, double* Fc, int nrhs, hipStream_t s) {
-    constexpr int cap = rc_cap<L>();
-    switch (rc_for(nrhs, cap)) {
-      case 1: go<1>(g, pl, Fp, Fc, nrhs, s); break;
-      case 2: go<(cap >= 2 ? 2 : 1)>(g, pl, Fp, Fc, nrhs, s); break;
-      case 4: go<(cap >= 4 ? 4 : 1)>(g, pl, Fp, Fc, nrhs, s); break;
-      case 8: go<(cap >= 8 ? 8 : 1)>(g, pl, Fp, Fc, nrhs, s); break;
-      default: go<cap>(g, pl, Fp, Fc, nrhs, s); break;
-    }
+    const long long nvec = (long long)(1u << (3 * pl)) * nrhs;
+    const unsigned blocks = (unsigned)std::min<long long>((nvec + m2m_nv<L>() - 1) / m2m_nv<L>(), 1 << 20);
+    hipLaunchKernelGGL((l2l_kernel<L>), dim3(blocks), dim3(kM2MThreads), 0, s, g, pl, Fp, Fc, nrhs);
     return hipGetLastError();
   }
 };
+// Leaves per L2P wave: about 64 points' worth, within the LDS stage.
+inline int l2p_group(const PassGeom& g, int order, int rc) {
+  const double nleaf = (double)(1u << (3 * g.depth));
+  const double per_leaf = (double)g.n / nleaf;
+  int G = per_leaf > 0.0 ? (int)(64.0 / per_leaf) : 64;
+  const int cap = kL2PLds / (order * order * order * rc * (int)sizeof(double));
+  G = std::min(std::max(G, 1), std::max(cap, 1));
+  return std::min(G, 64);
+}
+
 template <int L> struct L2PRun {
+  template <int RC>
+  static void go(const PassGeom& g, const double* F, int nrhs, int r0, double* phis, hipStream_t s) {
+    const unsigned nleaf = 1u << (3 * g.depth);
+    const int G = l2p_group(g, L, RC);
+    const size_t lds = (size_t)G * L * L * L * RC * sizeof(double);
+    hipLaunchKernelGGL((l2p_kernel<L, RC>), dim3((nleaf + G - 1) / G), dim3(kL2PThreads), lds, s, g, F,
+                       nrhs, r0, G, phis);
+  }
   static hipError_t run(const PassGeom& g, const double* F, int nrhs, double* phis, hipStream_t s) {
-    hipLaunchKernelGGL(l2p_kernel<L>, dim3((unsigned)((g.n + 127) / 128)), dim3(128), 0, s, g, F, nrhs, phis);
-    return hipGetLastError();
+    for (int r0 = 0; r0 < nrhs;) {
+      if (nrhs - r0 >= 4) { go<4>(g, F, nrhs, r0, phis, s); r0 += 4; }
+      else { go<1>(g, F, nrhs, r0, phis, s); r0 += 1; }
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
 };
+
+// Leaf block edge of the near field: 4 (a 6^3-leaf region) when leaves hold few points, 2 when
+// they hold many or the tree is shallow, 1 for the root alone.
+inline int p2p_block_edge(const PassGeom& g) {
+  const int side = 1 << g.depth;
+  const double per_leaf = (double)g.n / ((double)side * side * side);
+  if (side >= 4 && per_leaf <= 8.0) return 4;
+  return side >= 2 ? 2 : 1;
+}
+
+template <int KIND, int RC>
+void p2p_go(const PassGeom& g, const double* qs, const double* far, int nrhs, int r0, double* out,
+            hipStream_t s) {
+  const int b = p2p_block_edge(g), side = 1 << g.depth;
+  const unsigned nb = (unsigned)(side / b);
+  const dim3 grid(nb * nb * nb), block(kP2PThreads);
+  if (b == 4) hipLaunchKernelGGL((p2p_kernel<KIND, RC, 4>), grid, block, 0, s, g, qs, far, nrhs, r0, out);
+  else if (b == 2) hipLaunchKernelGGL((p2p_kernel<KIND, RC, 2>), grid, block, 0, s, g, qs, far, nrhs, r0, out);
+  else hipLaunchKernelGGL((p2p_kernel<KIND, RC, 1>), grid, block, 0, s, g, qs, far, nrhs, r0, out);
+}
 
 template <int KIND>
 hipError_t p2p_kind(const PassGeom& g, const double* qs, const double* far, int nrhs, double* out,
                     hipStream_t s) {
-  const dim3 grid((unsigned)((g.n + 127) / 128)), block(128);
   int r0 = 0;
   while (r0 < nrhs) {
     const int left = nrhs - r0;
     if (left >= 16) {
-      hipLaunchKernelGGL((p2p_kernel<KIND, 16>), grid, block, 0, s, g, qs, far, nrhs, r0, out);
+      p2p_go<KIND, 16>(g, qs, far, nrhs, r0, out, s);
       r0 += 16;
     } else if (left >= 4) {
-      hipLaunchKernelGGL((p2p_kernel<KIND, 4>), grid, block, 0, s, g, qs, far, nrhs, r0, out);
+      p2p_go<KIND, 4>(g, qs, far, nrhs, r0, out, s);
       r0 += 4;
     } else {
-      hipLaunchKernelGGL((p2p_kernel<KIND, 1>), grid, block, 0, s, g, qs, far, nrhs, r0, out);
+      p2p_go<KIND, 1>(g, qs, far, nrhs, r0, out, s);
       r0 += 1;
     }
     const hipError_t e = hipGetLastError();
