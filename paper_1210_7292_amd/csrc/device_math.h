@@ -73,9 +73,8 @@ __device__ inline double kern(double r2, double kp) {
 template <int KIND>
 __device__ inline double kern_dr(double r2, double kp) {
   if (KIND == kInvR) {
-    if (!(r2 > 0.0)) return 0.0;
-    const double ir = rsqrt(r2);
-    return -ir * ir * ir;
+    const double ir = rsqrt(r2 > 0.0 ? r2 : 1.0);
+    return r2 > 0.0 ? -ir * ir * ir : 0.0;
   }
   if (KIND == kInvSqrtR2C2) {
     const double ir = rsqrt(r2 + kp);

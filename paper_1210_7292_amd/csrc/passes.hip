@@ -6,6 +6,7 @@
 // [cell][l^3][rhs] with cells of a level in Morton order and interpolation points in the order
 // m(a) = a1 + l a2 + l^2 a3 (Sec. 3.1).
 #include <algorithm>
+#include <cmath>
 
 #include "device_math.h"
 #include "internal.h"
@@ -145,9 +146,14 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(PassGeom g, int parent
   __shared__ double T[NV * 4 * NN];  // x stage [v][cy + 2 cz][B0 + L b1 + L^2 b2]
   const int tid = threadIdx.x;
   for (int i = tid; i < 2 * L * L; i += kM2MThreads) sM[i] = g.m2m[i];
-  const long long nvec = (long long)(1u << (3 * parent_level)) * nrhs;   // v = P * nrhs + r
-  for (long long v0 = (long long)blockIdx.x * NV; v0 < nvec; v0 += (long long)gridDim.x * NV) {
-    const int nv = (int)min((long long)NV, nvec - v0);
+  // a block owns PG whole parents and takes their (parent, rhs) vectors NV at a time, so the
+  // right-hand sides of a parent share one L2
+  const long long npar = 1ll << (3 * parent_level);
+  const int PG = max(1, NV / nrhs);
+  for (long long P0 = (long long)blockIdx.x * PG; P0 < npar; P0 += (long long)gridDim.x * PG)
+  for (int w0 = 0; w0 < (int)min((long long)PG, npar - P0) * nrhs; w0 += NV) {
+    const int nv = min(NV, (int)min((long long)PG, npar - P0) * nrhs - w0);
+    const long long v0 = P0 * nrhs + w0;   // vector v = P * nrhs + r
     double t[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -221,9 +227,12 @@ __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(PassGeom g, int parent
   __shared__ double T1[NV * 4 * NN];   // y stage [v][cy + 2 cz][B0 + L b1 + L^2 b2]
   const int tid = threadIdx.x;
   for (int i = tid; i < 2 * L * L; i += kM2MThreads) sM[i] = g.m2m[i];
-  const long long nvec = (long long)(1u << (3 * parent_level)) * nrhs;
-  for (long long v0 = (long long)blockIdx.x * NV; v0 < nvec; v0 += (long long)gridDim.x * NV) {
-    const int nv = (int)min((long long)NV, nvec - v0);
+  const long long npar = 1ll << (3 * parent_level);
+  const int PG = max(1, NV / nrhs);
+  for (long long P0 = (long long)blockIdx.x * PG; P0 < npar; P0 += (long long)gridDim.x * PG)
+  for (int w0 = 0; w0 < (int)min((long long)PG, npar - P0) * nrhs; w0 += NV) {
+    const int nv = min(NV, (int)min((long long)PG, npar - P0) * nrhs - w0);
+    const long long v0 = P0 * nrhs + w0;
     // the children's current locals (the M2L result), in flight during the contractions
     double old[PER];
     long long addr[PER];
@@ -353,6 +362,46 @@ __global__ __launch_bounds__(kL2PThreads) void l2p_kernel(PassGeom g, const doub
     for (int r = 0; r < RC; ++r)
       if (r < rc) phis[(long long)i * nrhs + r0 + r] = acc[r];
   }
+}
+
+// The same per point, reading the leaf's locals from memory (large expansions, sparse leaves).
+template <int L, int RC>
+__global__ __launch_bounds__(128) void l2p_direct_kernel(PassGeom g, const double* __restrict__ F,
+                                                         int nrhs, int r0, double* __restrict__ phis) {
+  constexpr int NN = L * L * L;
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  const int rc = min(RC, nrhs - r0);
+  const unsigned leaf = (unsigned)g.leaf_of[i];
+  double c[3], half;
+  cell_center(g, g.depth, leaf, c, &half);
+  const double inv_half = 1.0 / half;
+  double sx[L], sy[L], sz[L];
+  cheb_basis_all<L>((g.xs[i] - c[0]) * inv_half, g.tk, sx);
+  cheb_basis_all<L>((g.ys[i] - c[1]) * inv_half, g.tk, sy);
+  cheb_basis_all<L>((g.zs[i] - c[2]) * inv_half, g.tk, sz);
+  const double* Fl = F + (long long)leaf * NN * nrhs + r0;
+  double acc[RC];
+#pragma unroll
+  for (int r = 0; r < RC; ++r) acc[r] = 0.0;
+  for (int a2 = 0; a2 < L; ++a2)
+    for (int a1 = 0; a1 < L; ++a1) {
+      double sr[RC];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) sr[r] = 0.0;
+#pragma unroll
+      for (int a0 = 0; a0 < L; ++a0) {
+        const double* f = Fl + (long long)(a0 + L * a1 + L * L * a2) * nrhs;
+#pragma unroll
+        for (int r = 0; r < RC; ++r) sr[r] += sx[a0] * (r < rc ? f[r] : 0.0);
+      }
+      const double w = sy[a1] * sz[a2];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) acc[r] += w * sr[r];
+    }
+#pragma unroll
+  for (int r = 0; r < RC; ++r)
+    if (r < rc) phis[i * nrhs + r0 + r] = acc[r];
 }
 
 // ---- near field + scatter to the caller's order ------------------------------------------
@@ -582,6 +631,189 @@ __global__ void grad_kernel(PassGeom g, const double* __restrict__ qs, const dou
   out[dst + 2] = grad[2];
 }
 
+// ---- the same gradient with one right-hand side, in two tiled passes -----------------------
+// Far part: one wave per group of G leaves with both locals (of q and of g) staged in LDS, as
+// in L2P; it writes the far part. Near part: the near-field tiling with sources staged as
+// (x, y, z, q, g); it adds the near part (or writes it when there is no far field).
+template <int L>
+__global__ __launch_bounds__(kL2PThreads) void grad_far_kernel(PassGeom g, const double* __restrict__ qs,
+                                                               const double* __restrict__ gs,
+                                                               const double* __restrict__ Fq,
+                                                               const double* __restrict__ Fg, int roles,
+                                                               int G, double* __restrict__ out) {
+  constexpr int NN = L * L * L;
+  __shared__ double stk[L * L];
+  extern __shared__ double sF[];   // [G][NN] locals of q, then [G][NN] locals of g
+  const int tid = threadIdx.x;
+  for (int i = tid; i < L * L; i += kL2PThreads) stk[i] = g.tk[i];
+  const unsigned nleaf = 1u << (3 * g.depth);
+  const unsigned leaf0 = blockIdx.x * (unsigned)G;
+  const int ng = (int)min((unsigned)G, nleaf - leaf0);
+  const int tot = ng * NN;
+  for (int base = 0; base < tot; base += 4 * kL2PThreads) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * kL2PThreads + tid;
+      a[u] = idx < tot ? Fq[(long long)leaf0 * NN + idx] : 0.0;
+      b[u] = idx < tot ? Fg[(long long)leaf0 * NN + idx] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * kL2PThreads + tid;
+      if (idx < tot) {
+        sF[idx] = a[u];
+        sF[G * NN + idx] = b[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int ps = g.leaf_start[leaf0], pe = g.leaf_start[leaf0 + ng];
+  for (int i = ps + tid; i < pe; i += kL2PThreads) {
+    const unsigned leaf = (unsigned)g.leaf_of[i];
+    double c[3], half;
+    cell_center(g, g.depth, leaf, c, &half);
+    const double p[3] = {g.xs[i], g.ys[i], g.zs[i]};
+    double sv[3][L], dv[3][L];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const double u = (p[ax] - c[ax]) / half;
+      cheb_basis_all<L>(u, stk, sv[ax]);
+      cheb_basis_deriv_all<L>(u, stk, dv[ax]);
+    }
+    const double wq = (roles & 1) ? gs[i] : 0.0, wg = (roles & 2) ? qs[i] : 0.0;
+    const double* fq = sF + (leaf - leaf0) * NN;
+    const double* fg = fq + G * NN;
+    double gr[3] = {0.0, 0.0, 0.0};
+    for (int a2 = 0; a2 < L; ++a2)
+#pragma unroll
+      for (int a1 = 0; a1 < L; ++a1) {
+        double s0 = 0.0, d0 = 0.0;
+#pragma unroll
+        for (int a0 = 0; a0 < L; ++a0) {
+          const int beta = a0 + L * a1 + L * L * a2;
+          const double w = wq * fq[beta] + wg * fg[beta];
+          s0 += sv[0][a0] * w;
+          d0 += dv[0][a0] * w;
+        }
+        gr[0] += d0 * sv[1][a1] * sv[2][a2];
+        gr[1] += s0 * dv[1][a1] * sv[2][a2];
+        gr[2] += s0 * sv[1][a1] * dv[2][a2];
+      }
+    const double du = 1.0 / half;
+    const long long dst = (long long)g.perm[i] * 3;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[dst + d] = gr[d] * du;
+  }
+}
+
+template <int KIND, int B>
+__global__ __launch_bounds__(kP2PThreads) void grad_near_kernel(PassGeom g, const double* __restrict__ qs,
+                                                                const double* __restrict__ gs, int roles,
+                                                                int add, double* __restrict__ out) {
+  constexpr int R = B + 2, NR = R * R * R, CAP = 1024;
+  __shared__ int soff[NR + 1];
+  __shared__ int sstart[NR];
+  __shared__ int swave[kP2PThreads / 64];
+  __shared__ double4 sp[CAP];    // x, y, z, q
+  __shared__ double sgv[CAP];    // g
+  const int tid = threadIdx.x;
+  const int side = 1 << g.depth;
+  int bx, by, bz;
+  demorton3(blockIdx.x, bx, by, bz);
+  bx *= B;
+  by *= B;
+  bz *= B;
+  int cnt = 0, st = 0;
+  if (tid < NR) {
+    const int gx = bx - 1 + tid % R, gy = by - 1 + (tid / R) % R, gz = bz - 1 + tid / (R * R);
+    if (gx >= 0 && gy >= 0 && gz >= 0 && gx < side && gy < side && gz < side) {
+      const unsigned m = morton3(gx, gy, gz);
+      st = g.leaf_start[m];
+      cnt = g.leaf_start[m + 1] - st;
+    }
+    sstart[tid] = st;
+  }
+  int total;
+  const int ex = block_exclusive_scan(cnt, swave, total);
+  if (tid < NR) soff[tid] = ex;
+  if (tid == 0) soff[NR] = total;
+  __syncthreads();
+  const int tb = g.leaf_start[blockIdx.x * B * B * B], te = g.leaf_start[(blockIdx.x + 1) * B * B * B];
+  const int nch = (total + CAP - 1) / CAP;
+  const double c2 = kernel_param<KIND>(g.c);
+  for (int t0 = tb; t0 < te; t0 += kP2PThreads) {
+    const int i = t0 + tid;
+    const bool valid = i < te;
+    int ebase = 0, fi = -1;
+    double xi = 0.0, yi = 0.0, zi = 0.0, wq = 0.0, wg = 0.0;
+    if (valid) {
+      int lx, ly, lz;
+      demorton3((unsigned)g.leaf_of[i], lx, ly, lz);
+      const int ox = lx - bx + 1, oy = ly - by + 1, oz = lz - bz + 1;
+      const int eo = ox + R * oy + R * R * oz;
+      fi = soff[eo] + (i - sstart[eo]);
+      ebase = (ox - 1) + R * (oy - 1) + R * R * (oz - 1);
+      xi = g.xs[i];
+      yi = g.ys[i];
+      zi = g.zs[i];
+      wq = (roles & 1) ? gs[i] : 0.0;   // weights of the sources' q
+      wg = (roles & 2) ? qs[i] : 0.0;   // and of their g
+    }
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int ch = 0; ch < nch; ++ch) {
+      const int c0 = ch * CAP, c1 = min(total, c0 + CAP);
+      if (nch > 1 || t0 == tb) {
+        __syncthreads();
+        for (int u = tid; u < c1 - c0; u += kP2PThreads) {
+          const int f = c0 + u;
+          int lo = 0, hi = NR;
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (soff[mid] <= f) lo = mid;
+            else hi = mid;
+          }
+          const long long j = sstart[lo] + (f - soff[lo]);
+          sp[u] = make_double4(g.xs[j], g.ys[j], g.zs[j], qs[j]);
+          sgv[u] = gs[j];
+        }
+        __syncthreads();
+      }
+      if (!valid) continue;
+      int row = 0, f = 0, fe = 0;
+      auto seg = [&](int rw) {
+        const int e0 = ebase + R * (rw % 3) + R * R * (rw / 3);
+        f = max(soff[e0], c0);
+        fe = min(soff[e0 + 3], c1);
+      };
+      seg(0);
+      while (f >= fe && ++row < 9) seg(row);
+      while (row < 9) {
+        {
+          const double4 sj = sp[f - c0];
+          const double ddx = xi - sj.x, ddy = yi - sj.y, ddz = zi - sj.z;
+          double k = kern_dr<KIND>(ddx * ddx + ddy * ddy + ddz * ddz, c2) * (wq * sj.w + wg * sgv[f - c0]);
+          k = f != fi ? k : 0.0;
+          acc[0] += k * ddx;
+          acc[1] += k * ddy;
+          acc[2] += k * ddz;
+        }
+        if (++f >= fe) {
+          while (++row < 9) {
+            seg(row);
+            if (f < fe) break;
+          }
+        }
+      }
+    }
+    if (valid) {
+      const long long dst = (long long)g.perm[i] * 3;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) out[dst + d] = (add ? out[dst + d] : 0.0) + acc[d];
+    }
+  }
+}
+
 // ---- non-empty pair counting for the algorithmic flop count -------------------------------
 __device__ inline bool cell_nonempty(const int* leaf_start, int depth, int level, unsigned cell) {
   const int sh = 3 * (depth - level);
@@ -627,17 +859,22 @@ hipError_t dispatch_order(int order, Args... args) {
   }
 }
 
-// Leaves per P2M workgroup: the most whose work units fit one pass of the block.
-inline int p2m_group(int order, int rc) {
+// Leaves per P2M workgroup: the most whose work units fit one pass of the block, and enough
+// to hold about 48 points (sparse leaves then take several passes per group rather than one
+// small workgroup each).
+inline int p2m_group(const PassGeom& g, int order, int rc) {
   const int per_leaf = order * order * rc, pass = kP2MThreads * kP2MUnits;
-  return per_leaf >= pass ? 1 : pass / per_leaf;
+  int G = per_leaf >= pass ? 1 : pass / per_leaf;
+  const double pts = (double)g.n / (double)(1u << (3 * g.depth));
+  if (pts > 0.0) G = std::max(G, (int)std::ceil(48.0 / pts));
+  return std::min(G, pass);
 }
 
 template <int L> struct P2MRun {
   template <int RC>
   static void go(const PassGeom& g, const double* qs, int nrhs, int r0, double* W, hipStream_t s) {
     const unsigned nleaf = 1u << (3 * g.depth);
-    const int G = p2m_group(L, RC);
+    const int G = p2m_group(g, L, RC);
     const unsigned blocks = (nleaf + G - 1) / G;
     hipLaunchKernelGGL((p2m_kernel<L, RC>), dim3(blocks), dim3(kP2MThreads), 0, s, g, qs, nrhs, r0, G, W);
   }
@@ -654,18 +891,21 @@ template <int L> struct P2MRun {
     return hipSuccess;
   }
 };
+inline unsigned m2m_blocks(int pl, int nrhs, int nv) {
+  const long long npar = 1ll << (3 * pl);
+  const int pg = std::max(1, nv / nrhs);
+  return (unsigned)std::min<long long>((npar + pg - 1) / pg, 1 << 20);
+}
 template <int L> struct M2MRun {
   static hipError_t run(const PassGeom& g, int pl, const double* Wc, double* Wp, int nrhs, hipStream_t s) {
-    const long long nvec = (long long)(1u << (3 * pl)) * nrhs;
-    const unsigned blocks = (unsigned)std::min<long long>((nvec + m2m_nv<L>() - 1) / m2m_nv<L>(), 1 << 20);
+    const unsigned blocks = m2m_blocks(pl, nrhs, m2m_nv<L>());
     hipLaunchKernelGGL((m2m_kernel<L>), dim3(blocks), dim3(kM2MThreads), 0, s, g, pl, Wc, Wp, nrhs);
     return hipGetLastError();
   }
 };
 template <int L> struct L2LRun {
   static hipError_t run(const PassGeom& g, int pl, const double* Fp, double* Fc, int nrhs, hipStream_t s) {
-    const long long nvec = (long long)(1u << (3 * pl)) * nrhs;
-    const unsigned blocks = (unsigned)std::min<long long>((nvec + m2m_nv<L>() - 1) / m2m_nv<L>(), 1 << 20);
+    const unsigned blocks = m2m_blocks(pl, nrhs, m2m_nv<L>());
     hipLaunchKernelGGL((l2l_kernel<L>), dim3(blocks), dim3(kM2MThreads), 0, s, g, pl, Fp, Fc, nrhs);
     return hipGetLastError();
   }
@@ -685,6 +925,12 @@ template <int L> struct L2PRun {
   static void go(const PassGeom& g, const double* F, int nrhs, int r0, double* phis, hipStream_t s) {
     const unsigned nleaf = 1u << (3 * g.depth);
     const int G = l2p_group(g, L, RC);
+    if (G * (double)g.n / nleaf < 16.0) {
+      // too few points per staged group to fill a wave: one thread per point, locals from L2
+      hipLaunchKernelGGL((l2p_direct_kernel<L, RC>), dim3((unsigned)((g.n + 127) / 128)), dim3(128), 0, s, g,
+                         F, nrhs, r0, phis);
+      return;
+    }
     const size_t lds = (size_t)G * L * L * L * RC * sizeof(double);
     hipLaunchKernelGGL((l2p_kernel<L, RC>), dim3((nleaf + G - 1) / G), dim3(kL2PThreads), lds, s, g, F,
                        nrhs, r0, G, phis);
@@ -746,8 +992,25 @@ template <int KIND> struct GradAtKind {
   template <int L> struct Run {
     static hipError_t run(const PassGeom& g, const double* qs, const double* gs, const double* Fq,
                           const double* Fg, int nrhs, int roles, double* out, hipStream_t s) {
-      hipLaunchKernelGGL((grad_kernel<KIND, L>), dim3((unsigned)((g.n + 127) / 128)), dim3(128), 0, s,
-                         g, qs, gs, Fq, Fg, nrhs, roles, out);
+      const unsigned nleaf = 1u << (3 * g.depth);
+      const int G = l2p_group(g, L, 2);
+      const bool far = Fq != nullptr;
+      if (nrhs != 1 || (far && G * (double)g.n / nleaf < 16.0)) {
+        hipLaunchKernelGGL((grad_kernel<KIND, L>), dim3((unsigned)((g.n + 127) / 128)), dim3(128), 0, s,
+                           g, qs, gs, Fq, Fg, nrhs, roles, out);
+        return hipGetLastError();
+      }
+      if (far) {
+        const size_t lds = (size_t)2 * G * L * L * L * sizeof(double);
+        hipLaunchKernelGGL((grad_far_kernel<L>), dim3((nleaf + G - 1) / G), dim3(kL2PThreads), lds, s, g, qs, gs,
+                           Fq, Fg, roles, G, out);
+      }
+      const int b = p2p_block_edge(g), side = 1 << g.depth;
+      const unsigned nb = (unsigned)(side / b);
+      const int add = far ? 1 : 0;
+      if (b == 4) hipLaunchKernelGGL((grad_near_kernel<KIND, 4>), dim3(nb * nb * nb), dim3(kP2PThreads), 0, s, g, qs, gs, roles, add, out);
+      else if (b == 2) hipLaunchKernelGGL((grad_near_kernel<KIND, 2>), dim3(nb * nb * nb), dim3(kP2PThreads), 0, s, g, qs, gs, roles, add, out);
+      else hipLaunchKernelGGL((grad_near_kernel<KIND, 1>), dim3(nb * nb * nb), dim3(kP2PThreads), 0, s, g, qs, gs, roles, add, out);
       return hipGetLastError();
     }
   };
