@@ -216,7 +216,7 @@ void free_tree_arrays(bbfmm_tree* t) {
 bbfmm_status adaptive_segments(bbfmm_plan* p, int nrhs, hipStream_t s) {
   if (p->segs_nrhs == nrhs || p->h_segs.empty()) return BBFMM_OK;
   BBFMM_HIP_TRY(hipStreamSynchronize(s));
-  const int cols = m2l_block_cols(p->lowrank);
+  const int cols = m2l_block_cols(p->lowrank, p->order, p->prec);
   long long blocks = 0;
   for (M2LLevel& sg : p->h_segs) {
     const long long c = (long long)sg.npar * nrhs;
@@ -241,7 +241,7 @@ M2LArgs adaptive_m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double
   a.lv[0].F = F;
   a.nlev = 0;
   a.nblocks = p->seg_blocks;
-  a.cols = m2l_block_cols(p->lowrank);
+  a.cols = m2l_block_cols(p->lowrank, p->order, p->prec);
   a.ops_hi = p->ops_hi; a.ops_lo = p->ops_lo;
   a.op_off = p->d_op_off; a.op_rank = p->d_op_rank;
   a.tab = p->d_tab; a.grp = p->d_grp; a.sig = p->d_sig; a.siginv = p->d_siginv;

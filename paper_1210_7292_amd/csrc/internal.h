@@ -115,10 +115,10 @@ long long m2l_split_scratch_doubles(int order, int slots);
 // Returns the LDS-capacity rank limit of the compressed M2L kernel for an order.
 int m2l_ia_rank_limit(int order);
 // Columns ((target, rhs) pairs) per M2L workgroup.
-int m2l_block_cols(bool lowrank);
+int m2l_block_cols(bool lowrank, int order, int prec);
 // Launches the M2L over the levels in `a` (blocks = a.nblocks rounded up to 8). Uniform trees:
 // the tiling is computed here. Adaptive trees (a.segs set): a.nblocks, a.cols and the segments'
-// block_begin come from the caller, with a.cols = m2l_block_cols(lowrank).
+// block_begin come from the caller, with a.cols = m2l_block_cols(lowrank, order, prec).
 hipError_t launch_m2l(int order, bool lowrank, int prec, const M2LArgs& a, hipStream_t s);
 // MFMA work actually issued per (target tile of 64 columns, representative p, one t),
 // in flops, for reporting.

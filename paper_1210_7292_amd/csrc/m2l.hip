@@ -503,9 +503,9 @@ struct Lowrank {
   static constexpr int LD = RMAX + 1;
   static constexpr bool SPLIT = PREC == 2;
   static constexpr bool PREFETCH = K16 <= 8;
-  // chunk of super-steps held in registers: the whole column with 4 waves; half of it with 8
-  // waves (2 waves per SIMD halve the register budget; the other wave covers the second load)
-  static constexpr int CH = PREFETCH ? (W8 == 4 ? K16 : (K16 + 1) / 2) : 4;
+  // chunk of super-steps held in registers: half the column (with 2 waves per SIMD the register
+  // budget holds no more; the other wave on the SIMD covers the second chunk's load)
+  static constexpr int CH = PREFETCH ? (K16 + 1) / 2 : 4;
   static constexpr int NCHUNK = (K16 + CH - 1) / CH;
 
   static __device__ inline void load(gdouble* src, int nrhs, int kq, int c0, double (&w)[CH][4]) {
@@ -578,7 +578,7 @@ struct Lowrank {
 };
 
 template <int L, int RMAX, int PREC, int W8, bool ONE_RHS, bool AD>
-__global__ __launch_bounds__(64 * W8) void m2l_lowrank_kernel(M2LArgs a) {
+__global__ __launch_bounds__(64 * W8, 2) void m2l_lowrank_kernel(M2LArgs a) {
   using K = Lowrank<L, RMAX, PREC, W8, ONE_RHS>;
   using T = typename K::T;
   using V = typename K::V;
@@ -770,7 +770,17 @@ template <int L, int PREC> constexpr int full_kc() { return L <= 2 ? 8 : (L == 8
 // the largest orders fit the register file with two waves per SIMD
 template <int L> constexpr int full_rs() { return L >= 7 ? 2 : 1; }
 template <int L> constexpr int rank_limit() { return L <= 6 ? 32 : 16; }
-constexpr int kLowrankWaves = 8;
+// Waves per compressed-kernel workgroup: 4 (64 columns) when the workgroup's LDS lets two of
+// them share a CU, so that one computes while the other restages factors at a representative
+// change; 8 otherwise. Mirrors the kernel's LDS arrays.
+constexpr int lowrank_lds_bytes(int L, int prec) {
+  const int nn = L * L * L, np = (nn + 15) / 16 * 16, rmax = L <= 6 ? 32 : 16;
+  const int factors = 2 * (prec == 2 ? 2 : 1) * (nn + 1) * (rmax + 1) * (prec == 0 ? 8 : 4);
+  const int sig = factors + kNumPerms * np * 2 <= 160 * 1024 ? kNumPerms * np * 2 : 0;
+  return factors + sig + kFarPerOctant * 4 + kNumSym * 4 + 2 * kNumSym * 8 + 16;
+}
+constexpr int lowrank_waves(int L, int prec) { return lowrank_lds_bytes(L, prec) <= 80 * 1024 ? 4 : 8; }
+constexpr int kLowrankWavesMax = 8;
 
 // Fills the per-level tiling for `cols` columns per block.
 void tile(M2LArgs& a, int cols) {
@@ -818,21 +828,22 @@ template <int L, int PREC, bool AD>
 hipError_t launch_ld(bool lowrank, M2LArgs a, hipStream_t s) {
   if (lowrank) {
     if constexpr (L >= 3) {
-      auto kern1 = m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, true, AD>;
-      auto kernn = m2l_lowrank_kernel<L, rank_limit<L>(), PREC, kLowrankWaves, false, AD>;
+      constexpr int W8 = lowrank_waves(L, PREC);
+      auto kern1 = m2l_lowrank_kernel<L, rank_limit<L>(), PREC, W8, true, AD>;
+      auto kernn = m2l_lowrank_kernel<L, rank_limit<L>(), PREC, W8, false, AD>;
       unsigned grid;
       if (!AD) {
-        tile(a, 16 * kLowrankWaves);
-        split_tail(a, a.nrhs == 1 ? (const void*)kern1 : (const void*)kernn, 64 * kLowrankWaves,
+        tile(a, 16 * W8);
+        split_tail(a, a.nrhs == 1 ? (const void*)kern1 : (const void*)kernn, 64 * W8,
                    (L * L * L + 15) / 16 * 16);
         grid = (unsigned)(a.main_grid + a.ntail * a.tsplit);
       } else {
         grid = (unsigned)((a.nblocks + 7) / 8 * 8);
       }
       if (a.nrhs == 1)
-        hipLaunchKernelGGL(kern1, dim3(grid), dim3(64 * kLowrankWaves), 0, s, a);
+        hipLaunchKernelGGL(kern1, dim3(grid), dim3(64 * W8), 0, s, a);
       else
-        hipLaunchKernelGGL(kernn, dim3(grid), dim3(64 * kLowrankWaves), 0, s, a);
+        hipLaunchKernelGGL(kernn, dim3(grid), dim3(64 * W8), 0, s, a);
     } else {
       return hipErrorInvalidValue;
     }
@@ -877,13 +888,15 @@ int m2l_ia_rank_limit(int order) {
   return order <= 6 ? 32 : 16;
 }
 
-int m2l_block_cols(bool lowrank) { return lowrank ? 16 * kLowrankWaves : kCols; }
+int m2l_block_cols(bool lowrank, int order, int prec) {
+  return lowrank ? 16 * lowrank_waves(order, prec) : kCols;
+}
 
 long long m2l_split_scratch_doubles(int order, int slots) {
   // split parts of one launch: rem * parts <= slots (parts <= slots / rem, or 2 when rem is
   // within slots / 2)
   const int np = (order * order * order + 15) / 16 * 16;
-  return (long long)slots * np * 16 * kLowrankWaves;
+  return (long long)slots * np * 16 * kLowrankWavesMax;
 }
 
 hipError_t launch_m2l(int order, bool lowrank, int prec, const M2LArgs& a0, hipStream_t s) {
