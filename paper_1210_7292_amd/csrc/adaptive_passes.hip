@@ -289,32 +289,68 @@ __global__ __launch_bounds__(kAdP2LThreads) void ad_p2l_kernel(AdaptiveGeom g, c
 }
 
 // ---- L2P: phi_far[i] = sum_a S(x_i, xbar_a) F_leaf[a] ----------------------------------------
+// One workgroup per leaf: its locals are staged in LDS in chunks of right-hand sides; wave w takes
+// right-hand sides w, w + 4, ... of a chunk with one lane per point, so every read of a local
+// coefficient is one LDS address for the whole wave (a broadcast).
+constexpr int kAdL2PThreads = 256;
+constexpr int kAdL2PLds = 32 * 1024;   // bytes of locals staged per chunk
+
 template <int L>
-__global__ void ad_l2p_kernel(AdaptiveGeom g, const double* __restrict__ F, int nrhs,
-                              double* __restrict__ phis) {
+__global__ __launch_bounds__(kAdL2PThreads) void ad_l2p_kernel(AdaptiveGeom g, const int* __restrict__ leaves,
+                                                               const double* __restrict__ F, int nrhs,
+                                                               int rcmax, double* __restrict__ phis) {
   constexpr int NN = L * L * L;
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
-  const int leaf = g.leaf_of[i];
+  __shared__ double stk[L * L];
+  extern __shared__ double sF[];   // [NN][rc]: the leaf's locals of one right-hand-side chunk
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  constexpr int NW = kAdL2PThreads / 64;
+  for (int i = tid; i < L * L; i += kAdL2PThreads) stk[i] = g.tk[i];
+  const int leaf = leaves[blockIdx.x];
+  const int ps = g.start[leaf], pe = g.end[leaf];
   const double* cp = g.cen + 4LL * leaf;
   const double inv_half = 1.0 / cp[3];
-  double sx[L], sy[L], sz[L];
-  cheb_basis_all<L>((g.xs[i] - cp[0]) * inv_half, g.tk, sx);
-  cheb_basis_all<L>((g.ys[i] - cp[1]) * inv_half, g.tk, sy);
-  cheb_basis_all<L>((g.zs[i] - cp[2]) * inv_half, g.tk, sz);
   const double* Fl = F + (long long)leaf * NN * nrhs;
-  for (int r = 0; r < nrhs; ++r) {
-    double acc = 0.0;
+  for (int r0 = 0; r0 < nrhs; r0 += rcmax) {
+    const int rc = min(rcmax, nrhs - r0);
+    const int tot = NN * rc;
+    __syncthreads();
+    for (int base = 0; base < tot; base += 8 * kAdL2PThreads) {
+      double t[8];
 #pragma unroll
-    for (int a2 = 0; a2 < L; ++a2)
-#pragma unroll
-      for (int a1 = 0; a1 < L; ++a1) {
-        double s = 0.0;
-#pragma unroll
-        for (int a0 = 0; a0 < L; ++a0) s += sx[a0] * Fl[(a0 + L * a1 + L * L * a2) * nrhs + r];
-        acc += sy[a1] * sz[a2] * s;
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + u * kAdL2PThreads + tid;
+        const int beta = idx / rc, r = idx - beta * rc;
+        t[u] = idx < tot ? Fl[(long long)beta * nrhs + r0 + r] : 0.0;
       }
-    phis[i * nrhs + r] = acc;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + u * kAdL2PThreads + tid;
+        if (idx < tot) sF[idx] = t[u];
+      }
+    }
+    __syncthreads();
+    for (int i0 = ps; i0 < pe; i0 += 64) {
+      const int i = i0 + lane;
+      const bool ok = i < pe;
+      double sx[L], sy[L], sz[L];
+      const int ii = ok ? i : ps;
+      cheb_basis_all<L>((g.xs[ii] - cp[0]) * inv_half, stk, sx);
+      cheb_basis_all<L>((g.ys[ii] - cp[1]) * inv_half, stk, sy);
+      cheb_basis_all<L>((g.zs[ii] - cp[2]) * inv_half, stk, sz);
+      for (int r = wave; r < rc; r += NW) {
+        double acc = 0.0;
+#pragma unroll 1
+        for (int a2 = 0; a2 < L; ++a2)
+#pragma unroll
+          for (int a1 = 0; a1 < L; ++a1) {
+            double sa = 0.0;
+#pragma unroll
+            for (int a0 = 0; a0 < L; ++a0) sa += sx[a0] * sF[(a0 + L * a1 + L * L * a2) * rc + r];
+            acc += sy[a1] * sz[a2] * sa;
+          }
+        if (ok) phis[(long long)i * nrhs + r0 + r] = acc;
+      }
+    }
   }
 }
 
@@ -505,8 +541,13 @@ template <int L> struct AdL2L {
 };
 
 template <int L> struct AdL2P {
-  static hipError_t run(const AdaptiveGeom& g, const double* F, int nrhs, double* phis, hipStream_t s) {
-    hipLaunchKernelGGL(ad_l2p_kernel<L>, dim3((unsigned)((g.n + 127) / 128)), dim3(128), 0, s, g, F, nrhs, phis);
+  static hipError_t run(const AdaptiveGeom& g, const int* leaves, int nleaves, const double* F, int nrhs,
+                        double* phis, hipStream_t s) {
+    if (nleaves <= 0) return hipSuccess;
+    const int rcmax = std::max(1, std::min(nrhs, kAdL2PLds / (L * L * L * (int)sizeof(double))));
+    const size_t lds = (size_t)L * L * L * rcmax * sizeof(double);
+    hipLaunchKernelGGL(ad_l2p_kernel<L>, dim3((unsigned)nleaves), dim3(kAdL2PThreads), lds, s, g, leaves, F,
+                       nrhs, rcmax, phis);
     return hipGetLastError();
   }
 };
@@ -625,8 +666,9 @@ hipError_t launch_ad_p2l(const AdaptiveGeom& g, const int* x_node, const int* x_
                          const double* qs, int nrhs, double* F, hipStream_t s) {
   return ad_kind<AdP2L>(g.kernel, g, x_node, x_off, x_idx, nx, qs, nrhs, F, s);
 }
-hipError_t launch_ad_l2p(const AdaptiveGeom& g, const double* F, int nrhs, double* phis, hipStream_t s) {
-  return ad_order<AdL2P>(g.order, g, F, nrhs, phis, s);
+hipError_t launch_ad_l2p(const AdaptiveGeom& g, const int* leaves, int nleaves, const double* F, int nrhs,
+                         double* phis, hipStream_t s) {
+  return ad_order<AdL2P>(g.order, g, leaves, nleaves, F, nrhs, phis, s);
 }
 hipError_t launch_ad_m2p(const AdaptiveGeom& g, const int* leaves, const int* w_off, const int* w_idx,
                          int nleaves, const double* W, int nrhs, double* phis, hipStream_t s) {

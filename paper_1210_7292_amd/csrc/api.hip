@@ -302,7 +302,7 @@ bbfmm_status run_chain_adaptive(bbfmm_plan* p, const double* in, int nrhs, doubl
     for (int l = 2; l < t->depth; ++l)
       BBFMM_HIP_TRY(launch_ad_l2l(g, T.level_off[l], T.level_off[l + 1], F, nrhs, s));
     BBFMM_HIP_TRY(mark(p, kL2L, s));
-    BBFMM_HIP_TRY(launch_ad_l2p(g, F, nrhs, p->phis, s));
+    BBFMM_HIP_TRY(launch_ad_l2p(g, t->d_leaves, nleaves, F, nrhs, p->phis, s));
     if (!T.w_idx.empty())
       BBFMM_HIP_TRY(launch_ad_m2p(g, t->d_leaves, t->d_w_off, t->d_w_idx, nleaves, W, nrhs, p->phis, s));
     BBFMM_HIP_TRY(mark(p, kL2P, s));

@@ -249,7 +249,8 @@ hipError_t launch_ad_l2l(const AdaptiveGeom& g, int node_begin, int node_end, do
                          hipStream_t s);
 hipError_t launch_ad_p2l(const AdaptiveGeom& g, const int* x_node, const int* x_off, const int* x_idx,
                          int nx, const double* qs, int nrhs, double* F, hipStream_t s);
-hipError_t launch_ad_l2p(const AdaptiveGeom& g, const double* F, int nrhs, double* phis, hipStream_t s);
+hipError_t launch_ad_l2p(const AdaptiveGeom& g, const int* leaves, int nleaves, const double* F, int nrhs,
+                         double* phis, hipStream_t s);
 hipError_t launch_ad_m2p(const AdaptiveGeom& g, const int* leaves, const int* w_off, const int* w_idx,
                          int nleaves, const double* W, int nrhs, double* phis, hipStream_t s);
 hipError_t launch_ad_p2p_scatter(const AdaptiveGeom& g, const int* leaf_pos, const int* u_off,

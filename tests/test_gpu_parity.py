@@ -314,6 +314,27 @@ def test_adjoint_and_gradient_match_oracle():
     assert rel(gt + gs, grad) < 1e-14
 
 
+def test_clustered_points_on_a_uniform_tree():
+    """A dense cluster (about 140 points in each of 8 leaves) beside sparse leaves: the cluster's
+    6^3-leaf region holds more points than one LDS stage of the near field and of the gradient's
+    near part, so both run in chunks; P2M takes several point batches per leaf group and L2P
+    several passes of its wave over the group's points."""
+    say("clustered")
+    rng = np.random.default_rng(21)
+    pts = np.concatenate([0.25 + 0.25 * rng.random((1100, 3)), rng.random((400, 3))])
+    n, order, depth = pts.shape[0], 4, 3
+    q, g = rng.uniform(-1, 1, (n, 2)), rng.uniform(-1, 1, (n, 1))
+    tree = pk.Octree(dev(pts), depth)
+    plan = pk.Plan(tree, "inv_r", order)
+    phi = host(plan.apply(dev(q)))
+    assert rel(phi, O.fmm_apply(pts, q, order, depth, "inv_r").phi) < 1e-12
+    q1 = np.ascontiguousarray(q[:, :1])
+    plan.apply(dev(q1))
+    plan.apply_adjoint(dev(g))
+    grad = host(plan.eval_grad(dev(q1), dev(g), 3))
+    assert rel(grad, O.fmm_grad_points(pts, q1, g, order, depth)) < 1e-11
+
+
 def test_autograd_against_finite_differences():
     say("autograd")
     rng = np.random.default_rng(14)
