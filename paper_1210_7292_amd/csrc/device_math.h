@@ -52,8 +52,8 @@ __host__ __device__ inline double kernel_param(double c) {
 template <int KIND>
 __device__ inline double kern(double r2, double kp) {
   if (KIND == kInvR) {
-    // branch-free: rsqrt of a safe argument, then the select for r = 0
-    const double ir = rsqrt(r2 > 0.0 ? r2 : 1.0);
+    // branch-free: the select for r = 0 discards rsqrt(0) = inf
+    const double ir = rsqrt(r2);
     return r2 > 0.0 ? ir : 0.0;
   }
   if (KIND == kInvSqrtR2C2) return rsqrt(r2 + kp);
@@ -73,7 +73,7 @@ __device__ inline double kern(double r2, double kp) {
 template <int KIND>
 __device__ inline double kern_dr(double r2, double kp) {
   if (KIND == kInvR) {
-    const double ir = rsqrt(r2 > 0.0 ? r2 : 1.0);
+    const double ir = rsqrt(r2);
     return r2 > 0.0 ? -ir * ir * ir : 0.0;
   }
   if (KIND == kInvSqrtR2C2) {
