@@ -42,7 +42,8 @@ __global__ void gather_rows_kernel(const double* __restrict__ in, const int* __r
 // basis values of a batch of the group's points are computed once per point into LDS. A work
 // unit is (leaf, a1, a2, rhs): it accumulates the L outputs a0 = 0..L-1 of that line over the
 // leaf's points in the batch, so one product S_y S_z q serves L outputs. Each thread owns up to
-// kP2MUnits units of a pass; G is chosen so that one pass covers the group.
+// kP2MUnits units of a pass; G is chosen so that one pass covers the group, or larger where
+// leaves are sparse (the group then takes several passes).
 constexpr int kP2MThreads = 256;
 constexpr int kP2MBatch = 128;
 constexpr int kP2MUnits = 2;
