@@ -652,7 +652,7 @@ __global__ __launch_bounds__(64 * W8, 2) void m2l_lowrank_kernel(M2LArgs a) {
       const T* Ul = SPLIT ? static_cast<const T*>(a.ops_lo) + offu : nullptr;
       const T* Vl = SPLIT ? static_cast<const T*>(a.ops_lo) + offv : nullptr;
       // factor loads in batches of SB issued back to back, then their LDS stores
-      constexpr int SB = 4;
+      constexpr int SB = 8;
       const int tot = (NN + 1) * rv;
 #pragma unroll 1
       for (int x0 = tid; x0 < tot; x0 += SB * NT) {
@@ -669,23 +669,20 @@ __global__ __launch_bounds__(64 * W8, 2) void m2l_lowrank_kernel(M2LArgs a) {
             tvl[u] = Vl[gv];
             tul[u] = Ul[gu];
           }
-          if (!inv) tv[u] = T(0);
-          if (!inu) tu[u] = T(0);
-          if (SPLIT) {
-            if (!inv) tvl[u] = T(0);
-            if (!inu) tul[u] = T(0);
-          }
         }
+        // entries outside the factors (the zero row l^3, U's columns beyond ceil4(r)) are zeroed
+        // here rather than at the loads, so the loads of a batch are all in flight together
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
           const int x = x0 + u * NT;
           if (x < tot) {
             const int row = x / rv, cc = x - row * rv;
-            vhi[row * LD + cc] = tv[u];
-            uhi[row * LD + cc] = tu[u];
+            const bool inv = row < NN, inu = inv && cc < ru;
+            vhi[row * LD + cc] = inv ? tv[u] : T(0);
+            uhi[row * LD + cc] = inu ? tu[u] : T(0);
             if (SPLIT) {
-              vlo[row * LD + cc] = tvl[u];
-              ulo[row * LD + cc] = tul[u];
+              vlo[row * LD + cc] = inv ? tvl[u] : T(0);
+              ulo[row * LD + cc] = inu ? tul[u] : T(0);
             }
           }
         }
