@@ -698,6 +698,115 @@ def fmm_apply(points: np.ndarray, q: np.ndarray, order: int, depth: int, kind: s
     return FMMResult(far + near, mult, loc_m2l, loc, near, far, stats)
 
 
+def p2m_chunked(tree: UniformTree, q: np.ndarray, order: int, chunk: int = 1 << 17) -> np.ndarray:
+    """Leaf multipoles as `p2m`, with the points taken in chunks of the leaf order (bounded
+    memory for millions of points): within a chunk each leaf's points are summed in index order."""
+    n = tree.points.shape[0]
+    nleaf = 8 ** tree.depth
+    out = np.zeros((nleaf, order ** 3, q.shape[1]))
+    by_leaf = np.argsort(tree.leaf, kind="stable")
+    lc = tree.local_coords()
+    for s0 in range(0, n, chunk):
+        idx = by_leaf[s0:s0 + chunk]
+        leaves = tree.leaf[idx]
+        heads = np.flatnonzero(np.r_[True, leaves[1:] != leaves[:-1]])
+        basis = tensor_basis(lc[idx], order)
+        for r in range(q.shape[1]):
+            out[leaves[heads], :, r] += np.add.reduceat(basis * q[idx, r:r + 1], heads, axis=0)
+    return out
+
+
+def interaction_pairs_of(level: int, cells: np.ndarray):
+    """The far-field pairs of `interaction_pairs` restricted to the given target cells (cell
+    indices of `level`): {t: (target cell, source cell)}, the same rule (Sec. 3.2)."""
+    s = 1 << level
+    cells = np.asarray(cells, dtype=np.int64)
+    X = np.stack([cells % s, (cells // s) % s, cells // (s * s)], axis=1)
+    out = {}
+    for t in far_transfer_vectors():
+        Y = X - np.asarray(t)[None, :]
+        inside = np.all((Y >= 0) & (Y < s), axis=1)
+        parents_near = np.max(np.abs(X // 2 - Y // 2), axis=1) <= 1
+        not_near = np.max(np.abs(X - Y), axis=1) > 1
+        ok = inside & parents_near & not_near
+        if np.any(ok):
+            out[t] = (cells[ok], UniformTree.cell_index(Y[ok], level))
+    return out
+
+
+def fmm_apply_sampled(points: np.ndarray, q: np.ndarray, order: int, depth: int, targets: np.ndarray,
+                      kind: str = "inv_r", c: float = 0.0, eps: float = 0.0, lo=(0.0, 0.0, 0.0),
+                      width: float = 1.0, compressor: str = "svd") -> np.ndarray:
+    """phi of `fmm_apply` at the selected targets only, (len(targets), nrhs).
+
+    The same passes in the same order, evaluated only where the targets need them: P2M and
+    M2M for every cell (multipoles of all sources), the M2L of Eq. (m2l_bbfmm) for the
+    ancestors of the targets' leaves at each level (operators formed directly per t at the
+    level's width, no symmetries), L2L down those ancestor chains, L2P and the near field at
+    the targets. For point sets too large for the full sweep."""
+    points = np.ascontiguousarray(points, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    if q.ndim == 1:
+        q = q[:, None]
+    targets = np.asarray(targets, dtype=np.int64)
+    tree = UniformTree(points, depth, np.asarray(lo, dtype=np.float64), float(width))
+    nt, nrhs, nn = targets.size, q.shape[1], order ** 3
+    far = np.zeros((nt, nrhs))
+    if depth >= 2:
+        mult = {depth: p2m_chunked(tree, q, order)}
+        for lev in range(depth - 1, 1, -1):
+            mult[lev] = m2m(mult[lev + 1], lev + 1, order)
+        tijk = tree.leaf_ijk[targets]
+        chain_cells, chain_loc = {}, {}
+        for lev in range(2, depth + 1):
+            ijk = tijk >> (depth - lev)
+            cells = np.unique(UniformTree.cell_index(ijk, lev))
+            wl = width / (1 << lev)
+            f = np.zeros((cells.size, nn, nrhs))
+            for t, (xi, yi) in interaction_pairs_of(lev, cells).items():
+                cols = mult[lev][yi].transpose(1, 0, 2).reshape(nn, -1)
+                if eps > 0:
+                    u, v = compressed_operator(t, wl, order, kind, c, eps, compressor)
+                    prod = u @ (v.T @ cols)
+                else:
+                    prod = m2l_operator(t, wl, order, kind, c) @ cols
+                f[np.searchsorted(cells, xi)] += prod.reshape(nn, xi.size, nrhs).transpose(1, 0, 2)
+            if lev > 2:
+                # L2L (Eq. l2l_bbfmm): F_child += S_child F_parent along the chains
+                s = 1 << lev
+                cijk = np.stack([cells % s, (cells // s) % s, cells // (s * s)], axis=1)
+                pcell = UniformTree.cell_index(cijk // 2, lev - 1)
+                ppos = np.searchsorted(chain_cells[lev - 1], pcell)
+                octs = cijk % 2
+                for o in itertools.product((0, 1), repeat=3):
+                    sel = np.all(octs == np.asarray(o)[None, :], axis=1)
+                    if np.any(sel):
+                        smat = child_to_parent_matrix(o, order)
+                        f[sel] += np.einsum("bB,nBr->nbr", smat, chain_loc[lev - 1][ppos[sel]])
+            chain_cells[lev], chain_loc[lev] = cells, f
+        leafpos = np.searchsorted(chain_cells[depth], tree.leaf[targets])
+        basis = tensor_basis(tree.local_coords()[targets], order)
+        far = np.einsum("nb,nbr->nr", basis, chain_loc[depth][leafpos])
+    # near field at the targets: the 27 neighbour leaves, own leaf included, j != i
+    s = 1 << depth
+    by_leaf = np.argsort(tree.leaf, kind="stable")
+    starts = np.concatenate([[0], np.cumsum(np.bincount(tree.leaf, minlength=s ** 3))])
+    near = np.zeros((nt, nrhs))
+    for k, i in enumerate(targets):
+        js = []
+        for off in near_offsets():
+            nb = tree.leaf_ijk[i] + np.asarray(off)
+            if np.any(nb < 0) or np.any(nb >= s):
+                continue
+            leaf = UniformTree.cell_index(nb, depth)
+            js.append(by_leaf[starts[leaf]:starts[leaf + 1]])
+        js = np.concatenate(js)
+        js = js[js != i]
+        if js.size:
+            near[k] = kernel(kind, points[i][None, :], points[js], c) @ q[js]
+    return far + near
+
+
 def fmm_adjoint(points, g, order, depth, kind="inv_r", c=0.0, eps=0.0, lo=(0.0, 0.0, 0.0),
                 width=1.0, compressor: str = "svd") -> np.ndarray:
     """A^T g through the literally transposed chain: L2P^T, L2L^T, M2L^T (K_t^T), M2M^T, P2M^T, P2P^T."""
@@ -717,33 +826,36 @@ def fmm_adjoint(points, g, order, depth, kind="inv_r", c=0.0, eps=0.0, lo=(0.0, 
 
 
 def fmm_grad_points(points, q, g, order, depth, kind="inv_r", c=0.0, eps=0.0,
-                    lo=(0.0, 0.0, 0.0), width=1.0, compressor: str = "svd") -> np.ndarray:
+                    lo=(0.0, 0.0, 0.0), width=1.0, compressor: str = "svd", targets=None) -> np.ndarray:
     """d/dx_i of L = sum_k g_k . phi_k(x) with the tree (cell membership and centres) fixed.
 
     Target role: g_i . grad L2P(F^(q))(x_i) + near-field grad; source role: q_i . grad of the
     P2M basis paired with the adjoint locals (= the transposed chain applied to g), + near field.
+    `targets` (optional): the points i whose rows are returned, (len(targets), 3); all by default.
     """
     points = np.ascontiguousarray(points, dtype=np.float64)
     q = np.atleast_2d(np.asarray(q, dtype=np.float64).T).T
     g = np.atleast_2d(np.asarray(g, dtype=np.float64).T).T
     tree = UniformTree(points, depth, np.asarray(lo, dtype=np.float64), float(width))
     n = points.shape[0]
-    out = np.zeros((n, 3))
+    rows = np.arange(n) if targets is None else np.asarray(targets, dtype=np.int64)
+    out = np.zeros((rows.size, 3))
     if depth >= 2:
         fq = fmm_apply(points, q, order, depth, kind, c, eps, lo, width,
                        compressor=compressor).locals[depth]
         fg = _adjoint_leaf_locals(points, g, order, depth, kind, c, eps, lo, width, compressor)
-        u = tree.local_coords()
+        u = tree.local_coords()[rows]
         scale = 2.0 / tree.cell_width(depth)
-        dbasis = tensor_basis_grad(u, order) * scale      # (n, l^3, 3)
-        out += np.einsum("nbk,nbr,nr->nk", dbasis, fq[tree.leaf], g)
-        out += np.einsum("nbk,nbr,nr->nk", dbasis, fg[tree.leaf], q)
+        dbasis = tensor_basis_grad(u, order) * scale      # (rows, l^3, 3)
+        leaf = tree.leaf[rows]
+        out += np.einsum("nbk,nbr,nr->nk", dbasis, fq[leaf], g[rows])
+        out += np.einsum("nbk,nbr,nr->nk", dbasis, fg[leaf], q[rows])
     # near field, both roles
     s = 1 << depth
     order_ = np.argsort(tree.leaf, kind="stable")
     counts = np.bincount(tree.leaf, minlength=s ** 3)
     starts = np.concatenate([[0], np.cumsum(counts)])
-    for i in range(n):
+    for k_out, i in enumerate(rows):
         ijk = tree.leaf_ijk[i]
         for off in near_offsets():
             nb = ijk + np.asarray(off)
@@ -755,7 +867,7 @@ def fmm_grad_points(points, q, g, order, depth, kind="inv_r", c=0.0, eps=0.0,
             if js.size:
                 gr = kernel_grad_x(kind, points[i][None, :], points[js], c)   # (m, 3)
                 w = q[js] @ g[i] + g[js] @ q[i]
-                out[i] += w @ gr
+                out[k_out] += w @ gr
     return out
 
 

@@ -343,3 +343,88 @@ def test_gradient_of_pure_near_field_is_brute_force_gradient():
         lp = np.sum(g * O.brute_force(pp, q, "inv_r"))
         lm = np.sum(g * O.brute_force(pm, q, "inv_r"))
         assert abs((lp - lm) / (2 * h) - b[i, k]) < 1e-6 * max(1, abs(b[i, k]))
+
+
+# ---------------------------------------------------------------- kernels (closed forms, gradients)
+
+
+def test_regularised_kernel_closed_form():
+    """1/sqrt(r^2 + c^2) at Pythagorean triples (exact in FP64), its value c^-1 at r = 0, and its
+    limit 1/r as c -> 0; a c-for-c^2 slip fails the triples."""
+    r = np.array([3.0, 5.0, 8.0, 0.0, 0.6])
+    c = np.array([4.0, 12.0, 15.0, 0.25, 0.8])
+    want = np.array([1 / 5, 1 / 13, 1 / 17, 4.0, 1.0])
+    for ri, ci, wi in zip(r, c, want):
+        assert abs(O.kernel_of_r("inv_sqrt_r2c2", np.array([ri]), ci)[0] - wi) <= 2e-16 * wi
+    rr = np.linspace(0.1, 2.0, 20)
+    assert np.max(np.abs(O.kernel_of_r("inv_sqrt_r2c2", rr, 1e-9) * rr - 1.0)) < 1e-15
+    # through kernel(): distance from two points (3-4-0 triangle, c = 12 -> 1/13)
+    x, y = np.array([1.0, 2.0, 3.0]), np.array([4.0, 6.0, 3.0])
+    assert abs(O.kernel("inv_sqrt_r2c2", x, y, 12.0) - 1 / 13) < 1e-17
+
+
+@pytest.mark.parametrize("kind,c", [("inv_sqrt_r2c2", 1e-3), ("inv_sqrt_r2c2", 0.7), ("r2", 0.0),
+                                    ("r4", 0.0), ("inv_r", 0.0)])
+def test_kernel_gradient_matches_finite_differences(kind, c):
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-1, 1, (40, 3))
+    y = rng.uniform(-1, 1, (40, 3))
+    g = O.kernel_grad_x(kind, x, y, c)
+    h = 1e-6
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        fd = (O.kernel(kind, x + e, y, c) - O.kernel(kind, x - e, y, c)) / (2 * h)
+        assert np.max(np.abs(fd - g[:, k]) / np.maximum(1.0, np.abs(g[:, k]))) < 1e-7, (kind, k)
+
+
+def test_polynomial_kernel_gradients_closed_form():
+    """grad_x |x-y|^2 = 2 (x-y); grad_x |x-y|^4 = 4 |x-y|^2 (x-y)."""
+    x, y = np.array([0.5, -1.0, 2.0]), np.array([1.5, 1.0, -1.0])
+    d = x - y
+    assert np.allclose(O.kernel_grad_x("r2", x, y), 2 * d, rtol=0, atol=1e-15)
+    assert np.allclose(O.kernel_grad_x("r4", x, y), 4 * (d @ d) * d, rtol=1e-15, atol=0)
+
+
+# ---------------------------------------------------------------- sampled-target evaluation
+
+
+@pytest.mark.parametrize("kind,c,eps,nrhs", [("inv_r", 0.0, 0.0, 2), ("inv_sqrt_r2c2", 0.05, 0.0, 1),
+                                             ("inv_r", 0.0, 1e-5, 1)])
+def test_sampled_apply_equals_full_apply(kind, c, eps, nrhs):
+    rng = np.random.default_rng(12)
+    pts, q = rng.random((2500, 3)), rng.uniform(-1, 1, (2500, nrhs))
+    tg = rng.choice(2500, 60, replace=False)
+    full = O.fmm_apply(pts, q, 4, 3, kind, c, eps).phi
+    samp = O.fmm_apply_sampled(pts, q, 4, 3, tg, kind, c, eps)
+    assert np.max(np.abs(samp - full[tg])) < 1e-13 * np.max(np.abs(full))
+
+
+def test_sampled_apply_is_exact_for_polynomial_kernel():
+    """An independent pin of the sampled path: with |x-y|^2 at order 3 the multilevel scheme
+    reproduces the direct sum at the targets (depth 4: four M2L levels and three L2L steps)."""
+    rng = np.random.default_rng(13)
+    pts, q = rng.random((3000, 3)), rng.uniform(-1, 1, (3000, 1))
+    tg = rng.choice(3000, 40, replace=False)
+    samp = O.fmm_apply_sampled(pts, q, 3, 4, tg, "r2")
+    ref = O.brute_force(pts, q, "r2", targets=tg)
+    assert O.rel_l2(samp, ref) < 1e-12
+
+
+def test_chunked_p2m_equals_p2m():
+    rng = np.random.default_rng(14)
+    pts, q = rng.random((900, 3)), rng.uniform(-1, 1, (900, 2))
+    tree = O.UniformTree(pts, 2, np.zeros(3), 1.0)
+    a = O.p2m(tree, q, 4)
+    b = O.p2m_chunked(tree, q, 4, chunk=37)
+    assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a))
+
+
+def test_gradient_rows_equal_full_gradient():
+    rng = np.random.default_rng(15)
+    pts = rng.random((400, 3))
+    q, g = rng.uniform(-1, 1, (400, 1)), rng.uniform(-1, 1, (400, 1))
+    rows = np.array([3, 77, 150, 399])
+    full = O.fmm_grad_points(pts, q, g, 4, 2, "inv_r", eps=1e-5)
+    part = O.fmm_grad_points(pts, q, g, 4, 2, "inv_r", eps=1e-5, targets=rows)
+    assert np.max(np.abs(part - full[rows])) < 1e-14 * np.max(np.abs(full))
