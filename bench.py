@@ -1,11 +1,15 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X bbFMM: one FMM matvec phi = A q per step.
 
-Default workload (the configuration the headline metric is quoted on): N = 1,000,000 points
-uniform in the unit cube, kernel 1/r, Chebyshev order 5, uniform octree of depth 6, the 16
-unique M2L operators each SVD-compressed at eps = 1e-5 (IAblk), FP64, one density vector.
+Default workload: the largest single-GPU FP64 configuration, N = 4,000,000 points uniform in the
+unit cube, kernel 1/sqrt(r^2 + c^2) with c = 1e-3, Chebyshev order 7, uniform octree of depth 7,
+four density vectors, full-rank symmetry-blocked M2L (NAblk) in FP64; the FP32 and split-FP32 M2L
+variants are timed on the same tree and reported in the same line with their errors against
+the FP64 result, the direct sum and the stored oracle samples. `--config N` selects another
+workload (1: 10^4 points order 4; 2: 10^6 points order 5 compressed; 4: 10^6 points forward +
+adjoint + gradient; 5: 8x10^6 points adaptive order 8, FP32 M2L).
 
-A step is one apply: gather -> P2M -> M2M -> M2L (levels 2..6) -> L2L -> L2P -> near field ->
+A step is one apply: gather -> P2M -> M2M -> M2L (levels 2..7) -> L2L -> L2P -> near field ->
 scatter, with points, densities, tree and operators resident in HBM. Tree build and operator
 precompute are timed once and reported beside it. Prints one JSON line.
 """
@@ -131,6 +135,41 @@ def run_ablation(torch, np, pk, tree, plan, w, level, stream, reps=3):
     return res
 
 
+def oracle_samples(config, w):
+    """The oracle's stored potentials at the seeded targets of this workload, when they exist
+    (tests/golden/cfg<N>_samples.json, written by the scripts beside them)."""
+    path = os.path.join(ROOT, "tests", "golden", f"cfg{config}_samples.json")
+    if not os.path.exists(path):
+        return None
+    s = json.load(open(path))
+    return s if s.get("workload") == w.name else None
+
+
+def sample_error(np, out, samples):
+    """rel. L2 error of the device result at the stored targets against the oracle there."""
+    got = out.detach().cpu().numpy()[np.asarray(samples["targets"])]
+    ref = np.asarray(samples["phi_oracle"], dtype=np.float64).reshape(got.shape[0], -1)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def m2l_traffic(workload, prec, variant, compressor):
+    """HBM bytes of one M2L launch from the committed rocprofv3 counters (FETCH_SIZE + WRITE_SIZE,
+    scaled by the copy-kernel calibration), only while the M2L source is the one they were taken
+    on; None otherwise."""
+    import hashlib
+    try:
+        t = json.load(open(os.path.join(ROOT, "profiles", "m2l_traffic.json")))
+        src = open(os.path.join(ROOT, t["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != t["sha256"] or variant != "blocked" or compressor != "svd":
+            return None
+        for e in t["entries"]:
+            if e["workload"] == workload and e["m2l_prec"] == prec:
+                return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+    return None
+
+
 def cpu_baseline(w, inp, sample_n, grad_mode=False, compressor="svd"):
     """The oracle (as it stands) on a bounded sample of the same workload, on the host cores."""
     import numpy as np
@@ -241,14 +280,17 @@ def run_helmholtz(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, help="workload number (1-5)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 5 for the workloads of 4M points and more, else 20)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 1, or 3 below 4M points)")
+    ap.add_argument("--config", type=int, default=3, help="workload number (1-5)")
     ap.add_argument("--prec", default=None, help="override M2L precision: fp64 | fp32 | split32")
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="points in the oracle sample (default: 100000; 20000 for order 7)")
     ap.add_argument("--variants", action="store_true",
-                    help="also time the other M2L precisions and report their errors vs this one")
+                    help="also time the other M2L precisions and report their errors vs this one "
+                         "(always on for workload 3)")
+    ap.add_argument("--no-variants", action="store_true", help="workload 3 without the precision variants")
     ap.add_argument("--ablation", type=int, default=0, metavar="LEVEL",
                     help="also time the M2L of LEVEL with the unblocked variants (NA, NAsym, IA, IAsym)")
     ap.add_argument("--compressor", default="svd", choices=("svd", "aca"),
@@ -274,6 +316,13 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 3}))
         return
+    if args.gpus == 1:
+        from workloads import WORKLOADS as _W
+        big = _W[args.config].n >= 4_000_000
+        if args.steps is None:
+            args.steps = 5 if big else 20
+        if args.warmup is None:
+            args.warmup = 1 if big else 3
     if args.helmholtz is not None and args.gpus == 1:
         run_helmholtz(args)
         return
@@ -343,7 +392,7 @@ def main():
     # per-pass breakdown from separate steps: HIP events recorded by the library between its
     # passes, on the stream the kernels run on
     plan.set_timing(True)
-    for _ in range(max(1, min(args.steps, 5))):
+    for _ in range(max(1, min(args.steps, 5 if ms_per_step < 1000 else 1))):
         step()
     torch.cuda.synchronize()
     passes, calls = plan.pass_times()
@@ -380,8 +429,14 @@ def main():
         err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
         log(f"[bench] rel L2 error vs direct sum at {targets.numel()} targets: {err:.3e}")
 
+    samples = oracle_samples(args.config, w)
+    err_oracle = None
+    if samples is not None:
+        err_oracle = sample_error(np, out, samples)
+        log(f"[bench] rel L2 error vs the oracle at {len(samples['targets'])} stored targets: {err_oracle:.3e}")
+
     variants = None
-    if args.variants:
+    if (args.variants or args.config == 3) and not args.no_variants and not grad_mode:
         variants = []
         for other in ("fp64", "fp32", "split32"):
             if other == prec:
@@ -390,9 +445,10 @@ def main():
             o2 = torch.empty_like(q)
             p2.apply(q, o2)
             torch.cuda.synchronize()
+            vsteps = max(1, args.steps // 2) if ms_per_step > 1000 else args.steps
             a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a0.record(stream)
-            for _ in range(args.steps):
+            for _ in range(vsteps):
                 p2.apply(q, o2)
             a1.record(stream)
             torch.cuda.synchronize()
@@ -401,13 +457,18 @@ def main():
             torch.cuda.synchronize()
             pt, pc = p2.pass_times()
             p2.set_timing(False)
-            v = {"m2l_prec": other, "ms_per_step": a0.elapsed_time(a1) / args.steps,
+            v = {"m2l_prec": other, "steps": vsteps, "ms_per_step": a0.elapsed_time(a1) / vsteps,
                  "m2l_ms": pt["m2l"] / max(pc, 1),
                  "rel_l2_vs_" + prec: float(torch.linalg.norm(o2 - out) / torch.linalg.norm(out))}
             v["m2l_tflops"] = flops / (v["m2l_ms"] * 1e-3) / 1e12
+            v["m2l_frac_of_peak"] = v["m2l_tflops"] / PEAK_TFLOPS[other]
+            v["m2l_speedup_vs_" + prec] = m2l_ms / v["m2l_ms"]
+            v["apply_speedup_vs_" + prec] = ms_per_step / v["ms_per_step"]
             if err is not None:
                 got2 = o2[targets]
                 v["rel_l2_err_vs_direct"] = float(torch.linalg.norm(got2 - ref) / torch.linalg.norm(ref))
+            if samples is not None:
+                v["rel_l2_err_vs_oracle"] = sample_error(np, o2, samples)
             log(f"[bench] variant {v}")
             variants.append(v)
             del p2, o2
@@ -429,18 +490,7 @@ def main():
                                args.variant if args.variant != "blocked" else args.compressor)
         log(f"[bench] oracle: {cpu['value']:.3e} points/s")
 
-    # HBM traffic of the M2L launch from the committed rocprofv3 counters, only while the kernel
-    # source is the one they were taken on (null otherwise)
-    traffic = None
-    try:
-        import hashlib
-        t = json.load(open(os.path.join(ROOT, "profiles", "m2l_traffic.json")))
-        src = open(os.path.join(ROOT, t["source"]), "rb").read()
-        if (hashlib.sha256(src).hexdigest() == t["sha256"] and t["workload"] == w.name
-                and prec == "fp64" and args.variant == "blocked"):
-            traffic = t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
-    except (OSError, KeyError, ValueError):
-        traffic = None
+    traffic = m2l_traffic(w.name, prec, args.variant, args.compressor)
 
     variant = {"sa": "SA", "sarcmp": "SArcmp"}.get(args.variant, "IAblk" if w.svd_eps > 0 else "NAblk")
     line = {
@@ -463,6 +513,10 @@ def main():
                    "compressor": args.compressor if w.svd_eps > 0 else None},
         "m2l_gflops": achieved * 1e3,
         "rel_l2_err_vs_direct": err,
+        "rel_l2_err_vs_oracle": err_oracle,
+        "error_samples": (f"{len(samples['targets'])} seeded targets, oracle values stored by "
+                          f"tests/golden/make_cfg{args.config}_samples.py" if samples is not None else
+                          f"{len(inp.sample_targets)} seeded targets (direct sum only)"),
         "passes_ms_per_call": per,
         "passes_achieved": achieved_bw,
         "passes_work": work,

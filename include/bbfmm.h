@@ -27,8 +27,12 @@
  *    into leaf (Morton) order internally and returns results in the caller's order.
  *  - Trees and plans own their device buffers (allocated by build/precompute, and by apply when
  *    a larger nrhs than before is requested), released by the matching *_destroy.
- *  - One plan runs one apply-type call at a time (its work buffers are shared); overlapping
- *    calls on the same plan from different streams race. A plan must not outlive its tree.
+ *  - One plan runs one apply-type call at a time (its work buffers are shared). Calls on one
+ *    stream are ordered by it; a call on another stream than the plan's previous call returns
+ *    BBFMM_ESTATE while that call has not completed (checked with an event the plan records
+ *    after each call; synchronise the first stream, or use one stream per plan). Two threads
+ *    calling into one plan at the same time are not supported. A plan must not outlive its
+ *    tree.
  */
 #ifndef BBFMM_H
 #define BBFMM_H
@@ -182,6 +186,16 @@ typedef struct bbfmm_plan bbfmm_plan;
 bbfmm_status bbfmm_build_octree(const double* d_points, int64_t n, const bbfmm_tree_opts* opts,
                                 void* stream, bbfmm_tree** out);
 
+/* Moves the points of a uniform tree without rebuilding it: d_points (n x 3 row-major FP64,
+ * the tree's n, caller order) replaces the coordinates when every point stays in the leaf it was
+ * sorted into (the leaf rule of bbfmm_build_octree without its clamp, so also inside the root
+ * cube). Cell membership, centres and plans built on the tree stay valid, so an apply after the
+ * move evaluates the FMM approximation of Sec. 2.1.1 at the new positions; this is the fixed
+ * tree under which bbfmm_eval_grad differentiates. Synchronises `stream` (one check on the
+ * device). Errors: EINVAL (null, a point that left its leaf or is not finite: the tree is then
+ * unchanged), EUNSUPPORTED (adaptive tree). */
+bbfmm_status bbfmm_tree_update_points(bbfmm_tree* tree, const double* d_points, void* stream);
+
 /* Precomputes the M2L operators of Sec. 3.1, Eq. (m2lmatrix) for the 16 transfer vectors of
  * T_sym (Eq. reduced_interaction_list) in FP64 on the host, at unit cell width for homogeneous
  * kernels (scaled per level, Sec. 3.2) or at every level's width otherwise; compresses each by
@@ -203,9 +217,14 @@ bbfmm_status bbfmm_apply(bbfmm_plan* plan, const double* d_q, int32_t nrhs, doub
                          void* stream);
 
 /* grad_q = A^T g through the transposed chain L2P^T, L2L^T, M2L^T (K_t^T = K_{-t}), M2M^T,
- * P2M^T and the transposed near field. For the symmetric kernels supported here, with one point
- * set as sources and targets, A^T = A, so this runs the forward passes on g; the leaf adjoint
- * locals are kept for bbfmm_eval_grad. Same argument rules as bbfmm_apply. */
+ * P2M^T and the transposed near field. Precondition, which every plan of this library meets by
+ * construction: the kernel is symmetric, K(x, y) = K(y, x) (all bbfmm_kernel values are functions
+ * of |x - y| alone), and the sources are the targets (one point set per tree). Then L2P^T = P2M
+ * (the same interpolation polynomials), L2L^T = M2M, K_t^T = K_{-t} for every transfer vector
+ * (kept by both compressors) and the near field is symmetric, so A^T = A and this call runs the
+ * forward passes on g; the leaf adjoint locals are kept for bbfmm_eval_grad. A kernel without
+ * that symmetry, or distinct source and target sets, would need the literally transposed chain
+ * and is not accepted by bbfmm_precompute_m2l. Same argument rules as bbfmm_apply. */
 bbfmm_status bbfmm_apply_adjoint(bbfmm_plan* plan, const double* d_g, int32_t nrhs,
                                  double* d_grad_q, void* stream);
 
@@ -219,6 +238,21 @@ bbfmm_status bbfmm_apply_adjoint(bbfmm_plan* plan, const double* d_g, int32_t nr
  * Errors: EINVAL, ESTATE (apply or apply_adjoint missing, or nrhs mismatch). */
 bbfmm_status bbfmm_eval_grad(bbfmm_plan* plan, const double* d_q, const double* d_g, int32_t nrhs,
                              int32_t roles, double* d_grad_x, void* stream);
+
+/* Complex Helmholtz potential phi_i = sum_{j != i} e^{ik|x_i - x_j|} / |x_i - x_j| q_j (Sec. 5,
+ * Eq. kernel_functions, 4 pi dropped) in the bbFMM's low-frequency regime, from the plans of its
+ * two real parts on one tree: re (BBFMM_K_HELM_COS) and im (BBFMM_K_HELM_SIN), with the same
+ * order and wavenumber c. complex_q = 0: d_q is n x nrhs real FP64 and phi = A_cos q + i A_sin q;
+ * complex_q = 1: d_q is n x nrhs complex FP64 (interleaved re, im pairs: the layout of C99
+ * double _Complex), both plans run on [Re q | Im q] (2 nrhs columns) and
+ * phi = (A_cos Re q - A_sin Im q) + i (A_cos Im q + A_sin Re q), combined on the device. d_phi:
+ * n x nrhs complex FP64, overwritten. Staging buffers (3 x n x 2 nrhs doubles at most) are owned
+ * by `re` and allocated on the first call that needs them; both plans' forward locals are
+ * overwritten. Errors: EINVAL (null, plans of other kernels or with different tree, order or
+ * wavenumber, nrhs < 1 or above 64 for real q and 32 for complex q, d_q == d_phi), ENOMEM,
+ * ESTATE (as bbfmm_apply, for either plan). */
+bbfmm_status bbfmm_helmholtz_apply(bbfmm_plan* re, bbfmm_plan* im, const double* d_q, int32_t nrhs,
+                                   int32_t complex_q, double* d_phi, void* stream);
 
 /* Per-pass tracing. While enabled, every apply-type call records HIP events on its stream between
  * its passes (no synchronisation). bbfmm_plan_pass_times waits for the recorded events and returns
@@ -242,11 +276,13 @@ const char* bbfmm_version(void);
  * the order m(a) = a1 + l a2 + l^2 a3 of Sec. 3.1, each point nrhs values.
  * --------------------------------------------------------------------------------------- */
 
-/* Copies expansions of `level` from the last apply-type call: which = 0 multipoles W,
- * 1 M2L output (before L2L), 2 locals after L2L. d_out: 8^level * l^3 * nrhs FP64.
- * Errors: EINVAL (level outside [2, depth], which outside [0, 2]), ESTATE (no apply yet). */
+/* Copies expansions of `level` from the last bbfmm_apply: which = 0 multipoles W,
+ * 1 M2L output (before L2L), 2 locals after L2L. d_out: 8^level * l^3 * nrhs FP64, where nrhs
+ * must be that apply's number of right-hand sides.
+ * Errors: EINVAL (level outside [2, depth], which outside [0, 2], another nrhs), ESTATE (no apply
+ * yet), EUNSUPPORTED (adaptive tree). */
 bbfmm_status bbfmm_debug_get_expansions(const bbfmm_plan* plan, int32_t level, int32_t which,
-                                        double* d_out, void* stream);
+                                        int32_t nrhs, double* d_out, void* stream);
 
 /* Runs only the M2L of `level` on caller multipoles d_w (layout above) and writes the M2L
  * output to d_f (overwritten), with the plan's operators and precision. */

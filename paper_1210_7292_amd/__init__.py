@@ -28,5 +28,6 @@ from .binding import (  # noqa: F401
     lib,
     plan_stats,
     precompute_m2l,
+    update_points,
 )
-from .autograd import FMMFunction  # noqa: F401
+from .autograd import FMMFunction, fmm, make_plan  # noqa: F401

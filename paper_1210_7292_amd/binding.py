@@ -63,10 +63,12 @@ _lib = None
 _P = C.c_void_p
 SIGNATURES = [
     ("bbfmm_build_octree", C.c_int, [_P, C.c_int64, C.POINTER(TreeOpts), _P, C.POINTER(_P)]),
+    ("bbfmm_tree_update_points", C.c_int, [_P, _P, _P]),
     ("bbfmm_precompute_m2l", C.c_int, [_P, C.POINTER(PlanOpts), _P, C.POINTER(_P)]),
     ("bbfmm_apply", C.c_int, [_P, _P, C.c_int32, _P, _P]),
     ("bbfmm_apply_adjoint", C.c_int, [_P, _P, C.c_int32, _P, _P]),
     ("bbfmm_eval_grad", C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
+    ("bbfmm_helmholtz_apply", C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
     ("bbfmm_plan_stats", C.c_int, [_P, C.POINTER(Stats)]),
     ("bbfmm_plan_set_timing", C.c_int, [_P, C.c_int32]),
     ("bbfmm_plan_pass_times", C.c_int, [_P, _P, _P]),
@@ -74,7 +76,7 @@ SIGNATURES = [
     ("bbfmm_tree_destroy", None, [_P]),
     ("bbfmm_last_error", C.c_char_p, []),
     ("bbfmm_version", C.c_char_p, []),
-    ("bbfmm_debug_get_expansions", C.c_int, [_P, C.c_int32, C.c_int32, _P, _P]),
+    ("bbfmm_debug_get_expansions", C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
     ("bbfmm_debug_m2l_level", C.c_int, [_P, C.c_int32, _P, C.c_int32, _P, _P]),
     ("bbfmm_debug_tree_order", C.c_int, [_P, _P, _P, _P]),
     ("bbfmm_host_symmetry", C.c_int, [C.c_int32, _P, _P, _P, _P]),
@@ -114,16 +116,25 @@ def _stream(torch_mod, device) -> Optional[int]:
     return torch_mod.cuda.current_stream(device).cuda_stream
 
 
-def _dev_ptr(t, dtype, shape_last=None, name="tensor"):
-    import torch
+def _check_shape(t, rows=None, cols=None, name="tensor", dims=2):
+    """Raises EINVAL unless t has `dims` dimensions, `rows` rows and `cols` columns (None: any).
+    Runs before any device pointer is handed to the library, which trusts the sizes it is given."""
+    shape = tuple(t.shape)
+    if len(shape) != dims or (rows is not None and shape[0] != rows) or (cols is not None and shape[-1] != cols):
+        want = ", ".join("n" if v is None else str(v) for v in
+                         ([rows] + [None] * (dims - 2) + [cols] if dims >= 2 else [rows]))
+        raise BBFMMError(-1, f"{name} has shape {shape}, expected ({want})")
+
+
+def _dev_ptr(t, dtype, shape_last=None, name="tensor", rows=None):
+    if rows is not None or shape_last is not None:
+        _check_shape(t, rows, shape_last, name)
     if not t.is_cuda:
         raise BBFMMError(-1, f"{name} must be a device tensor")
     if t.dtype != dtype:
         raise BBFMMError(-1, f"{name} must be {dtype}")
     if not t.is_contiguous():
         raise BBFMMError(-1, f"{name} must be contiguous")
-    if shape_last is not None and (t.dim() != 2 or t.shape[1] != shape_last):
-        raise BBFMMError(-1, f"{name} must have shape (n, {shape_last})")
     return C.c_void_p(t.data_ptr())
 
 
@@ -155,32 +166,63 @@ def precompute_m2l(tree, kernel: str = "inv_r", order: int = 5, svd_eps: float =
     return out
 
 
-def apply(plan, q, out=None):
-    """bbfmm_apply: phi = A q for q of shape (n, nrhs) float64 on the device."""
+def update_points(tree, points, n: int):
+    """bbfmm_tree_update_points: moves the n points of a uniform tree, each within its leaf."""
     import torch
-    qp = _dev_ptr(q, torch.float64, None, "q")
+    p = _dev_ptr(points, torch.float64, 3, "points", rows=n)
+    _check(lib().bbfmm_tree_update_points(tree, p, _P(_stream(torch, points.device))))
+
+
+def apply(plan, q, out=None, n: Optional[int] = None):
+    """bbfmm_apply: phi = A q for q of shape (n, nrhs) float64 on the device (n = the tree's
+    point count when given; the library trusts it)."""
+    import torch
+    _check_shape(q, n, None, "q")
+    if out is not None:
+        _check_shape(out, q.shape[0], q.shape[1], "out")
+    qp = _dev_ptr(q, torch.float64, None, "q", rows=n)
     out = torch.empty_like(q) if out is None else out
-    _check(lib().bbfmm_apply(plan, qp, q.shape[1], _dev_ptr(out, torch.float64, q.shape[1], "out"),
+    _check(lib().bbfmm_apply(plan, qp, q.shape[1], _dev_ptr(out, torch.float64, q.shape[1], "out", rows=q.shape[0]),
                              _P(_stream(torch, q.device))))
     return out
 
 
-def apply_adjoint(plan, g, out=None):
+def apply_adjoint(plan, g, out=None, n: Optional[int] = None):
     import torch
-    gp = _dev_ptr(g, torch.float64, None, "g")
+    _check_shape(g, n, None, "g")
+    if out is not None:
+        _check_shape(out, g.shape[0], g.shape[1], "out")
+    gp = _dev_ptr(g, torch.float64, None, "g", rows=n)
     out = torch.empty_like(g) if out is None else out
-    _check(lib().bbfmm_apply_adjoint(plan, gp, g.shape[1], _dev_ptr(out, torch.float64, g.shape[1], "out"),
+    _check(lib().bbfmm_apply_adjoint(plan, gp, g.shape[1],
+                                     _dev_ptr(out, torch.float64, g.shape[1], "out", rows=g.shape[0]),
                                      _P(_stream(torch, g.device))))
     return out
 
 
-def eval_grad(plan, q, g, roles: int = 3, out=None):
+def eval_grad(plan, q, g, roles: int = 3, out=None, n: Optional[int] = None):
     import torch
+    _check_shape(q, n, None, "q")
     n = q.shape[0]
+    _check_shape(g, n, q.shape[1], "g")
+    if out is not None:
+        _check_shape(out, n, 3, "out")
     out = torch.empty((n, 3), dtype=torch.float64, device=q.device) if out is None else out
-    _check(lib().bbfmm_eval_grad(plan, _dev_ptr(q, torch.float64, None, "q"),
-                                 _dev_ptr(g, torch.float64, q.shape[1], "g"), q.shape[1], int(roles),
-                                 _dev_ptr(out, torch.float64, 3, "out"), _P(_stream(torch, q.device))))
+    _check(lib().bbfmm_eval_grad(plan, _dev_ptr(q, torch.float64, None, "q", rows=n),
+                                 _dev_ptr(g, torch.float64, q.shape[1], "g", rows=n), q.shape[1], int(roles),
+                                 _dev_ptr(out, torch.float64, 3, "out", rows=n), _P(_stream(torch, q.device))))
+    return out
+
+
+def helmholtz_apply(re_plan, im_plan, q, n: Optional[int] = None):
+    """bbfmm_helmholtz_apply: complex phi (n, nrhs) complex128 from real float64 or complex128 q."""
+    import torch
+    _check_shape(q, n, None, "q")
+    cplx = torch.is_complex(q)
+    qp = _dev_ptr(q, torch.complex128 if cplx else torch.float64, None, "q")
+    out = torch.empty(tuple(q.shape), dtype=torch.complex128, device=q.device)
+    _check(lib().bbfmm_helmholtz_apply(re_plan, im_plan, qp, q.shape[1], 1 if cplx else 0,
+                                       C.c_void_p(out.data_ptr()), _P(_stream(torch, q.device))))
     return out
 
 
@@ -306,6 +348,10 @@ class Octree:
         """Adaptive trees: the node arrays and interaction lists (see adaptive_arrays)."""
         return adaptive_arrays(self.handle, self.n)
 
+    def update_points(self, points):
+        """Moves the points (n, 3) float64, each within its leaf (uniform trees)."""
+        update_points(self.handle, points, self.n)
+
     def order(self):
         """(perm, leaf_start): caller index of each sorted point and the leaf offsets."""
         import torch
@@ -335,13 +381,13 @@ class Plan:
                                      variant)
 
     def apply(self, q, out=None):
-        return apply(self.handle, q, out)
+        return apply(self.handle, q, out, self.tree.n)
 
     def apply_adjoint(self, g, out=None):
-        return apply_adjoint(self.handle, g, out)
+        return apply_adjoint(self.handle, g, out, self.tree.n)
 
     def eval_grad(self, q, g, roles: int = 3, out=None):
-        return eval_grad(self.handle, q, g, roles, out)
+        return eval_grad(self.handle, q, g, roles, out, self.tree.n)
 
     def stats(self) -> dict:
         return plan_stats(self.handle)
@@ -360,13 +406,16 @@ class Plan:
         """Copies W (0), the M2L output (1) or the locals (2) of `level` (Morton cell order)."""
         import torch
         out = torch.empty((8 ** level, self.order ** 3, nrhs), dtype=torch.float64, device=self.tree.device)
-        _check(lib().bbfmm_debug_get_expansions(self.handle, level, which, _P(out.data_ptr()),
+        _check(lib().bbfmm_debug_get_expansions(self.handle, level, which, int(nrhs), _P(out.data_ptr()),
                                                 _P(_stream(torch, self.tree.device))))
         return out
 
     def m2l_level(self, level: int, w):
         """Runs only the M2L of `level` on multipoles w (8^level, l^3, nrhs) in Morton order."""
         import torch
+        _check_shape(w, 8 ** level, None, "w", dims=3)
+        if w.shape[1] != self.order ** 3:
+            raise BBFMMError(-1, f"w has shape {tuple(w.shape)}, expected ({8 ** level}, {self.order ** 3}, nrhs)")
         f = torch.empty_like(w)
         _check(lib().bbfmm_debug_m2l_level(self.handle, level, _dev_ptr(w, torch.float64, None, "w"),
                                            w.shape[2], _P(f.data_ptr()), _P(_stream(torch, w.device))))
@@ -375,6 +424,9 @@ class Plan:
     def m2l_unblocked(self, level: int, w, variant: str):
         """Runs the M2L of `level` with an unblocked variant: "NA", "NAsym", "IA" or "IAsym"."""
         import torch
+        _check_shape(w, 8 ** level, None, "w", dims=3)
+        if w.shape[1] != self.order ** 3:
+            raise BBFMMError(-1, f"w has shape {tuple(w.shape)}, expected ({8 ** level}, {self.order ** 3}, nrhs)")
         f = torch.empty_like(w)
         v = {"NA": 0, "NAsym": 1, "IA": 2, "IAsym": 3}[variant]
         _check(lib().bbfmm_m2l_unblocked(self.handle, level, v, _dev_ptr(w, torch.float64, None, "w"), w.shape[2],
@@ -390,9 +442,9 @@ class Plan:
 
 class HelmholtzPlan:
     """The Helmholtz potential phi_i = sum_j e^{ik|x_i - x_j|} / |x_i - x_j| q_j (4 pi dropped) as
-    two plans on one tree, for the real part cos(kr)/r and the imaginary part sin(kr)/r. Real q:
-    phi = A_cos q + i A_sin q. Complex q: both parts applied to [Re q, Im q] as 2 nrhs columns.
-    Low-frequency regime only (cells a fraction of a wavelength wide)."""
+    two plans on one tree, for the real part cos(kr)/r and the imaginary part sin(kr)/r, combined
+    by the library (bbfmm_helmholtz_apply). Low-frequency regime only (cells a fraction of a
+    wavelength wide)."""
 
     def __init__(self, tree: Octree, k: float, order: int = 5, svd_eps: float = 0.0, m2l_prec: str = "fp64",
                  compressor: str = "svd"):
@@ -402,13 +454,8 @@ class HelmholtzPlan:
         self.im = Plan(tree, "helm_sin", order, svd_eps, m2l_prec, self.k, compressor)
 
     def apply(self, q):
-        import torch
-        if torch.is_complex(q):
-            nr = q.shape[1]
-            both = torch.cat([q.real, q.imag], dim=1).contiguous()
-            a, b = self.re.apply(both), self.im.apply(both)
-            return torch.complex(a[:, :nr] - b[:, nr:], a[:, nr:] + b[:, :nr])
-        return torch.complex(self.re.apply(q), self.im.apply(q))
+        """phi (n, nrhs) complex128 for q (n, nrhs) float64 or complex128 (bbfmm_helmholtz_apply)."""
+        return helmholtz_apply(self.re.handle, self.im.handle, q, self.tree.n)
 
 
 def fmm_apply(points, q, depth: int, order: int, kernel: str = "inv_r", svd_eps: float = 0.0,

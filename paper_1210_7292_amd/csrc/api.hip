@@ -21,12 +21,12 @@ void set_error(bbfmm_status code, const std::string& msg) {
   g_last_error = msg;
 }
 
-namespace {
-
 bbfmm_status fail(bbfmm_status code, const std::string& msg) {
   set_error(code, msg);
   return code;
 }
+
+namespace {
 
 template <typename T>
 hipError_t dmalloc(T** p, size_t count, long long* bytes) {
@@ -206,7 +206,8 @@ void free_tree_arrays(bbfmm_tree* t) {
   dfree(t->d_start); dfree(t->d_end); dfree(t->d_cen); dfree(t->d_child_begin); dfree(t->d_child_end);
   dfree(t->d_oct); dfree(t->d_leaves); dfree(t->d_leaf_pos); dfree(t->d_u_off); dfree(t->d_u_idx);
   dfree(t->d_w_off); dfree(t->d_w_idx); dfree(t->d_x_node); dfree(t->d_x_off); dfree(t->d_x_idx);
-  dfree(t->d_m2l_tgt); dfree(t->d_vsrc);
+  dfree(t->d_m2l_tgt); dfree(t->d_vsrc); dfree(t->d_move_flag);
+  t->d_move_flag = nullptr;
   t->xs = t->ys = t->zs = nullptr;
   t->perm = t->leaf_of = t->leaf_start = nullptr;
 }
@@ -257,8 +258,8 @@ M2LArgs adaptive_m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double
 enum Pass { kPassStart = -1, kGather = 0, kP2M, kM2M, kM2L, kL2L, kL2P, kP2P, kNumPasses };
 
 // Records an event tagged with the pass that just ended (tracing only).
-hipError_t mark(bbfmm_plan* p, int tag, hipStream_t s) {
-  if (!p->timing) return hipSuccess;
+hipError_t mark(bbfmm_plan* p, const Work& wk, int tag, hipStream_t s) {
+  if (!p->timing || !wk.trace) return hipSuccess;
   if (p->ev_used == p->ev_pool.size()) {
     hipEvent_t e;
     hipError_t er = hipEventCreate(&e);
@@ -273,70 +274,66 @@ hipError_t mark(bbfmm_plan* p, int tag, hipStream_t s) {
 // The chain on an adaptive tree: P2M at the leaves, M2M up to level 2, M2L over the V lists,
 // P2L over the X lists, L2L down, L2P and M2P over the W lists at the leaves, and the near field
 // over the U lists. P2L is timed with L2L and M2P with L2P.
-bbfmm_status run_chain_adaptive(bbfmm_plan* p, const double* in, int nrhs, double* out, int slot,
+bbfmm_status run_chain_adaptive(bbfmm_plan* p, const double* in, int nrhs, double* out, const Work& wk,
                                 hipStream_t s) {
   const bbfmm_tree* t = p->tree;
   const AdaptiveTopology& T = t->topo;
   const AdaptiveGeom g = ageom_of(p);
-  double* qs = p->qs[slot];
-  BBFMM_HIP_TRY(mark(p, kPassStart, s));
+  double* qs = wk.qs;
+  BBFMM_HIP_TRY(mark(p, wk, kPassStart, s));
   BBFMM_HIP_TRY(launch_gather_rows(in, t->perm, t->n, nrhs, qs, s));
-  BBFMM_HIP_TRY(mark(p, kGather, s));
+  BBFMM_HIP_TRY(mark(p, wk, kGather, s));
   const double* far = nullptr;
   const int nleaves = (int)T.leaves.size();
   if (t->depth >= 2) {
     bbfmm_status st = adaptive_segments(p, nrhs, s);
     if (st != BBFMM_OK) return st;
-    double* W = p->W;
-    double* F = p->F[slot];
+    double* W = wk.W;
+    double* F = wk.F;
     BBFMM_HIP_TRY(launch_ad_p2m(g, t->d_leaves, nleaves, qs, nrhs, W, s));
-    BBFMM_HIP_TRY(mark(p, kP2M, s));
+    BBFMM_HIP_TRY(mark(p, wk, kP2M, s));
     for (int l = t->depth - 1; l >= 2; --l)
       BBFMM_HIP_TRY(launch_ad_m2m(g, T.level_off[l], T.level_off[l + 1], W, nrhs, s));
-    BBFMM_HIP_TRY(mark(p, kM2M, s));
+    BBFMM_HIP_TRY(mark(p, wk, kM2M, s));
     BBFMM_HIP_TRY(launch_fill_zero(F, p->exp_elems * nrhs, s));
     const M2LArgs a = adaptive_m2l_args(p, nrhs, W, F);
     BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, s));
-    BBFMM_HIP_TRY(mark(p, kM2L, s));
+    BBFMM_HIP_TRY(mark(p, wk, kM2L, s));
     BBFMM_HIP_TRY(launch_ad_p2l(g, t->d_x_node, t->d_x_off, t->d_x_idx, (int)T.x_node.size(), qs, nrhs, F, s));
     for (int l = 2; l < t->depth; ++l)
       BBFMM_HIP_TRY(launch_ad_l2l(g, T.level_off[l], T.level_off[l + 1], F, nrhs, s));
-    BBFMM_HIP_TRY(mark(p, kL2L, s));
-    BBFMM_HIP_TRY(launch_ad_l2p(g, t->d_leaves, nleaves, F, nrhs, p->phis, s));
+    BBFMM_HIP_TRY(mark(p, wk, kL2L, s));
+    BBFMM_HIP_TRY(launch_ad_l2p(g, t->d_leaves, nleaves, F, nrhs, wk.phis, s));
     if (!T.w_idx.empty())
-      BBFMM_HIP_TRY(launch_ad_m2p(g, t->d_leaves, t->d_w_off, t->d_w_idx, nleaves, W, nrhs, p->phis, s));
-    BBFMM_HIP_TRY(mark(p, kL2P, s));
-    far = p->phis;
+      BBFMM_HIP_TRY(launch_ad_m2p(g, t->d_leaves, t->d_w_off, t->d_w_idx, nleaves, W, nrhs, wk.phis, s));
+    BBFMM_HIP_TRY(mark(p, wk, kL2P, s));
+    far = wk.phis;
   }
   BBFMM_HIP_TRY(launch_ad_p2p_scatter(g, t->d_leaf_pos, t->d_u_off, t->d_u_idx, qs, far, nrhs, out, s));
-  BBFMM_HIP_TRY(mark(p, kP2P, s));
-  p->slot_nrhs[slot] = nrhs;
+  BBFMM_HIP_TRY(mark(p, wk, kP2P, s));
   return BBFMM_OK;
 }
 
-// One forward pass of the chain on `in` (caller order) into `out` (caller order); slot 0 keeps
-// the locals of an apply, slot 1 those of an adjoint apply.
-bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, int slot,
-                       hipStream_t s) {
-  bbfmm_status st = ensure_buffers(p, nrhs, slot);
-  if (st != BBFMM_OK) return st;
+// One forward pass of the chain on `in` (caller order) into `out` (caller order) with the work
+// arrays `wk`.
+bbfmm_status run_chain_in(bbfmm_plan* p, const double* in, int nrhs, double* out, const Work& wk, hipStream_t s) {
   const bbfmm_tree* t = p->tree;
-  if (t->adaptive) return run_chain_adaptive(p, in, nrhs, out, slot, s);
+  if (t->adaptive) return run_chain_adaptive(p, in, nrhs, out, wk, s);
   const PassGeom g = geom_of(p);
-  double* qs = p->qs[slot];
-  BBFMM_HIP_TRY(mark(p, kPassStart, s));
+  double* qs = wk.qs;
+  BBFMM_HIP_TRY(mark(p, wk, kPassStart, s));
   BBFMM_HIP_TRY(launch_gather_rows(in, t->perm, t->n, nrhs, qs, s));
-  BBFMM_HIP_TRY(mark(p, kGather, s));
+  BBFMM_HIP_TRY(mark(p, wk, kGather, s));
   const double* far = nullptr;
   if (t->depth >= 2) {
-    double* W = p->W;
-    double* F = p->F[slot];
+    double* W = wk.W;
+    double* F = wk.F;
     const int d = t->depth;
     BBFMM_HIP_TRY(launch_p2m(g, qs, nrhs, W + p->level_off[d] * nrhs, s));
-    BBFMM_HIP_TRY(mark(p, kP2M, s));
+    BBFMM_HIP_TRY(mark(p, wk, kP2M, s));
     for (int l = d - 1; l >= 2; --l)
       BBFMM_HIP_TRY(launch_m2m(g, l, W + p->level_off[l + 1] * nrhs, W + p->level_off[l] * nrhs, nrhs, s));
-    BBFMM_HIP_TRY(mark(p, kM2M, s));
+    BBFMM_HIP_TRY(mark(p, wk, kM2M, s));
     if (p->variant != 0) {
       const bbfmm_status st2 = sa_levels(p, nrhs, W, F, -1, s);
       if (st2 != BBFMM_OK) return st2;
@@ -351,18 +348,28 @@ bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, i
       const M2LArgs a = m2l_args(p, nrhs, W, F, -1);
       BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, s));
     }
-    BBFMM_HIP_TRY(mark(p, kM2L, s));
+    BBFMM_HIP_TRY(mark(p, wk, kM2L, s));
     for (int l = 3; l <= d; ++l)
       BBFMM_HIP_TRY(launch_l2l(g, l - 1, F + p->level_off[l - 1] * nrhs, F + p->level_off[l] * nrhs, nrhs, s));
-    BBFMM_HIP_TRY(mark(p, kL2L, s));
-    BBFMM_HIP_TRY(launch_l2p(g, F + p->level_off[d] * nrhs, nrhs, p->phis, s));
-    BBFMM_HIP_TRY(mark(p, kL2P, s));
-    far = p->phis;
+    BBFMM_HIP_TRY(mark(p, wk, kL2L, s));
+    BBFMM_HIP_TRY(launch_l2p(g, F + p->level_off[d] * nrhs, nrhs, wk.phis, s));
+    BBFMM_HIP_TRY(mark(p, wk, kL2P, s));
+    far = wk.phis;
   }
   BBFMM_HIP_TRY(launch_p2p_scatter(g, qs, far, nrhs, out, s));
-  BBFMM_HIP_TRY(mark(p, kP2P, s));
-  p->slot_nrhs[slot] = nrhs;
+  BBFMM_HIP_TRY(mark(p, wk, kP2P, s));
   return BBFMM_OK;
+}
+
+// The chain with the plan's own buffers: slot 0 keeps the locals of an apply, slot 1 those of an
+// adjoint apply (for bbfmm_eval_grad).
+bbfmm_status run_chain(bbfmm_plan* p, const double* in, int nrhs, double* out, int slot, hipStream_t s) {
+  bbfmm_status st = ensure_buffers(p, nrhs, slot);
+  if (st != BBFMM_OK) return st;
+  const Work wk{p->qs[slot], p->W, p->F[slot], p->phis, true};
+  st = run_chain_in(p, in, nrhs, out, wk, s);
+  if (st == BBFMM_OK) p->slot_nrhs[slot] = nrhs;
+  return st;
 }
 
 std::vector<int> octant_tables(std::vector<int>* grp) {
@@ -591,6 +598,42 @@ bbfmm_status build_adaptive(std::unique_ptr<bbfmm_tree>& t, const double* d_poin
 }
 
 }  // namespace
+
+bbfmm_status run_chain_work(bbfmm_plan* p, const double* in, int nrhs, double* out, const Work& wk,
+                            hipStream_t s) {
+  return run_chain_in(p, in, nrhs, out, wk, s);
+}
+
+// A plan holds one set of work buffers. A call on another stream than the plan's last call may
+// start only once that call has completed; calls on the same stream are ordered by the stream.
+bbfmm_status begin_call(bbfmm_plan* p, hipStream_t s) {
+  if (!p->busy_set || p->busy_stream == s) return BBFMM_OK;
+  const hipError_t q = hipEventQuery(p->busy);
+  if (q == hipErrorNotReady)
+    return fail(BBFMM_ESTATE, "the plan's previous call on another stream has not completed (one call at a time "
+                              "per plan; synchronise that stream first)");
+  if (q != hipSuccess) return fail(BBFMM_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+  return BBFMM_OK;
+}
+
+bbfmm_status end_call(bbfmm_plan* p, hipStream_t s, bbfmm_status st) {
+  if (st != BBFMM_OK) return st;
+  if (!p->busy) BBFMM_HIP_TRY(hipEventCreateWithFlags(&p->busy, hipEventDisableTiming));
+  BBFMM_HIP_TRY(hipEventRecord(p->busy, s));
+  p->busy_stream = s;
+  p->busy_set = true;
+  return BBFMM_OK;
+}
+
+bbfmm_status check_apply_args(const bbfmm_plan* p, const double* in, int32_t nrhs,
+                                     const double* out) {
+  if (!p) return fail(BBFMM_EINVAL, "plan is null");
+  if (!in || !out) return fail(BBFMM_EINVAL, "null input or output");
+  if (nrhs < 1 || nrhs > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64]");
+  if (in == out) return fail(BBFMM_EINVAL, "input and output must not alias");
+  return BBFMM_OK;
+}
+
 }  // namespace bbfmm
 
 using namespace bbfmm;
@@ -677,6 +720,24 @@ bbfmm_status bbfmm_build_octree(const double* d_points, int64_t n, const bbfmm_t
   cleanup();
   t->bytes = bytes;
   *out = t.release();
+  return BBFMM_OK;
+}
+
+bbfmm_status bbfmm_tree_update_points(bbfmm_tree* t, const double* d_points, void* stream) {
+  if (!t || !d_points) return fail(BBFMM_EINVAL, "null tree or points");
+  if (t->adaptive) return fail(BBFMM_EUNSUPPORTED, "moving the points of an adaptive tree");
+  if (!t->xs) return fail(BBFMM_ESTATE, "host-only tree");
+  hipStream_t s = (hipStream_t)stream;
+  if (!t->d_move_flag) BBFMM_HIP_TRY(dmalloc(&t->d_move_flag, 1, &t->bytes));
+  unsigned bad = 0;
+  const double wleaf = t->width / (double)(1 << t->depth);
+  BBFMM_HIP_TRY(hipMemsetAsync(t->d_move_flag, 0, sizeof(unsigned), s));
+  BBFMM_HIP_TRY(launch_move_check(d_points, t->n, t->perm, t->leaf_of, t->lo, wleaf, t->depth, t->d_move_flag, s));
+  BBFMM_HIP_TRY(hipMemcpyAsync(&bad, t->d_move_flag, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  BBFMM_HIP_TRY(hipStreamSynchronize(s));
+  if (bad != 0)
+    return fail(BBFMM_EINVAL, std::to_string(bad) + " points left their leaf or the root cube (or are not finite)");
+  BBFMM_HIP_TRY(launch_move_write(d_points, t->n, t->perm, t->xs, t->ys, t->zs, s));
   return BBFMM_OK;
 }
 
@@ -977,7 +1038,9 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
 void bbfmm_plan_destroy(bbfmm_plan* p) {
   if (!p) return;
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  if (p->busy) (void)hipEventDestroy(p->busy);
   free_buffers(p);
+  dfree(p->cplx_q); dfree(p->cplx_a); dfree(p->cplx_b);
   dfree(p->ops_hi); dfree(p->ops_lo); dfree(p->d_op_off); dfree(p->d_op_rank); dfree(p->d_tab);
   dfree(p->d_grp); dfree(p->d_sig); dfree(p->d_siginv); dfree(p->d_tk); dfree(p->d_m2m);
   dfree(p->d_zeros); dfree(p->d_segs); dfree(p->d_utgt); dfree(p->d_uvsrc);
@@ -987,19 +1050,12 @@ void bbfmm_plan_destroy(bbfmm_plan* p) {
   delete p;
 }
 
-static bbfmm_status check_apply_args(const bbfmm_plan* p, const double* in, int32_t nrhs,
-                                     const double* out) {
-  if (!p) return fail(BBFMM_EINVAL, "plan is null");
-  if (!in || !out) return fail(BBFMM_EINVAL, "null input or output");
-  if (nrhs < 1 || nrhs > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64]");
-  if (in == out) return fail(BBFMM_EINVAL, "input and output must not alias");
-  return BBFMM_OK;
-}
-
 bbfmm_status bbfmm_apply(bbfmm_plan* p, const double* d_q, int32_t nrhs, double* d_phi, void* stream) {
   bbfmm_status st = check_apply_args(p, d_q, nrhs, d_phi);
   if (st != BBFMM_OK) return st;
-  return run_chain(p, d_q, nrhs, d_phi, 0, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = begin_call(p, s)) != BBFMM_OK) return st;
+  return end_call(p, s, run_chain(p, d_q, nrhs, d_phi, 0, s));
 }
 
 bbfmm_status bbfmm_apply_adjoint(bbfmm_plan* p, const double* d_g, int32_t nrhs, double* d_grad_q,
@@ -1009,7 +1065,9 @@ bbfmm_status bbfmm_apply_adjoint(bbfmm_plan* p, const double* d_g, int32_t nrhs,
   // The supported kernels are symmetric and sources = targets: L2P^T = P2M, L2L^T = M2M,
   // K_t^T = K_{-t} (so M2L^T is the M2L of the reversed pairs) and the near field is symmetric;
   // the transposed chain is therefore the forward pass sequence run on g.
-  return run_chain(p, d_g, nrhs, d_grad_q, 1, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = begin_call(p, s)) != BBFMM_OK) return st;
+  return end_call(p, s, run_chain(p, d_g, nrhs, d_grad_q, 1, s));
 }
 
 bbfmm_status bbfmm_eval_grad(bbfmm_plan* p, const double* d_q, const double* d_g, int32_t nrhs,
@@ -1022,6 +1080,8 @@ bbfmm_status bbfmm_eval_grad(bbfmm_plan* p, const double* d_q, const double* d_g
   if (p->slot_nrhs[0] != nrhs || p->slot_nrhs[1] != nrhs)
     return fail(BBFMM_ESTATE, "eval_grad needs bbfmm_apply(q) and bbfmm_apply_adjoint(g) with this nrhs first");
   hipStream_t s = (hipStream_t)stream;
+  bbfmm_status st = begin_call(p, s);
+  if (st != BBFMM_OK) return st;
   const bbfmm_tree* t = p->tree;
   const PassGeom g = geom_of(p);
   // densities in sorted order are already in qs[0] / qs[1] from the two chains; re-gather in case
@@ -1031,7 +1091,48 @@ bbfmm_status bbfmm_eval_grad(bbfmm_plan* p, const double* d_q, const double* d_g
   const double* Fq = t->depth >= 2 ? p->F[0] + p->level_off[t->depth] * nrhs : nullptr;
   const double* Fg = t->depth >= 2 ? p->F[1] + p->level_off[t->depth] * nrhs : nullptr;
   BBFMM_HIP_TRY(launch_grad(g, p->qs[0], p->qs[1], Fq, Fg, nrhs, roles, d_grad_x, s));
-  return BBFMM_OK;
+  return end_call(p, s, BBFMM_OK);
+}
+
+bbfmm_status bbfmm_helmholtz_apply(bbfmm_plan* re, bbfmm_plan* im, const double* d_q, int32_t nrhs,
+                                   int32_t complex_q, double* d_phi, void* stream) {
+  if (!re || !im) return fail(BBFMM_EINVAL, "plan is null");
+  if (!d_q || !d_phi) return fail(BBFMM_EINVAL, "null input or output");
+  if (d_q == d_phi) return fail(BBFMM_EINVAL, "input and output must not alias");
+  if (complex_q != 0 && complex_q != 1) return fail(BBFMM_EINVAL, "complex_q must be 0 or 1");
+  const int cols = complex_q ? 2 * nrhs : nrhs;
+  if (nrhs < 1 || cols > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64] (real q) or [1, 32] (complex q)");
+  if (re == im) return fail(BBFMM_EINVAL, "the two plans must differ");
+  if (re->kernel != BBFMM_K_HELM_COS || im->kernel != BBFMM_K_HELM_SIN)
+    return fail(BBFMM_EINVAL, "re must be a cos(kr)/r plan and im a sin(kr)/r plan");
+  if (re->tree != im->tree || re->c != im->c || re->order != im->order)
+    return fail(BBFMM_EINVAL, "the two plans must share tree, order and wavenumber");
+  hipStream_t s = (hipStream_t)stream;
+  bbfmm_status st = begin_call(re, s);
+  if (st == BBFMM_OK) st = begin_call(im, s);
+  if (st != BBFMM_OK) return st;
+  const long long n = re->tree->n;
+  const long long need = n * cols;
+  if (need > re->cplx_cap) {
+    dfree(re->cplx_q); dfree(re->cplx_a); dfree(re->cplx_b);
+    re->cplx_q = re->cplx_a = re->cplx_b = nullptr;
+    re->cplx_cap = 0;
+    BBFMM_HIP_TRY(dmalloc(&re->cplx_q, (size_t)need, nullptr));
+    BBFMM_HIP_TRY(dmalloc(&re->cplx_a, (size_t)need, nullptr));
+    BBFMM_HIP_TRY(dmalloc(&re->cplx_b, (size_t)need, nullptr));
+    re->cplx_cap = need;
+  }
+  const double* in = d_q;
+  if (complex_q) {
+    BBFMM_HIP_TRY(launch_split_complex(d_q, n, nrhs, re->cplx_q, s));
+    in = re->cplx_q;
+  }
+  st = run_chain(re, in, cols, re->cplx_a, 0, s);
+  if (st == BBFMM_OK) st = run_chain(im, in, cols, re->cplx_b, 0, s);
+  if (st != BBFMM_OK) return st;
+  BBFMM_HIP_TRY(launch_combine_complex(re->cplx_a, re->cplx_b, n, nrhs, complex_q, d_phi, s));
+  st = end_call(re, s, BBFMM_OK);
+  return st != BBFMM_OK ? st : end_call(im, s, BBFMM_OK);
 }
 
 bbfmm_status bbfmm_plan_set_timing(bbfmm_plan* p, int32_t enable) {
@@ -1195,7 +1296,7 @@ bbfmm_status bbfmm_plan_stats(const bbfmm_plan* p, bbfmm_stats* out) {
   return BBFMM_OK;
 }
 
-bbfmm_status bbfmm_debug_get_expansions(const bbfmm_plan* p, int32_t level, int32_t which,
+bbfmm_status bbfmm_debug_get_expansions(const bbfmm_plan* p, int32_t level, int32_t which, int32_t nrhs_out,
                                         double* d_out, void* stream) {
   if (!p || !d_out) return fail(BBFMM_EINVAL, "null argument");
   const bbfmm_tree* t = p->tree;
@@ -1204,6 +1305,9 @@ bbfmm_status bbfmm_debug_get_expansions(const bbfmm_plan* p, int32_t level, int3
   if (which < 0 || which > 2) return fail(BBFMM_EINVAL, "which must be 0, 1 or 2");
   const int nrhs = p->slot_nrhs[0];
   if (nrhs == 0 || !p->W) return fail(BBFMM_ESTATE, "no apply has run on this plan");
+  if (nrhs_out != nrhs)
+    return fail(BBFMM_EINVAL, "nrhs " + std::to_string(nrhs_out) + " differs from the last apply's " +
+                                  std::to_string(nrhs));
   const size_t count = (size_t)(1LL << (3 * level)) * p->nn * nrhs;
   const double* src = nullptr;
   if (which == 0) src = p->W + p->level_off[level] * nrhs;
@@ -1225,14 +1329,17 @@ bbfmm_status bbfmm_debug_m2l_level(bbfmm_plan* p, int32_t level, const double* d
   if (p->tree->adaptive) return fail(BBFMM_EUNSUPPORTED, "uniform trees only");
   if (level < 2 || level > p->tree->depth) return fail(BBFMM_EINVAL, "level must be in [2, depth]");
   if (nrhs < 1 || nrhs > kMaxRhs) return fail(BBFMM_EINVAL, "nrhs must be in [1, 64]");
+  hipStream_t s = (hipStream_t)stream;
+  bbfmm_status st = begin_call(p, s);
+  if (st != BBFMM_OK) return st;
   if (p->variant != BBFMM_VARIANT_BLOCKED) {
-    bbfmm_status st = ensure_buffers(p, nrhs, 0);
+    st = ensure_buffers(p, nrhs, 0);
     if (st != BBFMM_OK) return st;
-    return sa_levels(p, nrhs, d_w, d_f, level, (hipStream_t)stream);
+    return end_call(p, s, sa_levels(p, nrhs, d_w, d_f, level, s));
   }
   const M2LArgs a = m2l_args(p, nrhs, d_w, d_f, level);
-  BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, (hipStream_t)stream));
-  return BBFMM_OK;
+  BBFMM_HIP_TRY(launch_m2l(p->order, p->lowrank, p->prec, a, s));
+  return end_call(p, s, BBFMM_OK);
 }
 
 bbfmm_status bbfmm_m2l_unblocked(bbfmm_plan* p, int32_t level, int32_t variant, const double* d_w,
@@ -1250,6 +1357,8 @@ bbfmm_status bbfmm_m2l_unblocked(bbfmm_plan* p, int32_t level, int32_t variant, 
     for (int q = 0; q < kNumSym; ++q)
       if (p->ranks[set * kNumSym + q] > 64) return fail(BBFMM_EUNSUPPORTED, "ranks above 64");
   hipStream_t s = (hipStream_t)stream;
+  const bbfmm_status st0 = begin_call(p, s);
+  if (st0 != BBFMM_OK) return st0;
   if (p->abl_variant != variant || p->abl_set != set) {
     // operators of the variant on the host, transposed, then uploaded
     const bool sym = variant == 1 || variant == 3;
@@ -1307,7 +1416,7 @@ bbfmm_status bbfmm_m2l_unblocked(bbfmm_plan* p, int32_t level, int32_t variant, 
   a.ops = p->d_abl_ops; a.op_off = p->d_abl_off; a.op_rank = p->d_abl_rank;
   a.tab = p->d_tab; a.sig = p->d_sig; a.variant = variant; a.nrhs = nrhs;
   BBFMM_HIP_TRY(launch_m2l_unblocked(L, a, s));
-  return BBFMM_OK;
+  return end_call(p, s, BBFMM_OK);
 }
 
 bbfmm_status bbfmm_debug_tree_order(const bbfmm_tree* t, int32_t* d_perm, int32_t* d_leaf_start,

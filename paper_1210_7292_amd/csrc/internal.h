@@ -135,6 +135,12 @@ hipError_t exclusive_scan(const int* in, int* out, long long n, hipStream_t s); 
 // Source lists (table entry -> source node or -1) of the given non-empty targets of a uniform level.
 hipError_t launch_uniform_vsrc(const int* leaf_start, int depth, int level, const int* tgt_node, int ntgt,
                                int node_base, const int* tab, int* vsrc, hipStream_t s);
+// Moved points of a uniform tree: *bad (zeroed by the caller) += points that left their leaf or
+// the root cube; then the sorted coordinates are rewritten in the tree's order.
+hipError_t launch_move_check(const double* pts, long long n, const int* perm, const int* leaf_of,
+                             const double lo[3], double wleaf, int depth, unsigned* bad, hipStream_t s);
+hipError_t launch_move_write(const double* pts, long long n, const int* perm, double* xs, double* ys, double* zs,
+                             hipStream_t s);
 hipError_t launch_scatter(const unsigned* keys, long long n, const int* leaf_start, int* cursor,
                           int* tmp, hipStream_t s);
 hipError_t launch_order(const double* pts, const unsigned* keys, long long n,
@@ -226,6 +232,11 @@ hipError_t launch_grad(const PassGeom& g, const double* qs, const double* gs, co
 hipError_t launch_count_pairs(const int* leaf_start, int depth, int level, const int* tab,
                               unsigned long long* counts16, hipStream_t s);
 
+// ---- complex Helmholtz staging -------------------------------------------------------------
+hipError_t launch_split_complex(const double* zq, long long n, int nrhs, double* q2, hipStream_t s);
+hipError_t launch_combine_complex(const double* a, const double* b, long long n, int nrhs, int cplx, double* phi,
+                                  hipStream_t s);
+
 // ---- adaptive passes ----------------------------------------------------------------------
 // Node arrays of an adaptive tree on the device (global node ids, level-major).
 struct AdaptiveGeom {
@@ -257,6 +268,16 @@ hipError_t launch_ad_p2p_scatter(const AdaptiveGeom& g, const int* leaf_pos, con
                                  const int* u_idx, const double* qs, const double* phis_far, int nrhs,
                                  double* phi_out, hipStream_t s);
 
+// Work arrays of one run of the chain: sorted densities, multipoles and locals of every level,
+// sorted far-field potentials; `trace` lets the pass tracing record events.
+struct Work {
+  double* qs;
+  double* W;
+  double* F;
+  double* phis;
+  bool trace;
+};
+
 }  // namespace bbfmm
 
 struct bbfmm_tree {
@@ -280,6 +301,7 @@ struct bbfmm_tree {
   int* d_w_off = nullptr; int* d_w_idx = nullptr;
   int* d_x_node = nullptr; int* d_x_off = nullptr; int* d_x_idx = nullptr;
   int* d_m2l_tgt = nullptr; int* d_vsrc = nullptr;
+  unsigned* d_move_flag = nullptr;   // counter of bbfmm_tree_update_points
 };
 
 struct bbfmm_plan {
@@ -346,9 +368,32 @@ struct bbfmm_plan {
   int* d_sa_rank = nullptr;                        // [set][512]
   double* d_what = nullptr;                        // [cells of the leaf level][rp][nrhs_cap]
   double* d_fhat = nullptr;
+  // complex Helmholtz applies (this plan as the real part): [Re q | Im q] and the two results
+  double* cplx_q = nullptr;
+  double* cplx_a = nullptr;
+  double* cplx_b = nullptr;
+  long long cplx_cap = 0;                          // doubles in each
+  // overlap guard: completion of the last apply-type call and the stream it ran on
+  hipEvent_t busy = nullptr;
+  hipStream_t busy_stream = nullptr;
+  bool busy_set = false;
   // per-pass tracing: events recorded in order, each tagged with the pass it closes (-1 = start)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_tag;
   size_t ev_used = 0;
 };
+
+namespace bbfmm {
+// The apply chain (gather -> P2M -> M2M -> M2L -> L2L -> L2P -> near field -> scatter) of a plan
+// on caller-provided work arrays; the plan's own buffers are not touched.
+bbfmm_status run_chain_work(bbfmm_plan* p, const double* in, int nrhs, double* out, const Work& wk,
+                            hipStream_t s);
+// Argument checks shared by the apply-type entry points, and the one-call-at-a-time guard of a
+// plan: begin_call refuses a call on another stream while the plan's last call is running,
+// end_call records the completion event of the call just enqueued.
+bbfmm_status check_apply_args(const bbfmm_plan* p, const double* in, int32_t nrhs, const double* out);
+bbfmm_status begin_call(bbfmm_plan* p, hipStream_t s);
+bbfmm_status end_call(bbfmm_plan* p, hipStream_t s, bbfmm_status st);
+bbfmm_status fail(bbfmm_status code, const std::string& msg);
+}  // namespace bbfmm

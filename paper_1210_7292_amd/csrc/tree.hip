@@ -108,6 +108,35 @@ __global__ void order_kernel(const double* __restrict__ pts, const unsigned* __r
   zs[dst] = pts[3 * (long long)i + 2];
 }
 
+// Moved points: counts the points whose leaf (same rule as leaf_keys_kernel, without the clamp)
+// differs from the one they were sorted into, or that are not finite or leave the root cube.
+__global__ void move_check_kernel(const double* __restrict__ pts, long long n, const int* __restrict__ perm,
+                                  const int* __restrict__ leaf_of, double lo0, double lo1, double lo2,
+                                  double inv_w, int side, unsigned* __restrict__ bad) {
+  const long long pos = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (pos >= n) return;
+  const long long i = perm[pos];
+  const double lo[3] = {lo0, lo1, lo2};
+  int c[3];
+  bool ok = true;
+  for (int r = 0; r < 3; ++r) {
+    const double f = floor((pts[3 * i + r] - lo[r]) * inv_w);
+    ok = ok && (f >= 0.0) && (f < (double)side);     // false for NaN
+    c[r] = ok ? (int)f : 0;
+  }
+  if (!ok || morton3(c[0], c[1], c[2]) != (unsigned)leaf_of[pos]) atomicAdd(bad, 1u);
+}
+
+__global__ void move_write_kernel(const double* __restrict__ pts, long long n, const int* __restrict__ perm,
+                                  double* __restrict__ xs, double* __restrict__ ys, double* __restrict__ zs) {
+  const long long pos = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (pos >= n) return;
+  const long long i = perm[pos];
+  xs[pos] = pts[3 * i + 0];
+  ys[pos] = pts[3 * i + 1];
+  zs[pos] = pts[3 * i + 2];
+}
+
 // ---- exclusive scan of int32, 1024 items per block ----------------------------------------
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
@@ -241,6 +270,20 @@ hipError_t launch_order(const double* pts, const unsigned* keys, long long n,
                         double* xs, double* ys, double* zs, hipStream_t s) {
   hipLaunchKernelGGL(order_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pts, keys, n,
                      leaf_start, tmp, perm, leaf_of, xs, ys, zs);
+  return hipGetLastError();
+}
+
+hipError_t launch_move_check(const double* pts, long long n, const int* perm, const int* leaf_of,
+                             const double lo[3], double wleaf, int depth, unsigned* bad, hipStream_t s) {
+  hipLaunchKernelGGL(move_check_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pts, n, perm, leaf_of,
+                     lo[0], lo[1], lo[2], 1.0 / wleaf, 1 << depth, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_move_write(const double* pts, long long n, const int* perm, double* xs, double* ys, double* zs,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(move_write_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pts, n, perm, xs, ys,
+                     zs);
   return hipGetLastError();
 }
 

@@ -26,7 +26,15 @@ def morton_to_oracle(a: np.ndarray, level: int) -> np.ndarray:
 
 
 def rel(a, b) -> float:
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    den = np.sqrt(np.sum(b * b))
-    return float(np.sqrt(np.sum((a - b) ** 2)) / (den if den > 0 else 1.0))
+    """||a - b||_2 / ||b||_2 over all entries (complex entries by their modulus). Real and complex
+    arrays are not mixed: comparing a complex result with a real reference (or the reverse)
+    raises, so that no imaginary part is dropped silently."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if np.iscomplexobj(a) != np.iscomplexobj(b):
+        raise TypeError("rel(): one argument is complex and the other is real")
+    dt = np.complex128 if np.iscomplexobj(a) else np.float64
+    a = a.astype(dt)
+    b = b.astype(dt)
+    den = np.sqrt(np.sum(np.abs(b) ** 2))
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2)) / (den if den > 0 else 1.0))

@@ -116,7 +116,23 @@ def test_complex_helmholtz_potential():
     phi_c = host(hp.apply(torch.complex(dev(qr), dev(qi))))
     oc = O.fmm_apply(pts, qr, order, depth, "helm_cos", k).phi
     osn = O.fmm_apply(pts, qr, order, depth, "helm_sin", k).phi
-    assert rel(phi_r, oc + 1j * osn) < 1e-12
+    assert np.iscomplexobj(phi_r) and np.iscomplexobj(phi_c)
+    # real densities: Re phi = A_cos q, Im phi = A_sin q
+    assert rel(phi_r.real, oc) < 1e-12
+    assert rel(phi_r.imag, osn) < 1e-12
+    # complex densities: Re phi = A_cos Re q - A_sin Im q, Im phi = A_cos Im q + A_sin Re q
+    oci = O.fmm_apply(pts, qi, order, depth, "helm_cos", k).phi
+    osi = O.fmm_apply(pts, qi, order, depth, "helm_sin", k).phi
+    e_re, e_im = rel(phi_c.real, oc - osi), rel(phi_c.imag, oci + osn)
+    say("  complex q: Re", e_re, "Im", e_im)
+    assert e_re < 1e-12 and e_im < 1e-12
+    assert rel(phi_c, (oc - osi) + 1j * (oci + osn)) < 1e-12
+    # the entry point refuses plans that do not form a (cos, sin) pair of one wavenumber
+    other = pk.Plan(tree, "helm_sin", order, 0.0, "fp64", 3.0)
+    with pytest.raises(pk.BBFMMError):
+        pk.binding.helmholtz_apply(hp.re.handle, other.handle, dev(qr), 4000)
+    with pytest.raises(pk.BBFMMError):
+        pk.binding.helmholtz_apply(hp.im.handle, hp.re.handle, dev(qr), 4000)
     tg = np.arange(0, 4000, 16)
     direct = O.brute_force_helmholtz(pts, qr + 1j * qi, k, tg)
     err = np.linalg.norm(phi_c[tg] - direct) / np.linalg.norm(direct)

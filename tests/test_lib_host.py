@@ -155,3 +155,38 @@ def test_validation_without_gpu():
     assert lib.bbfmm_host_operator(0, 0.0, 4, 1.0, 16, 0.0, 0, k.ctypes.data_as(C.c_void_p), None, None, None) == -1
     assert lib.bbfmm_host_operator(0, 0.0, 4, 1.0, 0, 1e-5, 2, k.ctypes.data_as(C.c_void_p), None, None, None) == -1
     assert b"compressor" in lib.bbfmm_last_error()
+
+
+def test_tree_update_points_validates_without_gpu():
+    lib = pk.lib()
+    assert lib.bbfmm_tree_update_points(None, C.c_void_p(8), None) == -1
+    assert b"null" in lib.bbfmm_last_error()
+
+
+def test_binding_rejects_wrong_shapes_before_any_launch():
+    """The library trusts the sizes it is given (n rows per array), so the binding checks every
+    device array against the tree's point count before it hands over a pointer. CPU tensors are
+    used here: the shape check fires before anything else, and no GPU is touched."""
+    torch = pytest.importorskip("torch")
+    bad = torch.zeros((5, 1), dtype=torch.float64)
+    ok = torch.zeros((10, 1), dtype=torch.float64)
+    h = C.c_void_p(0)
+    for call in (lambda: B.apply(h, bad, n=10), lambda: B.apply_adjoint(h, bad, n=10),
+                 lambda: B.eval_grad(h, bad, ok, 3, n=10), lambda: B.eval_grad(h, ok, bad, 3, n=10),
+                 lambda: B.update_points(h, torch.zeros((10, 2), dtype=torch.float64), 10),
+                 lambda: B.update_points(h, torch.zeros((9, 3), dtype=torch.float64), 10),
+                 lambda: B.apply(h, ok, out=bad, n=10),
+                 lambda: B.eval_grad(h, ok, ok, 3, out=torch.zeros((10, 2), dtype=torch.float64), n=10)):
+        with pytest.raises(pk.BBFMMError) as e:
+            call()
+        assert e.value.status == -1 and "shape" in str(e.value)
+    # a right-shaped host tensor is refused as not being device memory
+    with pytest.raises(pk.BBFMMError) as e:
+        B.apply(h, ok, n=10)
+    assert "device" in str(e.value)
+
+
+def test_helmholtz_apply_validates_without_gpu():
+    lib = pk.lib()
+    assert lib.bbfmm_helmholtz_apply(None, None, C.c_void_p(8), 1, 0, C.c_void_p(16), None) == -1
+    assert b"null" in lib.bbfmm_last_error()
