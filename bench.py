@@ -492,7 +492,12 @@ def main():
 
     traffic = m2l_traffic(w.name, prec, args.variant, args.compressor)
 
-    variant = {"sa": "SA", "sarcmp": "SArcmp"}.get(args.variant, "IAblk" if w.svd_eps > 0 else "NAblk")
+    variant = {"sa": "SA", "sarcmp": "SArcmp"}.get(args.variant)
+    if variant is None:
+        # the kernel the plan actually runs: the compressed kernel, or the full-rank one (also on
+        # truncated operators when a rank exceeds the compressed kernel's limit)
+        variant = "IAblk" if st["m2l_kernel"] == 1 else (
+            "NAblk" if w.svd_eps <= 0 else "NAblk on truncated operators (ranks above the compressed kernel's limit)")
     line = {
         "metric": "FMM points/sec of one apply (bbFMM, symmetry-blocked M2L), with M2L TFLOP/s vs "
                   "MFMA peak and rel. L2 error",

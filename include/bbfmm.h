@@ -48,7 +48,7 @@ typedef enum {
   BBFMM_EINVAL = -1,        /* invalid argument (null pointer, size, non-finite or out-of-box point) */
   BBFMM_ENOMEM = -2,        /* device or host allocation failed */
   BBFMM_EHIP = -3,          /* a HIP runtime call failed */
-  BBFMM_EUNSUPPORTED = -4,  /* valid but not supported by this build (e.g. order outside [2, 8]) */
+  BBFMM_EUNSUPPORTED = -4,  /* valid but not supported by this build (e.g. order outside [2, 9]) */
   BBFMM_ESTATE = -5         /* object in the wrong state (e.g. gradient requested before apply) */
 } bbfmm_status;
 
@@ -124,7 +124,9 @@ typedef struct {
   int32_t kernel;    /* bbfmm_kernel */
   double c;          /* regularisation of BBFMM_K_INV_SQRT_R2C2 (> 0), wavenumber of the
                         Helmholtz parts (>= 0), ignored otherwise */
-  int32_t order;     /* Chebyshev order l in [2, 8]; l^3 interpolation points per cell */
+  int32_t order;     /* Chebyshev order l in [2, 9] (the paper's accuracy study runs to 9);
+                        l^3 interpolation points per cell. Order 9: FP64 M2L, blocked variant,
+                        full-rank kernel (with svd_eps > 0 on the truncated operators) */
   double svd_eps;    /* <= 0: full-rank operators (variant NAblk); > 0: each of the 16 operators
                         truncated to the singular values > svd_eps * sigma_1, extended over a
                         tied cluster at the cut (variant IAblk) */
@@ -147,7 +149,8 @@ typedef struct {
                                            (adaptive: the V-list pairs) */
   int64_t pairs_nonempty;               /* ... of which both cells hold points (plan_stats only) */
   double m2l_flops_algorithmic;         /* per right-hand side: sum over non-empty pairs of
-                                           2 l^6 (full) or 4 l^3 r_p (compressed); SA variants:
+                                           2 l^6 (full-rank kernel, also when it runs truncated
+                                           operators) or 4 l^3 r_p (compressed kernel); SA variants:
                                            over all in-box pairs, 2 r^2 (core kept) or 4 r r_t,
                                            plus 4 l^3 r per cell (projection, expansion) */
   double m2l_flops_issued;              /* per right-hand side, MFMA work including padding */
@@ -156,6 +159,10 @@ typedef struct {
   int32_t variant;                      /* bbfmm_variant of the plan */
   int32_t sa_rank;                      /* SA variants: rank r of the basis (first operator set) */
   double sa_mean_core_rank;             /* SA variants: mean rank of the 316 cores (r where kept) */
+  int32_t m2l_kernel;                   /* the M2L kernel the plan runs: 0 full rank (NAblk; with
+                                           svd_eps > 0 when a rank exceeds the compressed kernel's
+                                           limit, on the truncated operators U_p V_p^T), 1
+                                           compressed (IAblk, Eq. ialowrank), 2 SA / SArcmp cores */
 } bbfmm_stats;
 
 typedef struct bbfmm_tree bbfmm_tree;
@@ -205,7 +212,7 @@ bbfmm_status bbfmm_tree_update_points(bbfmm_tree* tree, const double* d_points, 
  * uploads everything. `tree` is borrowed and must outlive the plan.
  * Errors: EINVAL (null, c <= 0 for INV_SQRT_R2C2, c < 0 for the Helmholtz parts, unknown kernel,
  * precision, compressor or variant),
- * EUNSUPPORTED (order outside [2, 8]). */
+ * EUNSUPPORTED (order outside [2, 9]; order 9 with FP32 / split M2L or an SA variant). */
 bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts* opts,
                                   void* stream, bbfmm_plan** out);
 
@@ -352,7 +359,7 @@ bbfmm_status bbfmm_host_symmetry(int32_t order, const int32_t t[3], int32_t* out
  * U (l^3 x r, = U_r Sigma_r) and V (l^3 x r) of `compressor` (bbfmm_compressor) into out_u /
  * out_v (each l^6 doubles capacity) with the rank in *out_rank. Any out pointer may be null.
  * Errors: EINVAL (unknown kernel or compressor, p outside [0, 16), width <= 0), EUNSUPPORTED
- * (order outside [2, 8]). */
+ * (order outside [2, 9]). */
 bbfmm_status bbfmm_host_operator(int32_t kernel, double c, int32_t order, double width,
                                  int32_t p, double svd_eps, int32_t compressor, double* out_k,
                                  double* out_u, double* out_v, int32_t* out_rank);
@@ -363,7 +370,7 @@ bbfmm_status bbfmm_host_operator(int32_t kernel, double c, int32_t order, double
  * V_t = U Vbar_t when recompressed. out_u, out_v: l^3 x r_t row-major (capacity l^3 x l^3 each,
  * may be null); *out_rank_t = r_t, *out_r = r (may be null). Recomputes the whole basis per call.
  * Errors: EINVAL (unknown kernel, width or svd_eps <= 0, t null or not far-field), EUNSUPPORTED
- * (order outside [2, 8]). */
+ * (order outside [2, 9]). */
 bbfmm_status bbfmm_host_sa_operator(int32_t kernel, double c, int32_t order, double width, double svd_eps,
                                     int32_t recompress, const int32_t t[3], double* out_u, double* out_v,
                                     int32_t* out_rank_t, int32_t* out_r);

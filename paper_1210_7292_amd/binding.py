@@ -42,7 +42,8 @@ class Stats(C.Structure):
                 ("pairs_total", C.c_int64), ("pairs_nonempty", C.c_int64),
                 ("m2l_flops_algorithmic", C.c_double), ("m2l_flops_issued", C.c_double),
                 ("precompute_seconds", C.c_double), ("device_bytes", C.c_int64),
-                ("variant", C.c_int32), ("sa_rank", C.c_int32), ("sa_mean_core_rank", C.c_double)]
+                ("variant", C.c_int32), ("sa_rank", C.c_int32), ("sa_mean_core_rank", C.c_double),
+                ("m2l_kernel", C.c_int32)]
 
 
 class AdaptiveInfo(C.Structure):

@@ -465,6 +465,7 @@ hipError_t ad_order(int order, Args... args) {
     case 6: return Fn<6>::run(args...);
     case 7: return Fn<7>::run(args...);
     case 8: return Fn<8>::run(args...);
+    case 9: return Fn<9>::run(args...);
     default: return hipErrorInvalidValue;
   }
 }

@@ -765,7 +765,11 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
       opts->variant != BBFMM_VARIANT_SARCMP)
     return fail(BBFMM_EINVAL, "unknown M2L variant");
   if (opts->order < 2 || opts->order > kMaxOrder)
-    return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
+    return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 9]");
+  if (opts->order == 9 && opts->m2l_prec != BBFMM_M2L_FP64)
+    return fail(BBFMM_EUNSUPPORTED, "order 9 runs the M2L in FP64 only");
+  if (opts->order == 9 && opts->variant != BBFMM_VARIANT_BLOCKED)
+    return fail(BBFMM_EUNSUPPORTED, "the SA variants run at orders up to 8");
   if (opts->variant != BBFMM_VARIANT_BLOCKED) {
     if (!(opts->svd_eps > 0)) return fail(BBFMM_EINVAL, "the SA variants need svd_eps > 0");
     if (tree->adaptive) return fail(BBFMM_EUNSUPPORTED, "the SA variants run on uniform trees");
@@ -1170,6 +1174,7 @@ bbfmm_status bbfmm_plan_stats(const bbfmm_plan* p, bbfmm_stats* out) {
   out->n_levels_m2l = t->depth >= 2 ? t->depth - 1 : 0;
   out->n_operator_sets = p->nsets;
   for (int q = 0; q < kNumSym; ++q) out->rank[q] = p->eps > 0 ? p->ranks[q] : p->nn;
+  out->m2l_kernel = p->variant != BBFMM_VARIANT_BLOCKED ? 2 : (p->lowrank ? 1 : 0);
   out->variant = p->variant;
   if (p->variant != BBFMM_VARIANT_BLOCKED && !p->sa_r.empty()) {
     out->sa_rank = p->sa_r[0];
@@ -1208,7 +1213,7 @@ bbfmm_status bbfmm_plan_stats(const bbfmm_plan* p, bbfmm_stats* out) {
         out->pairs_total += cnt[q];
         out->pairs_nonempty += cnt[q];
         const double r = p->ranks[set * kNumSym + q];
-        out->m2l_flops_algorithmic += c * (p->eps > 0 ? 4.0 * nn * r : 2.0 * nn * nn);
+        out->m2l_flops_algorithmic += c * (p->lowrank ? 4.0 * nn * r : 2.0 * nn * nn);
       }
       // issued: every tile of 64 columns runs every transfer vector of its octant
       for (int o = 0; o < 8; ++o) {
@@ -1275,7 +1280,7 @@ bbfmm_status bbfmm_plan_stats(const bbfmm_plan* p, bbfmm_stats* out) {
       const double c = (double)counts[16 * (l - 2) + q];
       out->pairs_nonempty += (long long)c;
       const double r = p->ranks[set * kNumSym + q];
-      out->m2l_flops_algorithmic += c * (p->eps > 0 ? 4.0 * nn * r : 2.0 * nn * nn);
+      out->m2l_flops_algorithmic += c * (p->lowrank ? 4.0 * nn * r : 2.0 * nn * nn);
     }
     // issued: every tile runs every transfer vector of its octant (upper bound for the segment
     // path, which skips transfer vectors without a source in the tile)
@@ -1525,7 +1530,7 @@ bbfmm_status bbfmm_host_adaptive_tree(const double* points, int64_t n, int32_t m
 
 bbfmm_status bbfmm_host_symmetry(int32_t order, const int32_t t[3], int32_t* out_t16,
                                  int32_t* out_p, int32_t* out_sigma) {
-  if (order < 2 || order > kMaxOrder) return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
+  if (order < 2 || order > kMaxOrder) return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 9]");
   const auto& reps = representatives();
   if (out_t16)
     for (int q = 0; q < kNumSym; ++q)
@@ -1549,7 +1554,7 @@ bbfmm_status bbfmm_host_operator(int32_t kernel, double c, int32_t order, double
                                  double svd_eps, int32_t compressor, double* out_k, double* out_u,
                                  double* out_v, int32_t* out_rank) {
   if (!valid_kernel(kernel)) return fail(BBFMM_EINVAL, "unknown kernel");
-  if (order < 2 || order > kMaxOrder) return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
+  if (order < 2 || order > kMaxOrder) return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 9]");
   if (p < 0 || p >= kNumSym) return fail(BBFMM_EINVAL, "p must be in [0, 16)");
   if (!(width > 0)) return fail(BBFMM_EINVAL, "width must be > 0");
   if (compressor != BBFMM_COMPRESS_SVD && compressor != BBFMM_COMPRESS_ACA)
@@ -1574,7 +1579,7 @@ bbfmm_status bbfmm_host_sa_operator(int32_t kernel, double c, int32_t order, dou
                                     int32_t recompress, const int32_t t[3], double* out_u, double* out_v,
                                     int32_t* out_rank_t, int32_t* out_r) {
   if (!valid_kernel(kernel)) return fail(BBFMM_EINVAL, "unknown kernel");
-  if (order < 2 || order > kMaxOrder) return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 8]");
+  if (order < 2 || order > kMaxOrder) return fail(BBFMM_EUNSUPPORTED, "order must be in [2, 9]");
   if (!(width > 0) || !(svd_eps > 0) || !t) return fail(BBFMM_EINVAL, "width and svd_eps must be > 0, t non-null");
   if (std::max({std::abs(t[0]), std::abs(t[1]), std::abs(t[2])}) < 2 ||
       std::max({std::abs(t[0]), std::abs(t[1]), std::abs(t[2])}) > 3)

@@ -9,7 +9,7 @@
 
 namespace bbfmm {
 
-constexpr int kMaxOrder = 8;
+constexpr int kMaxOrder = 9;
 constexpr int kNumSym = 16;      // |T_sym| (Eq. reduced_interaction_list)
 constexpr int kNumPerms = 48;    // 8 axial reflections x 6 axis orders
 constexpr int kFarPerOctant = 189;

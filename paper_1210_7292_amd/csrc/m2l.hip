@@ -761,12 +761,18 @@ __global__ __launch_bounds__(64 * W8, 2) void m2l_lowrank_kernel(M2LArgs a) {
 }
 
 // K_p column chunk of the full-rank kernel; order 8 in FP32 takes 16 so that the permutation
-// tables fit in LDS beside the chunk
-template <int L, int PREC> constexpr int full_kc() { return L <= 2 ? 8 : (L == 8 && PREC == 1) ? 16 : 32; }
+// tables fit in LDS beside the chunk, order 9 (FP64 only) 16 so that the chunk fits (99 KB)
+template <int L, int PREC> constexpr int full_kc() {
+  return L <= 2 ? 8 : ((L == 8 && PREC == 1) || L >= 9) ? 16 : 32;
+}
 // waves per column group of the full-rank kernel: row blocks split so that the accumulators of
 // the largest orders fit the register file with two waves per SIMD
 template <int L> constexpr int full_rs() { return L >= 7 ? 2 : 1; }
 template <int L> constexpr int rank_limit() { return L <= 6 ? 32 : 16; }
+// Order 9 runs the full-rank kernel in FP64 only: two factors of rank 16 would not fit in LDS
+// (2 x 730 x 17 doubles), and the FP32 accumulators with their FP64 sums would not fit the
+// register file beside the 23 row blocks per wave.
+constexpr int kMaxLowrankOrder = 8;
 // Waves per compressed-kernel workgroup: 4 (64 columns) when the workgroup's LDS lets two of
 // them share a CU, so that one computes while the other restages factors at a representative
 // change; 8 otherwise. Mirrors the kernel's LDS arrays.
@@ -824,7 +830,7 @@ void split_tail(M2LArgs& a, const void* kern, int threads, int np) {
 template <int L, int PREC, bool AD>
 hipError_t launch_ld(bool lowrank, M2LArgs a, hipStream_t s) {
   if (lowrank) {
-    if constexpr (L >= 3) {
+    if constexpr (L >= 3 && L <= kMaxLowrankOrder) {
       constexpr int W8 = lowrank_waves(L, PREC);
       auto kern1 = m2l_lowrank_kernel<L, rank_limit<L>(), PREC, W8, true, AD>;
       auto kernn = m2l_lowrank_kernel<L, rank_limit<L>(), PREC, W8, false, AD>;
@@ -874,6 +880,9 @@ hipError_t launch_prec(int order, bool lowrank, const M2LArgs& a, hipStream_t s)
     case 6: return launch_l<6, PREC>(lowrank, a, s);
     case 7: return launch_l<7, PREC>(lowrank, a, s);
     case 8: return launch_l<8, PREC>(lowrank, a, s);
+    case 9:
+      if constexpr (PREC == 0) return launch_l<9, 0>(lowrank, a, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -881,7 +890,7 @@ hipError_t launch_prec(int order, bool lowrank, const M2LArgs& a, hipStream_t s)
 }  // namespace
 
 int m2l_ia_rank_limit(int order) {
-  if (order < 3) return 0;
+  if (order < 3 || order > kMaxLowrankOrder) return 0;
   return order <= 6 ? 32 : 16;
 }
 
@@ -914,7 +923,7 @@ double m2l_issued_flops_per_t(int order, bool lowrank, int rank) {
   const int np = (nn + 15) / 16 * 16;
   const double mfma = 2.0 * 16 * 16 * 4;   // flops of one 16x16x4 MFMA
   if (!lowrank) {
-    const int kc = order <= 2 ? 8 : 32;
+    const int kc = order <= 2 ? 8 : order >= 9 ? 16 : 32;
     const int nch = (nn + kc - 1) / kc;
     return (double)(np / 16) * (nch * kc / 4) * mfma * 4;
   }

@@ -159,6 +159,7 @@ hipError_t launch_m2l_unblocked(int order, const AblationArgs& a, hipStream_t s)
     case 6: return launch_l<6>(a, s);
     case 7: return launch_l<7>(a, s);
     case 8: return launch_l<8>(a, s);
+    case 9: return launch_l<9>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -856,6 +856,7 @@ hipError_t dispatch_order(int order, Args... args) {
     case 6: return Fn<6>::run(args...);
     case 7: return Fn<7>::run(args...);
     case 8: return Fn<8>::run(args...);
+    case 9: return Fn<9>::run(args...);
     default: return hipErrorInvalidValue;
   }
 }

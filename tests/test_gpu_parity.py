@@ -172,8 +172,12 @@ def test_apply_with_aca_compression_matches_oracle(name, n, nrhs, order, depth, 
     phi = host(plan.apply(dev(q)))
     ref = O.fmm_apply(pts, q, order, depth, kind, c, eps, compressor="aca").phi
     err = rel(phi, ref)
-    say("  rel err", err, "ranks", plan.stats()["rank"][:4])
+    st = plan.stats()
+    say("  rel err", err, "ranks", st["rank"][:4], "kernel", st["m2l_kernel"])
     assert err < tol
+    # ranks above the compressed kernel's limit (16 at order 7) run the full-rank kernel on the
+    # truncated operators, and the plan reports it
+    assert st["m2l_kernel"] == (1 if max(st["rank"]) <= (32 if order <= 6 else 16) else 0)
     if prec == "fp64" and order <= 5:
         svd = O.fmm_apply(pts, q, order, depth, kind, c, eps).phi
         assert rel(phi, svd) < 10 * eps
@@ -603,3 +607,51 @@ def test_overlapping_calls_on_one_plan_are_refused():
     sb.synchronize()
     assert np.array_equal(host(out_a), ref) and np.array_equal(host(out_a2), ref)
     assert np.array_equal(host(out_b), ref)
+
+
+# ------------------------------------------------------------------------------ order 9
+
+
+def test_order9_m2l_level_and_apply_match_oracle():
+    """Chebyshev order 9 (the highest of the paper's accuracy study): the full-rank FP64 M2L of
+    one level and a whole apply against the oracle; FP32 M2L at order 9 is refused."""
+    say("order 9")
+    order = 9
+    pts, q = cube(64, 1, 1)
+    tree = pk.Octree(dev(pts), 2)
+    plan = pk.Plan(tree, "inv_r", order, 0.0, "fp64")
+    assert plan.stats()["m2l_kernel"] == 0
+    rng = np.random.default_rng(109)
+    w = rng.standard_normal((8 ** 2, order ** 3, 1))
+    f_gpu = host(plan.m2l_level(2, dev(oracle_to_morton(w, 2))))
+    err = rel(morton_to_oracle(f_gpu, 2), O.m2l_level(w, 2, 1.0, order, "inv_r", 0.0, 0.0))
+    say("  level 2 rel err", err)
+    assert err < 1e-12
+    pts, q = cube(1500, 2, 110)
+    tree = pk.Octree(dev(pts), 2)
+    plan = pk.Plan(tree, "inv_sqrt_r2c2", order, 0.0, "fp64", 1e-3)
+    phi = host(plan.apply(dev(q)))
+    err = rel(phi, O.fmm_apply(pts, q, order, 2, "inv_sqrt_r2c2", 1e-3).phi)
+    say("  apply rel err", err)
+    assert err < 1e-12
+    with pytest.raises(pk.BBFMMError) as e:
+        pk.Plan(tree, "inv_r", order, 0.0, "fp32")
+    assert e.value.status == -4
+
+
+def test_order9_adaptive_apply_matches_oracle():
+    say("order 9 adaptive")
+    from oracle import adaptive_oracle as A
+    rng = np.random.default_rng(111)
+    n = 700
+    gs = rng.standard_normal((n // 2, 3))
+    pts = np.concatenate([0.5 + 0.4 * gs / np.linalg.norm(gs, axis=1, keepdims=True),
+                          0.5 + 0.05 * rng.standard_normal((n - n // 2, 3))])
+    q = rng.uniform(-1, 1, (n, 1))
+    tree = pk.Octree(dev(pts), -1, root_width=0.0, max_leaf_points=48)
+    plan = pk.Plan(tree, "inv_r", 9, 0.0)
+    phi = host(plan.apply(dev(q)))
+    ref, _ = A.fmm_apply(pts, q, 9, 48)
+    err = rel(phi, ref)
+    say("  rel err", err)
+    assert err < 1e-12

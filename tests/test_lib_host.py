@@ -190,3 +190,4 @@ def test_helmholtz_apply_validates_without_gpu():
     lib = pk.lib()
     assert lib.bbfmm_helmholtz_apply(None, None, C.c_void_p(8), 1, 0, C.c_void_p(16), None) == -1
     assert b"null" in lib.bbfmm_last_error()
+
