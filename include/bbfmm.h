@@ -223,6 +223,24 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
 bbfmm_status bbfmm_apply(bbfmm_plan* plan, const double* d_q, int32_t nrhs, double* d_phi,
                          void* stream);
 
+/* bbfmm_apply without allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). Same result as
+ * bbfmm_apply (the same kernels on the same plan), with the chain's work arrays (sorted densities
+ * and potentials, multipoles and locals of every level: 8 (2 n + 2 e) nrhs bytes, each array
+ * rounded up to 256 bytes, e = the plan's expansion values per right-hand side) placed in one
+ * fixed device array of the library, 64 MiB (8 Mi doubles) per GPU, held from the library's load
+ * until the process ends, instead of the plan's buffers. The call allocates nothing and frees
+ * nothing; the plan's operators and tables (from bbfmm_precompute_m2l) are used as they are.
+ * Every call on a GPU shares that GPU's array and leaves its contents behind (every pass
+ * overwrites what it reads later, so nothing needs clearing): calls that overlap on one GPU
+ * (two plans, two streams, two threads) race, and must be serialised by the caller. The plan's
+ * own forward locals are not updated, so bbfmm_eval_grad and bbfmm_debug_get_expansions need a
+ * bbfmm_apply after it. The caller's device must be the plan's. Blocked M2L variant only.
+ * Errors: as bbfmm_apply, plus EINVAL when the work arrays exceed the 64 MiB, EUNSUPPORTED for
+ * the SA variants or a device index above 63. */
+bbfmm_status bbfmm_apply_noalloc(bbfmm_plan* plan, const double* d_q, int32_t nrhs, double* d_phi,
+                                 void* stream);
+
 /* grad_q = A^T g through the transposed chain L2P^T, L2L^T, M2L^T (K_t^T = K_{-t}), M2M^T,
  * P2M^T and the transposed near field. Precondition, which every plan of this library meets by
  * construction: the kernel is symmetric, K(x, y) = K(y, x) (all bbfmm_kernel values are functions

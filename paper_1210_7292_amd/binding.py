@@ -68,6 +68,7 @@ SIGNATURES = [
     ("bbfmm_precompute_m2l", C.c_int, [_P, C.POINTER(PlanOpts), _P, C.POINTER(_P)]),
     ("bbfmm_apply", C.c_int, [_P, _P, C.c_int32, _P, _P]),
     ("bbfmm_apply_adjoint", C.c_int, [_P, _P, C.c_int32, _P, _P]),
+    ("bbfmm_apply_noalloc", C.c_int, [_P, _P, C.c_int32, _P, _P]),
     ("bbfmm_eval_grad", C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
     ("bbfmm_helmholtz_apply", C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
     ("bbfmm_plan_stats", C.c_int, [_P, C.POINTER(Stats)]),
@@ -185,6 +186,17 @@ def apply(plan, q, out=None, n: Optional[int] = None):
     out = torch.empty_like(q) if out is None else out
     _check(lib().bbfmm_apply(plan, qp, q.shape[1], _dev_ptr(out, torch.float64, q.shape[1], "out", rows=q.shape[0]),
                              _P(_stream(torch, q.device))))
+    return out
+
+
+def apply_noalloc(plan, q, out, n: Optional[int] = None):
+    """bbfmm_apply_noalloc: phi = A q into the caller's `out` with the library's fixed work array
+    (no device allocation by the library; `out` must be provided)."""
+    import torch
+    _check_shape(q, n, None, "q")
+    _check_shape(out, q.shape[0], q.shape[1], "out")
+    _check(lib().bbfmm_apply_noalloc(plan, _dev_ptr(q, torch.float64, None, "q"), q.shape[1],
+                                     _dev_ptr(out, torch.float64, q.shape[1], "out"), _P(_stream(torch, q.device))))
     return out
 
 
@@ -383,6 +395,9 @@ class Plan:
 
     def apply(self, q, out=None):
         return apply(self.handle, q, out, self.tree.n)
+
+    def apply_noalloc(self, q, out):
+        return apply_noalloc(self.handle, q, out, self.tree.n)
 
     def apply_adjoint(self, g, out=None):
         return apply_adjoint(self.handle, g, out, self.tree.n)

@@ -191,3 +191,9 @@ def test_helmholtz_apply_validates_without_gpu():
     assert lib.bbfmm_helmholtz_apply(None, None, C.c_void_p(8), 1, 0, C.c_void_p(16), None) == -1
     assert b"null" in lib.bbfmm_last_error()
 
+
+def test_noalloc_validates_without_gpu():
+    lib = pk.lib()
+    assert lib.bbfmm_apply_noalloc(None, C.c_void_p(8), 1, C.c_void_p(16), None) == -1
+    assert lib.bbfmm_apply_noalloc(C.c_void_p(8), C.c_void_p(8), 1, C.c_void_p(8), None) == -1   # aliasing
+    assert b"alias" in lib.bbfmm_last_error()
