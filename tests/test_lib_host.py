@@ -147,7 +147,7 @@ def test_validation_without_gpu():
     assert lib.bbfmm_apply(None, C.c_void_p(8), 1, C.c_void_p(16), None) == -1
     assert lib.bbfmm_apply_adjoint(None, C.c_void_p(8), 1, C.c_void_p(16), None) == -1
     assert lib.bbfmm_eval_grad(None, None, None, 1, 3, None, None) == -1
-    assert lib.bbfmm_host_symmetry(9, None, None, None, None) == -4
+    assert lib.bbfmm_host_symmetry(10, None, None, None, None) == -4
     t = (C.c_int32 * 3)(1, 0, 0)
     assert lib.bbfmm_host_symmetry(4, t, None, None, None) == -1      # near-field vector
     k = np.zeros(64 * 64)
