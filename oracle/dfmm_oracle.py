@@ -294,10 +294,14 @@ def fmm_apply(points: np.ndarray, q: np.ndarray, order: int, depth: int, k: floa
 
     x1 = B.cheb_roots(order)
     a_idx = B.multi_indices(order)
-    # ---- P2M at the leaves (Eq. m2m_dfmm), one expansion per kept cone
     W: Dict[int, np.ndarray] = {}
     L: Dict[int, np.ndarray] = {}
     d = depth
+    phi = np.zeros(points.shape[0], dtype=np.complex128)
+    if d < top:
+        # no level with a far field: the near field below is the whole sum
+        return _near(points, q, tree, lists, kern, phi, DFMMResult(phi, lists, cones, grid, far_cone, W, L))
+    # ---- P2M at the leaves (Eq. m2m_dfmm), one expansion per kept cone
     wl = width / (1 << d)
     leaf_cells = lists.cells[d]
     W[d] = np.zeros((leaf_cells.size, cones[d].size, nn), dtype=np.complex128)
@@ -373,16 +377,19 @@ def fmm_apply(points: np.ndarray, q: np.ndarray, order: int, depth: int, k: floa
             val = np.einsum("naA,nA->na", smat, par[chp])
             L[lev + 1][:, sc, :] += np.exp(1j * k * (cnodes @ u)) * val
     # ---- L2P at the leaves (Eq. l2l_dfmm), summed over the kept cones
-    phi = np.zeros(points.shape[0], dtype=np.complex128)
     lc = centers(d, leaf_cells)
     for s, c in enumerate(cones[d]):
         u = dirs[d][c]
         nodes = lc[:, None, :] + 0.5 * wl * x1[a_idx][None, :, :]
         f = np.exp(-1j * k * (nodes @ u)) * L[d][:, s, :]
         phi += np.exp(1j * k * (points @ u)) * np.einsum("nb,nb->n", basis, f[pos])
-    # ---- near field: non-admissible leaf pairs (own leaf included), j != i
+    return _near(points, q, tree, lists, kern, phi, DFMMResult(phi, lists, cones, grid, far_cone, W, L))
+
+
+def _near(points, q, tree, lists, kern, phi, result):
+    """Adds the near field (non-admissible leaf pairs, own leaf included, j != i) into phi."""
     order_ = np.argsort(tree.leaf, kind="stable")
-    counts = np.bincount(tree.leaf, minlength=8 ** d)
+    counts = np.bincount(tree.leaf, minlength=8 ** tree.depth)
     starts = np.concatenate([[0], np.cumsum(counts)])
     nx, ny = lists.near
     for X, Y in zip(nx, ny):
@@ -391,4 +398,4 @@ def fmm_apply(points: np.ndarray, q: np.ndarray, order: int, depth: int, k: floa
         kmat = kern(points[ti][:, None, :], points[sj][None, :, :])
         kmat[ti[:, None] == sj[None, :]] = 0.0
         phi[ti] += kmat @ q[sj]
-    return DFMMResult(phi, lists, cones, grid, far_cone, W, L)
+    return result

@@ -93,6 +93,17 @@ def test_dephased_polynomial_kernel_is_exact_with_one_direction():
     assert np.linalg.norm(approx - ref) / np.linalg.norm(ref) > 1e-8
 
 
+def test_shallow_tree_is_the_direct_sum():
+    """Depth 0 and 1: no level has a far field, everything is near field."""
+    pts, rng = sphere(300, 5)
+    q = rng.uniform(-1, 1, 300) + 1j * rng.uniform(-1, 1, 300)
+    ref = D.brute_force(pts, q, 10.0)[:, 0]
+    for depth in (0, 1):
+        res = D.fmm_apply(pts, q, 4, depth, 10.0)
+        assert not res.lists.far
+        assert np.linalg.norm(res.phi - ref) / np.linalg.norm(ref) < 1e-14
+
+
 def test_low_frequency_reduces_to_the_bbfmm_oracle():
     """k w < 1 at every M2L level: one cone with u = 0 everywhere and the bbFMM lists, so the
     dFMM equals the bbFMM oracle's cos(kr)/r + i sin(kr)/r applies (Sec. 2.1.2: the two schemes
