@@ -277,6 +277,85 @@ def run_helmholtz(args):
     print(json.dumps(line))
 
 
+def run_dfmm(args):
+    """Directional FMM of e^{ikr}/r (high-frequency regime) on points on a sphere: the paper's
+    sphere set-up (random points on a sphere surface in a bounding cube 64 wavelengths/2pi wide,
+    k = 1, 6 levels), here N points on a sphere of radius 0.45 in the unit cube with k = 64
+    (the same k w per level), order `--dfmm-order`. Prints one JSON line: points/s of one complex
+    apply, M2L GFLOP/s (8 l^6 flops per far pair) against the FP64 MFMA peak, the per-level list
+    sizes (|T|, |T_sym|, cones) and the error against the direct sum."""
+    import numpy as np
+    import torch
+
+    import paper_1210_7292_amd as pk
+
+    dev = torch.device("cuda:0")
+    n, k, order, depth = args.dfmm_n, float(args.dfmm), args.dfmm_order, args.dfmm_depth
+    rng = np.random.default_rng(1210729200 + 40)
+    g = rng.standard_normal((n, 3))
+    pts_h = 0.5 + 0.45 * g / np.linalg.norm(g, axis=1, keepdims=True)
+    q_h = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
+    tg = rng.choice(n, 256, replace=False)
+    pts = torch.from_numpy(pts_h).to(dev)
+    q = torch.from_numpy(q_h).to(dev)
+    tree = pk.Octree(pts, depth)
+    t0 = time.perf_counter()
+    plan = pk.DFMMPlan(tree, k, order)
+    pre_s = time.perf_counter() - t0
+    st = plan.stats()
+    log(f"[bench] dfmm precompute {pre_s:.2f} s; hf {st['hf'][:depth + 1]}, cones {st['cones'][:depth + 1]}, "
+        f"|T| {st['n_t'][:depth + 1]}, |T_sym| {st['n_tsym'][:depth + 1]}, far pairs {st['far_pairs'][:depth + 1]}")
+    out = torch.empty(n, dtype=torch.complex128, device=dev)
+    for _ in range(args.warmup):
+        plan.apply(q, out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.apply(q, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    plan.set_timing(True)
+    plan.apply(q, out)
+    m2l_ms, calls = plan.m2l_time()
+    plan.set_timing(False)
+    m2l_ms /= max(calls, 1)
+    achieved = st["m2l_flops"] / (m2l_ms * 1e-3) / 1e12
+    # direct complex sum at seeded targets, FP64 on the device (measurement only)
+    x = pts[torch.from_numpy(tg).to(dev)]
+    direct = torch.zeros(tg.size, dtype=torch.complex128, device=dev)
+    for s0 in range(0, n, 1 << 16):
+        y = pts[s0:s0 + (1 << 16)]
+        r = ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1).sqrt()
+        kr = torch.where(r > 0, torch.exp(1j * k * r) / torch.where(r > 0, r, torch.ones_like(r)),
+                         torch.zeros_like(r, dtype=torch.complex128))
+        direct += kr @ q[s0:s0 + (1 << 16)]
+    got = out[torch.from_numpy(tg).to(dev)]
+    err = float(torch.linalg.norm(got - direct) / torch.linalg.norm(direct))
+    line = {
+        "metric": "dFMM points/sec of one complex apply (e^{ikr}/r, directional expansions), with M2L "
+                  "TFLOP/s vs FP64 MFMA peak and rel. L2 error",
+        "value": n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"sphere{n}_helmholtz_k{k:g}_p{order}_d{depth}", "n_points": n,
+                   "kernel": "e^{ikr}/r", "wavenumber": k, "order": order, "depth": depth,
+                   "geometry": "random points on a sphere of radius 0.45 (unit cube root)"},
+        "m2l_ms": m2l_ms, "m2l_gflops": achieved * 1e3,
+        "roofline": {"bound": "mfma", "kernel": "dfmm_m2l", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": achieved / 78.6, "traffic": None},
+        "levels": {"hf": st["hf"][:depth + 1], "cone_grid": st["cone_grid"][:depth + 1],
+                   "cones": st["cones"][:depth + 1], "cells": st["cells"][:depth + 1],
+                   "far_pairs": st["far_pairs"][:depth + 1], "T": st["n_t"][:depth + 1],
+                   "T_sym": st["n_tsym"][:depth + 1]},
+        "rel_l2_err_vs_direct": err, "error_sample": "256 seeded targets",
+        "precompute_s": pre_s,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +380,11 @@ def main():
     ap.add_argument("--helmholtz", type=float, default=None, metavar="K",
                     help="instead: the complex Helmholtz apply e^{ikr}/r with wavenumber K on the "
                          "workload's points")
+    ap.add_argument("--dfmm", type=float, default=None, metavar="K",
+                    help="instead: the directional FMM of e^{ikr}/r with wavenumber K on points on a sphere")
+    ap.add_argument("--dfmm-n", type=int, default=168_931, help="dFMM points (default: the paper's sphere count)")
+    ap.add_argument("--dfmm-order", type=int, default=5)
+    ap.add_argument("--dfmm-depth", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -325,6 +409,11 @@ def main():
             args.warmup = 1 if big else 3
     if args.helmholtz is not None and args.gpus == 1:
         run_helmholtz(args)
+        return
+    if args.dfmm is not None and args.gpus == 1:
+        if args.steps is None or args.config == 3:
+            args.steps, args.warmup = 5, 1
+        run_dfmm(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "

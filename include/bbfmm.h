@@ -296,6 +296,69 @@ const char* bbfmm_last_error(void);
 const char* bbfmm_version(void);
 
 /* ---------------------------------------------------------------------------------------
+ * Directional FMM (dFMM) for the Helmholtz kernel e^{ikr}/r (Sec. 2.1.2, Eqs. helmkerneldir,
+ * m2m_dfmm, m2l_dfmm, l2l_dfmm; Alg. near_far_field) on a uniform octree, FP64 complex, one
+ * density vector. Readings (the paper defers the dFMM's details to the cited dFMM paper):
+ *  - level l (cell width w) is high-frequency (directional) when k w >= 1, else low-frequency;
+ *  - same-level cells with t = (c_x - c_y) / w are admissible when ||t||_inf >= 2 and, at a
+ *    high-frequency level, ||t||_2 >= k w (|c_x - c_y| >= k w^2); the far and near lists are
+ *    Alg. near_far_field run level by level over the occupied cells;
+ *  - the cones of a high-frequency level are the squares of an m x m grid on each face of the
+ *    cube (m the smallest power of two >= k w, so the grids nest across levels), the direction u
+ *    of a cone is its normalised centre, and a far pair belongs to the cone hit by c_x - c_y; a
+ *    low-frequency level has one plain expansion (u = 0);
+ *  - M2M / L2L treat the child's equivalent sources as particles of the parent's directional
+ *    expansion, taking (giving) the child's expansion of the child-level cone containing the
+ *    parent cone;
+ *  - the M2L uses K(xbar_a, ybar_b) itself, so K_t = P_t K_p(t) P_t^T with the symmetries of
+ *    Sec. 4.2.1 for every t of the (larger) high-frequency lists; the pairs of a level are
+ *    grouped by representative p(t) = sorted |t| (Table size_T_all's |T_sym|) and each group is
+ *    one complex FP64 MFMA product, its columns added into the targets' locals with atomics
+ *    (results agree with any other summation order to rounding, not bitwise).
+ * The kernel at r = 0 between distinct points contributes ik (the limit of its smooth part);
+ * i = j is excluded.
+ * --------------------------------------------------------------------------------------- */
+typedef struct bbfmm_dfmm bbfmm_dfmm;
+
+typedef struct {
+  int64_t n_points;
+  int32_t depth, order;
+  double k;
+  int32_t hf[9];          /* per level: 1 high-frequency (directional), 0 low-frequency */
+  int32_t cone_grid[9];   /* m per level (0: one plain expansion) */
+  int32_t cones[9];       /* cones kept per level (used by its far pairs, or by the level above) */
+  int32_t cells[9];       /* occupied cells per level */
+  int64_t far_pairs[9];   /* far (M2L) pairs of occupied cells per level */
+  int32_t n_t[9];         /* distinct transfer vectors |T| per level */
+  int32_t n_tsym[9];      /* distinct representatives |T_sym| per level */
+  int64_t near_pairs;     /* near-field leaf pairs (own leaf included) */
+  double m2l_flops;       /* algorithmic: 8 l^6 per far pair (complex l^3 x l^3 matrix-vector) */
+  double precompute_seconds;
+  int64_t device_bytes;
+} bbfmm_dfmm_stats;
+
+/* Builds the lists, cones, symmetry groups and the complex operators K_p of every level's
+ * representatives on the host (FP64) and uploads them. `tree` (uniform) is borrowed. k > 0;
+ * order in [2, 7] (the paper's dFMM study runs to 7).
+ * Errors: EINVAL (null, k not finite or <= 0), EUNSUPPORTED (adaptive tree, order outside
+ * [2, 7], more than 2^31 expansion rows or pairs), ENOMEM, EHIP. */
+bbfmm_status bbfmm_dfmm_precompute(const bbfmm_tree* tree, double k, int32_t order, void* stream,
+                                   bbfmm_dfmm** out);
+
+/* phi_i = sum_{j != i} e^{ik|x_i - x_j|} / |x_i - x_j| q_j by the dFMM. d_q, d_phi: n complex FP64
+ * values (interleaved re, im), caller's point order; d_phi overwritten. One call at a time per
+ * plan (ESTATE for a call on another stream while the last one runs).
+ * Errors: EINVAL (null, d_q == d_phi), ESTATE, EHIP. */
+bbfmm_status bbfmm_dfmm_apply(bbfmm_dfmm* plan, const double* d_q, double* d_phi, void* stream);
+bbfmm_status bbfmm_dfmm_stats_of(const bbfmm_dfmm* plan, bbfmm_dfmm_stats* out);
+/* M2L timing: while enabled, each apply records HIP events around its M2L launch on its stream;
+ * bbfmm_dfmm_m2l_time waits for them and returns the summed milliseconds and the number of
+ * applies since timing was (re-)enabled. */
+bbfmm_status bbfmm_dfmm_set_timing(bbfmm_dfmm* plan, int32_t enable);
+bbfmm_status bbfmm_dfmm_m2l_time(bbfmm_dfmm* plan, double* out_ms, int32_t* out_calls);
+void bbfmm_dfmm_destroy(bbfmm_dfmm* plan);
+
+/* ---------------------------------------------------------------------------------------
  * Inspection entry points (testing and measurement). Expansion arrays are in the library's
  * layout: cells of a level in Morton order (x bit lowest), each cell l^3 interpolation points in
  * the order m(a) = a1 + l a2 + l^2 a3 of Sec. 3.1, each point nrhs values.

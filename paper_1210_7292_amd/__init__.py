@@ -9,6 +9,7 @@ from __future__ import annotations
 
 from .binding import (  # noqa: F401
     BBFMMError,
+    DFMMPlan,
     HelmholtzPlan,
     COMPRESSORS,
     KERNELS,

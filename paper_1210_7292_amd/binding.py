@@ -46,6 +46,14 @@ class Stats(C.Structure):
                 ("m2l_kernel", C.c_int32)]
 
 
+class DfmmStats(C.Structure):
+    _fields_ = [("n_points", C.c_int64), ("depth", C.c_int32), ("order", C.c_int32), ("k", C.c_double),
+                ("hf", C.c_int32 * 9), ("cone_grid", C.c_int32 * 9), ("cones", C.c_int32 * 9),
+                ("cells", C.c_int32 * 9), ("far_pairs", C.c_int64 * 9), ("n_t", C.c_int32 * 9),
+                ("n_tsym", C.c_int32 * 9), ("near_pairs", C.c_int64), ("m2l_flops", C.c_double),
+                ("precompute_seconds", C.c_double), ("device_bytes", C.c_int64)]
+
+
 class AdaptiveInfo(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n_nodes", C.c_int32), ("n_leaves", C.c_int32),
                 ("n_u", C.c_int64), ("n_w", C.c_int64), ("n_x_nodes", C.c_int64), ("n_x", C.c_int64),
@@ -91,6 +99,12 @@ SIGNATURES = [
     ("bbfmm_adaptive_info_of", C.c_int, [_P, C.POINTER(AdaptiveInfo)]),
     ("bbfmm_adaptive_array", C.c_int, [_P, C.c_int32, _P]),
     ("bbfmm_host_adaptive_tree", C.c_int, [_P, C.c_int64, C.c_int32, _P, C.c_double, C.POINTER(_P)]),
+    ("bbfmm_dfmm_precompute", C.c_int, [_P, C.c_double, C.c_int32, _P, C.POINTER(_P)]),
+    ("bbfmm_dfmm_apply", C.c_int, [_P, _P, _P, _P]),
+    ("bbfmm_dfmm_stats_of", C.c_int, [_P, C.POINTER(DfmmStats)]),
+    ("bbfmm_dfmm_set_timing", C.c_int, [_P, C.c_int32]),
+    ("bbfmm_dfmm_m2l_time", C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    ("bbfmm_dfmm_destroy", None, [_P]),
 ]
 
 
@@ -483,3 +497,62 @@ def fmm_apply(points, q, depth: int, order: int, kernel: str = "inv_r", svd_eps:
     if q.dim() == 1:
         return plan.apply(q.reshape(-1, 1).contiguous()).reshape(-1)
     return plan.apply(q)
+
+
+class DFMMPlan:
+    """A bbfmm_dfmm plan: the directional FMM of e^{ikr}/r on a uniform tree (one complex density
+    vector). apply(q) takes q of shape (n,) or (n, 1), complex128 or float64, and returns complex128."""
+
+    def __init__(self, tree: Octree, k: float, order: int = 4):
+        import torch
+        if tree.adaptive:
+            raise BBFMMError(-4, "the dFMM runs on uniform trees")
+        self.tree = tree
+        self.k = float(k)
+        self.order = int(order)
+        h = C.c_void_p()
+        _check(lib().bbfmm_dfmm_precompute(tree.handle, self.k, self.order, _P(_stream(torch, tree.device)),
+                                           C.byref(h)))
+        self.handle = h
+
+    def apply(self, q, out=None):
+        import torch
+        n = self.tree.n
+        if q.dim() == 2:
+            _check_shape(q, n, 1, "q")
+            q = q.reshape(n)
+        _check_shape(q, n, None, "q", dims=1)
+        if not torch.is_complex(q):
+            q = q.to(torch.complex128)
+        q = q.contiguous()
+        qp = _dev_ptr(q, torch.complex128, None, "q")
+        if out is None:
+            out = torch.empty(n, dtype=torch.complex128, device=q.device)
+        _check_shape(out, n, None, "out", dims=1)
+        _check(lib().bbfmm_dfmm_apply(self.handle, qp, _dev_ptr(out, torch.complex128, None, "out"),
+                                      _P(_stream(torch, q.device))))
+        return out
+
+    def stats(self) -> dict:
+        st = DfmmStats()
+        _check(lib().bbfmm_dfmm_stats_of(self.handle, C.byref(st)))
+        d = {}
+        for k, _ in DfmmStats._fields_:
+            v = getattr(st, k)
+            d[k] = list(v) if isinstance(v, C.Array) else v
+        return d
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().bbfmm_dfmm_set_timing(self.handle, 1 if enable else 0))
+
+    def m2l_time(self):
+        """(summed M2L milliseconds, applies) since set_timing(True)."""
+        ms, calls = C.c_double(), C.c_int32()
+        _check(lib().bbfmm_dfmm_m2l_time(self.handle, C.byref(ms), C.byref(calls)))
+        return ms.value, calls.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.bbfmm_dfmm_destroy(h)
+            self.handle = None

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libbbfmm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HIP_SOURCES = ["tree.hip", "passes.hip", "m2l.hip", "api.hip", "adaptive_tree.hip", "adaptive_passes.hip", "m2l_ablation.hip", "m2l_sa.hip", "complex.hip", "noalloc.hip"]
+HIP_SOURCES = ["tree.hip", "passes.hip", "m2l.hip", "api.hip", "adaptive_tree.hip", "adaptive_passes.hip", "m2l_ablation.hip", "m2l_sa.hip", "complex.hip", "noalloc.hip", "dfmm.hip"]
 CXX_SOURCES = ["host_math.cpp", "adaptive_host.cpp"]
 # Packed FP32 VALU instructions are disabled for all device code.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

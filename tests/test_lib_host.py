@@ -197,3 +197,11 @@ def test_noalloc_validates_without_gpu():
     assert lib.bbfmm_apply_noalloc(None, C.c_void_p(8), 1, C.c_void_p(16), None) == -1
     assert lib.bbfmm_apply_noalloc(C.c_void_p(8), C.c_void_p(8), 1, C.c_void_p(8), None) == -1   # aliasing
     assert b"alias" in lib.bbfmm_last_error()
+
+
+def test_dfmm_validates_without_gpu():
+    lib = pk.lib()
+    out = C.c_void_p()
+    assert lib.bbfmm_dfmm_precompute(None, 1.0, 4, None, C.byref(out)) == -1
+    assert lib.bbfmm_dfmm_apply(None, C.c_void_p(8), C.c_void_p(16), None) == -1
+    assert lib.bbfmm_dfmm_stats_of(None, None) == -1
