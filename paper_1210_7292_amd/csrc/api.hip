@@ -176,6 +176,7 @@ M2LArgs m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double* F, int 
   a.nlev = k;
   a.ops_hi = p->ops_hi; a.ops_lo = p->ops_lo;
   a.op_off = p->d_op_off; a.op_rank = p->d_op_rank;
+  a.max_rank = p->lowrank ? *std::max_element(p->ranks.begin(), p->ranks.end()) : 0;
   a.tab = p->d_tab; a.grp = p->d_grp; a.sig = p->d_sig; a.siginv = p->d_siginv;
   a.zeros = p->d_zeros;
   // the split of the last round needs the whole-apply launch (all levels)
@@ -245,6 +246,7 @@ M2LArgs adaptive_m2l_args(const bbfmm_plan* p, int nrhs, const double* W, double
   a.cols = m2l_block_cols(p->lowrank, p->order, p->prec);
   a.ops_hi = p->ops_hi; a.ops_lo = p->ops_lo;
   a.op_off = p->d_op_off; a.op_rank = p->d_op_rank;
+  a.max_rank = p->lowrank ? *std::max_element(p->ranks.begin(), p->ranks.end()) : 0;
   a.tab = p->d_tab; a.grp = p->d_grp; a.sig = p->d_sig; a.siginv = p->d_siginv;
   a.zeros = p->d_zeros;
   a.segs = p->d_segs;

@@ -327,6 +327,13 @@ __global__ __launch_bounds__(256 * RS) void dfmm_m2l_kernel(DM2L a) {
     acci[m] = f64x4{0, 0, 0, 0};
   }
   for (int ch = 0; ch < NCH; ++ch) {
+    // this chunk's source values, in flight while the operator chunk is staged
+    double2 bv[KS];
+#pragma unroll
+    for (int s2 = 0; s2 < KS; ++s2) {
+      const int k = ch * KC + 4 * s2 + kq;
+      bv[s2] = (valid && k < NN) ? src[si[k]] : make_double2(0.0, 0.0);
+    }
     __syncthreads();
     for (int x = tid; x < (NN + 1) * KC; x += NT) {
       const int row = x / KC, cc = x - row * KC, k = ch * KC + cc;
@@ -338,19 +345,26 @@ __global__ __launch_bounds__(256 * RS) void dfmm_m2l_kernel(DM2L a) {
     __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < KS; ++s2) {
-      const int k = ch * KC + 4 * s2 + kq;
-      double2 b = make_double2(0.0, 0.0);
-      if (valid && k < NN) b = src[si[k]];
+      const double2 b = bv[s2];
       const double nbi = -b.y;
+      double ar[MBW], ai[MBW];
 #pragma unroll
       for (int m = 0; m < MBW; ++m) {
         const int row = min(16 * (mb0 + m) + j, NN);
-        const double ar = kre[row * LDK + 4 * s2 + kq];
-        const double ai = kim[row * LDK + 4 * s2 + kq];
-        accr[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.x, accr[m], 0, 0, 0);
-        accr[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, nbi, accr[m], 0, 0, 0);
-        acci[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.y, acci[m], 0, 0, 0);
-        acci[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.x, acci[m], 0, 0, 0);
+        ar[m] = kre[row * LDK + 4 * s2 + kq];
+        ai[m] = kim[row * LDK + 4 * s2 + kq];
+      }
+      // the two products into each accumulator are issued 2 MBW instructions apart, so that
+      // consecutive MFMAs never depend on each other
+#pragma unroll
+      for (int m = 0; m < MBW; ++m) {
+        accr[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[m], b.x, accr[m], 0, 0, 0);
+        acci[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[m], b.y, acci[m], 0, 0, 0);
+      }
+#pragma unroll
+      for (int m = 0; m < MBW; ++m) {
+        accr[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[m], nbi, accr[m], 0, 0, 0);
+        acci[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[m], b.x, acci[m], 0, 0, 0);
       }
     }
   }

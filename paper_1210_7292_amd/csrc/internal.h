@@ -85,6 +85,7 @@ struct M2LArgs {
   const void* ops_lo;          // low parts (split precision)
   const long long* op_off;     // [set][16][2]: offset of K (or U) and V, in elements
   const int* op_rank;          // [set][16]
+  int max_rank;                // largest rank of the compressed operators (0 for full rank)
   const int* tab;              // [8][189]
   const int* grp;              // [8][17]
   const short* sig;            // [48][NP]; entries >= l^3 map to l^3

@@ -577,7 +577,9 @@ struct Lowrank {
   }
 };
 
-template <int L, int RMAX, int PREC, int W8, bool ONE_RHS, bool AD>
+// SLICED: some representative's rank exceeds RMAX, so factors are staged and applied in slices
+// of RMAX ranks; otherwise each representative's factors are staged once, whole.
+template <int L, int RMAX, int PREC, int W8, bool ONE_RHS, bool AD, bool SLICED>
 __global__ __launch_bounds__(64 * W8, 2) void m2l_lowrank_kernel(M2LArgs a) {
   using K = Lowrank<L, RMAX, PREC, W8, ONE_RHS>;
   using T = typename K::T;
@@ -632,6 +634,7 @@ __global__ __launch_bounds__(64 * W8, 2) void m2l_lowrank_kernel(M2LArgs a) {
   // transfer vectors of this workgroup: all, or one part of a split tile
   const int e_begin = bp.part < 0 ? 0 : bp.part * kFarPerOctant / a.tsplit;
   const int e_end = bp.part < 0 ? kFarPerOctant : (bp.part + 1) * kFarPerOctant / a.tsplit;
+  if constexpr (!SLICED) {
   double w[CH][4];
   int cur_p = -1, r = 0, zb = 0;
   gdouble* src = source(e_begin, tab[e_begin]);
@@ -719,6 +722,107 @@ __global__ __launch_bounds__(64 * W8, 2) void m2l_lowrank_kernel(M2LArgs a) {
       }
     }
   }
+  } else {
+  double w[CH][4];
+  // The transfer vectors of one representative are consecutive in the table. Its factors are
+  // staged in slices of RMAX ranks (one slice when r <= RMAX): U_p V_p^T = sum over slices of
+  // U_s V_s^T, so a slice is applied to every transfer vector of the representative as a
+  // factor pair of rank <= RMAX, and ranks above the LDS capacity of one slice cost one more
+  // read of the multipoles per slice rather than a different kernel.
+  for (int g0 = e_begin; g0 < e_end;) {
+    const int p = (tab[g0] >> 9) & 15;
+    int g1 = g0 + 1;
+    while (g1 < e_end && ((tab[g1] >> 9) & 15) == p) ++g1;
+    const int r = srank[p];
+    for (int cs = 0; cs < r; cs += RMAX) {
+      const int rs = min(RMAX, r - cs);          // ranks of this slice
+      const int zb = (rs + 15) / 16;
+      __syncthreads();
+      {
+      const int sw = 16 * zb;                    // staged columns
+      const int rv = (r + 15) / 16 * 16, ru = (r + 3) / 4 * 4;   // global factor row strides
+      const long long offu = soff[2 * p];
+      const long long offv = soff[2 * p + 1];
+      const T* Ug = static_cast<const T*>(a.ops_hi) + offu;   // [NN][ru]
+      const T* Vg = static_cast<const T*>(a.ops_hi) + offv;   // [NN][rv]
+      const T* Ul = SPLIT ? static_cast<const T*>(a.ops_lo) + offu : nullptr;
+      const T* Vl = SPLIT ? static_cast<const T*>(a.ops_lo) + offv : nullptr;
+      // factor loads in batches of SB issued back to back, then their LDS stores
+      constexpr int SB = 8;
+      const int tot = (NN + 1) * sw;
+#pragma unroll 1
+      for (int x0 = tid; x0 < tot; x0 += SB * NT) {
+        T tv[SB], tu[SB], tvl[SPLIT ? SB : 1], tul[SPLIT ? SB : 1];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          const int x = x0 + u * NT;
+          const int row = x / sw, cc = cs + (x - row * sw);
+          const bool inv = x < tot && row < NN && cc < rv, inu = inv && cc < ru;
+          const long long gv = inv ? (long long)row * rv + cc : 0, gu = inu ? (long long)row * ru + cc : 0;
+          tv[u] = Vg[gv];
+          tu[u] = Ug[gu];
+          if (SPLIT) {
+            tvl[u] = Vl[gv];
+            tul[u] = Ul[gu];
+          }
+        }
+        // entries outside the factors (the zero row l^3, columns beyond the rank) are zeroed
+        // here rather than at the loads, so the loads of a batch are all in flight together
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          const int x = x0 + u * NT;
+          if (x < tot) {
+            const int row = x / sw, lc = x - row * sw, cc = cs + lc;
+            const bool inv = row < NN && cc < rv, inu = inv && cc < ru;
+            vhi[row * LD + lc] = inv ? tv[u] : T(0);
+            uhi[row * LD + lc] = inu ? tu[u] : T(0);
+            if (SPLIT) {
+              vlo[row * LD + lc] = inv ? tvl[u] : T(0);
+              ulo[row * LD + lc] = inu ? tul[u] : T(0);
+            }
+          }
+        }
+      }
+      }
+      __syncthreads();
+      gdouble* src = source(g0, tab[g0]);
+      if (PREFETCH) K::load(src, nrhs, kq, 0, w);
+      for (int e = g0; e < g1; ++e) {
+        const int ent = tab[e];
+        const short* sg = sgbase + (ent >> 13) * NP;
+        // ---- GEMM 1 ----
+        V z[2] = {V{0, 0, 0, 0}, V{0, 0, 0, 0}};
+#pragma unroll
+        for (int c0 = 0; c0 < K16; c0 += CH) {
+          if (!PREFETCH || c0 > 0) K::load(src, nrhs, kq, c0, w);
+          if (zb == 1) K::template gemm1<1>(vhi, vlo, sg, j, kq, c0, w, z);
+          else K::template gemm1<RMAX / 16>(vhi, vlo, sg, j, kq, c0, w, z);
+        }
+        // ---- next transfer vector's multipoles, in flight during GEMM 2 ----
+        if (e + 1 < g1) {
+          src = source(e + 1, tab[e + 1]);
+          if (PREFETCH) K::load(src, nrhs, kq, 0, w);
+        }
+        // ---- GEMM 2 ----
+        int urow[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) urow[mb] = sg[16 * mb + j] * LD;
+        if (zb == 1) K::template gemm2<1>(uhi, ulo, urow, kq, rs, z, acc);
+        else K::template gemm2<RMAX / 16>(uhi, ulo, urow, kq, rs, z, acc);
+        // FP32 modes: each product is accumulated in FP32 and then added into FP64
+        if (PREC != 0) {
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[mb][v] += (double)acc[mb][v];
+            acc[mb] = V{0, 0, 0, 0};
+          }
+        }
+      }
+    }
+    g0 = g1;
+  }
+  }
   if (bp.part < 0) {
     store_tile<L, MB, PREC, V>(a, bp, col, kq, acc, acc64, PREC != 0);
     return;
@@ -768,11 +872,13 @@ template <int L, int PREC> constexpr int full_kc() {
 // waves per column group of the full-rank kernel: row blocks split so that the accumulators of
 // the largest orders fit the register file with two waves per SIMD
 template <int L> constexpr int full_rs() { return L >= 7 ? 2 : 1; }
+// ranks of one LDS slice of the compressed kernel's factors
 template <int L> constexpr int rank_limit() { return L <= 6 ? 32 : 16; }
 // Order 9 runs the full-rank kernel in FP64 only: two factors of rank 16 would not fit in LDS
 // (2 x 730 x 17 doubles), and the FP32 accumulators with their FP64 sums would not fit the
 // register file beside the 23 row blocks per wave.
 constexpr int kMaxLowrankOrder = 8;
+constexpr int kMaxLowrankRank = 128;
 // Waves per compressed-kernel workgroup: 4 (64 columns) when the workgroup's LDS lets two of
 // them share a CU, so that one computes while the other restages factors at a representative
 // change; 8 otherwise. Mirrors the kernel's LDS arrays.
@@ -832,8 +938,11 @@ hipError_t launch_ld(bool lowrank, M2LArgs a, hipStream_t s) {
   if (lowrank) {
     if constexpr (L >= 3 && L <= kMaxLowrankOrder) {
       constexpr int W8 = lowrank_waves(L, PREC);
-      auto kern1 = m2l_lowrank_kernel<L, rank_limit<L>(), PREC, W8, true, AD>;
-      auto kernn = m2l_lowrank_kernel<L, rank_limit<L>(), PREC, W8, false, AD>;
+      const bool sliced = a.max_rank > rank_limit<L>();
+      auto kern1 = sliced ? m2l_lowrank_kernel<L, rank_limit<L>(), PREC, W8, true, AD, true>
+                          : m2l_lowrank_kernel<L, rank_limit<L>(), PREC, W8, true, AD, false>;
+      auto kernn = sliced ? m2l_lowrank_kernel<L, rank_limit<L>(), PREC, W8, false, AD, true>
+                          : m2l_lowrank_kernel<L, rank_limit<L>(), PREC, W8, false, AD, false>;
       unsigned grid;
       if (!AD) {
         tile(a, 16 * W8);
@@ -891,7 +1000,9 @@ hipError_t launch_prec(int order, bool lowrank, const M2LArgs& a, hipStream_t s)
 
 int m2l_ia_rank_limit(int order) {
   if (order < 3 || order > kMaxLowrankOrder) return 0;
-  return order <= 6 ? 32 : 16;
+  // factors are applied in slices of 32 (orders <= 6) or 16 ranks; beyond half of l^3 the two
+  // products cost more than the full operator
+  return std::min(kMaxLowrankRank, order * order * order / 2);
 }
 
 int m2l_block_cols(bool lowrank, int order, int prec) {
@@ -927,9 +1038,16 @@ double m2l_issued_flops_per_t(int order, bool lowrank, int rank) {
     const int nch = (nn + kc - 1) / kc;
     return (double)(np / 16) * (nch * kc / 4) * mfma * 4;
   }
-  const int zb = (rank + 15) / 16;
-  const int steps2 = (rank + 3) / 4;
-  return ((double)zb * (np / 4) + (double)(np / 16) * steps2) * mfma * 4;
+  // per rank slice (32 ranks below order 7, 16 from order 7)
+  const int sw = order <= 6 ? 32 : 16;
+  double f = 0.0;
+  for (int cs = 0; cs < rank; cs += sw) {
+    const int rs = std::min(sw, rank - cs);
+    const int zb = (rs + 15) / 16;
+    const int steps2 = (rs + 3) / 4;
+    f += ((double)zb * (np / 4) + (double)(np / 16) * steps2) * mfma * 4;
+  }
+  return f;
 }
 
 }  // namespace bbfmm

@@ -175,9 +175,9 @@ def test_apply_with_aca_compression_matches_oracle(name, n, nrhs, order, depth, 
     st = plan.stats()
     say("  rel err", err, "ranks", st["rank"][:4], "kernel", st["m2l_kernel"])
     assert err < tol
-    # ranks above the compressed kernel's limit (16 at order 7) run the full-rank kernel on the
-    # truncated operators, and the plan reports it
-    assert st["m2l_kernel"] == (1 if max(st["rank"]) <= (32 if order <= 6 else 16) else 0)
+    # the compressed kernel runs any rank up to half of l^3 (beyond, the full-rank kernel on the
+    # truncated operators is cheaper), and the plan reports which one runs
+    assert st["m2l_kernel"] == (1 if max(st["rank"]) <= min(128, order ** 3 // 2) else 0)
     if prec == "fp64" and order <= 5:
         svd = O.fmm_apply(pts, q, order, depth, kind, c, eps).phi
         assert rel(phi, svd) < 10 * eps
@@ -655,3 +655,58 @@ def test_order9_adaptive_apply_matches_oracle():
     err = rel(phi, ref)
     say("  rel err", err)
     assert err < 1e-12
+
+
+# ------------------------------------------------------------------------------ IAblk at high accuracy
+
+
+@pytest.mark.parametrize("order,eps,compressor,level", [(6, 1e-6, "svd", 3), (7, 1e-7, "svd", 2),
+                                                        (8, 1e-8, "aca", 2)])
+def test_compressed_m2l_at_high_accuracy(order, eps, compressor, level):
+    """eps = 10^-order (Acc 6-8): ranks 34-62, above one LDS slice of the compressed kernel's
+    factors; the compressed kernel applies them in slices, and its M2L matches the oracle's."""
+    say("IAblk high rank", order, eps, compressor)
+    pts, _ = cube(64, 1, 1)
+    tree = pk.Octree(dev(pts), level)
+    plan = pk.Plan(tree, "inv_r", order, eps, "fp64", 0.0, compressor)
+    st = plan.stats()
+    say("  ranks", st["rank"], "kernel", st["m2l_kernel"])
+    assert st["m2l_kernel"] == 1 and max(st["rank"]) > (32 if order <= 6 else 16)
+    rng = np.random.default_rng(300 + order)
+    w = rng.standard_normal((8 ** level, order ** 3, 1))
+    f_gpu = host(plan.m2l_level(level, dev(oracle_to_morton(w, level))))
+    f_ref = O.m2l_level(w, level, 1.0, order, "inv_r", 0.0, eps, compressor=compressor)
+    err = rel(morton_to_oracle(f_gpu, level), f_ref)
+    say("  rel err", err)
+    assert err < 1e-12
+
+
+def test_compressed_apply_at_high_accuracy_and_faster_than_full_rank():
+    """A whole apply with eps 1e-6 at order 6 against the oracle, and its M2L time against the
+    full-rank kernel on the same tree (the compressed one does 4 l^3 r instead of 2 l^6 flops per
+    pair: about 3x fewer at these ranks)."""
+    say("IAblk high rank apply")
+    pts, q = cube(6000, 1, 301)
+    order, depth, eps = 6, 3, 1e-6
+    tree = pk.Octree(dev(pts), depth)
+    plan = pk.Plan(tree, "inv_r", order, eps)
+    assert plan.stats()["m2l_kernel"] == 1
+    phi = host(plan.apply(dev(q)))
+    err = rel(phi, O.fmm_apply(pts, q, order, depth, "inv_r", 0.0, eps).phi)
+    say("  rel err", err)
+    assert err < 1e-12
+    big, qb = cube(200000, 1, 302)
+    tree = pk.Octree(dev(big), 5)
+    times = {}
+    for name, e in (("compressed", 1e-6), ("full", 0.0)):
+        pl = pk.Plan(tree, "inv_r", order, e)
+        dq = dev(qb)
+        pl.apply(dq)
+        pl.set_timing(True)
+        for _ in range(3):
+            pl.apply(dq)
+        ms, calls = pl.pass_times()
+        times[name] = ms["m2l"] / calls
+        del pl
+    say("  M2L ms", times)
+    assert times["compressed"] < times["full"]
