@@ -400,6 +400,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 3}))
         return
+    if args.dfmm is not None and args.gpus == 1:
+        args.steps = 5 if args.steps is None else args.steps
+        args.warmup = 1 if args.warmup is None else args.warmup
+        run_dfmm(args)
+        return
     if args.gpus == 1:
         from workloads import WORKLOADS as _W
         big = _W[args.config].n >= 4_000_000
@@ -409,11 +414,6 @@ def main():
             args.warmup = 1 if big else 3
     if args.helmholtz is not None and args.gpus == 1:
         run_helmholtz(args)
-        return
-    if args.dfmm is not None and args.gpus == 1:
-        if args.steps is None or args.config == 3:
-            args.steps, args.warmup = 5, 1
-        run_dfmm(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "

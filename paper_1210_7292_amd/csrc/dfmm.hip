@@ -277,12 +277,11 @@ __global__ __launch_bounds__(kPassThreads) void dfmm_l2l_kernel(DGeom g, DLevel 
 // ---- M2L: per representative, a complex MFMA product over a tile of 64 pairs ---------------
 struct DM2L {
   const double2* W;
-  double2* F;
+  double2* P;                  // [pair][NN]: each pair's product K_p W_Y(sigma^-1), in K_p's rows
   const double* ops;           // per group: re [NN][NN] then im [NN][NN]
   const long long* op_off;     // [group]
   const long long* grp_end;    // [group] end of the group's pairs
   const int2* blocks;          // [block] (group, first pair)
-  const int* pair_x;           // target row
   const int* pair_y;           // source row
   const unsigned char* pair_perm;
   const short* siginv;         // [48][NP]
@@ -308,16 +307,18 @@ __global__ __launch_bounds__(256 * RS) void dfmm_m2l_kernel(DM2L a) {
   constexpr int KS = KC / 4;
   __shared__ double kre[(NN + 1) * LDK];
   __shared__ double kim[(NN + 1) * LDK];
+  __shared__ short ssi[kNumPerms * NP];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int j = lane % 16, kq = lane / 16;
   const int cw = wave % 4, mb0 = (wave / 4) * MBW;
+  for (int x = tid; x < kNumPerms * NP; x += NT) ssi[x] = a.siginv[x];
   const int2 bi = a.blocks[blockIdx.x];
   const int grp = bi.x;
   const long long pair = (long long)bi.y + 16 * cw + j;
   const bool valid = pair < a.grp_end[grp];
   const int perm = valid ? (int)a.pair_perm[pair] : 0;
   const double2* src = a.W + (valid ? (long long)a.pair_y[pair] * NN : 0);
-  const short* si = a.siginv + perm * NP;
+  const short* si = ssi + perm * NP;
   const double* opr = a.ops + a.op_off[grp];
   const double* opi = opr + (long long)NN * NN;
   f64x4 accr[MBW], acci[MBW];
@@ -326,6 +327,7 @@ __global__ __launch_bounds__(256 * RS) void dfmm_m2l_kernel(DM2L a) {
     accr[m] = f64x4{0, 0, 0, 0};
     acci[m] = f64x4{0, 0, 0, 0};
   }
+  __syncthreads();
   for (int ch = 0; ch < NCH; ++ch) {
     // this chunk's source values, in flight while the operator chunk is staged
     double2 bv[KS];
@@ -369,18 +371,38 @@ __global__ __launch_bounds__(256 * RS) void dfmm_m2l_kernel(DM2L a) {
     }
   }
   if (!valid) return;
-  double2* dst = a.F + (long long)a.pair_x[pair] * NN;
+  double2* dst = a.P + pair * NN;
 #pragma unroll
   for (int m = 0; m < MBW; ++m)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = 16 * (mb0 + m) + kq + 4 * v;
-      if (i < NN) {
-        double* d = reinterpret_cast<double*>(dst + si[i]);
-        unsafeAtomicAdd(d, accr[m][v]);
-        unsafeAtomicAdd(d + 1, acci[m][v]);
-      }
+      if (i < NN) dst[i] = make_double2(accr[m][v], acci[m][v]);
     }
+}
+
+// Second M2L phase: the locals of every expansion row are the sum of the products of its pairs,
+// read back through the pairs' permutations (F_X[i] = sum_q P_q[sigma_q(i)]), in the fixed
+// order of the per-row pair lists: no atomics, the same result on every run. One workgroup per
+// row (rows without pairs get zeros).
+__global__ __launch_bounds__(kPassThreads) void dfmm_m2l_reduce_kernel(const double2* __restrict__ P,
+                                                                       const long long* __restrict__ row_off,
+                                                                       const int* __restrict__ row_pairs,
+                                                                       const unsigned char* __restrict__ pair_perm,
+                                                                       const short* __restrict__ sig, int nn, int np,
+                                                                       double2* __restrict__ F) {
+  const long long row = blockIdx.x;
+  const long long q0 = row_off[row], q1 = row_off[row + 1];
+  for (int i = threadIdx.x; i < nn; i += kPassThreads) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (long long e = q0; e < q1; ++e) {
+      const int q = row_pairs[e];
+      const double2 v = P[(long long)q * nn + sig[(int)pair_perm[q] * np + i]];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    F[row * nn + i] = acc;
+  }
 }
 
 // ---- leaves: L2P (Eq. l2l_dfmm) over the leaf level's cones, near field, scatter ------------
@@ -542,8 +564,10 @@ struct bbfmm_dfmm {
   int* d_inv[kDfmmLevels] = {nullptr};
   double* d_tk = nullptr; double* d_xhat = nullptr; double* d_m1d = nullptr;
   double* d_ops = nullptr; long long* d_op_off = nullptr; long long* d_grp_end = nullptr;
-  int2* d_blocks = nullptr; int* d_pair_x = nullptr; int* d_pair_y = nullptr; unsigned char* d_pair_perm = nullptr;
-  short* d_siginv = nullptr;
+  int2* d_blocks = nullptr; int* d_pair_y = nullptr; unsigned char* d_pair_perm = nullptr;
+  short* d_siginv = nullptr; short* d_sig = nullptr;
+  long long* d_row_off = nullptr; int* d_row_pairs = nullptr;
+  double2* P = nullptr; long long npairs = 0;
   int* d_near_off = nullptr; unsigned* d_near_src = nullptr;
   double2* W = nullptr; double2* F = nullptr; double2* qs = nullptr;
   hipEvent_t busy = nullptr; hipStream_t busy_stream = nullptr; bool busy_set = false;
@@ -664,8 +688,9 @@ void free_dfmm(bbfmm_dfmm* p) {
     dfree(p->d_inv_off[l]); dfree(p->d_inv[l]);
   }
   dfree(p->d_tk); dfree(p->d_xhat); dfree(p->d_m1d); dfree(p->d_ops); dfree(p->d_op_off); dfree(p->d_grp_end);
-  dfree(p->d_blocks); dfree(p->d_pair_x); dfree(p->d_pair_y); dfree(p->d_pair_perm); dfree(p->d_siginv);
+  dfree(p->d_blocks); dfree(p->d_pair_y); dfree(p->d_pair_perm); dfree(p->d_siginv);
   dfree(p->d_near_off); dfree(p->d_near_src); dfree(p->W); dfree(p->F); dfree(p->qs);
+  dfree(p->d_sig); dfree(p->d_row_off); dfree(p->d_row_pairs); dfree(p->P);
   if (p->busy) (void)hipEventDestroy(p->busy);
   for (hipEvent_t x : p->ev) (void)hipEventDestroy(x);
 }
@@ -885,14 +910,27 @@ bbfmm_status bbfmm_dfmm_precompute(const bbfmm_tree* tree, double k, int32_t ord
   if ((long long)px.size() > 0x7fffffffLL) return fail(BBFMM_EUNSUPPORTED, "too many M2L pairs");
   p->ngroups = (int)groups.size();
   p->nblocks = (int)blocks.size();
-  // sigma^-1 tables
-  std::vector<short> sinv((size_t)kNumPerms * np, 0);
+  // sigma and sigma^-1 tables
+  std::vector<short> sinv((size_t)kNumPerms * np, 0), sfwd((size_t)kNumPerms * np, 0);
   std::vector<int32_t> sg(nn);
   for (int q = 0; q < kNumPerms; ++q) {
     sigma_table(L, q, sg.data());
-    for (int i = 0; i < nn; ++i) sinv[(size_t)q * np + sg[i]] = (short)i;
-    for (int i = nn; i < np; ++i) sinv[(size_t)q * np + i] = (short)(nn - 1);
+    for (int i = 0; i < nn; ++i) {
+      sinv[(size_t)q * np + sg[i]] = (short)i;
+      sfwd[(size_t)q * np + i] = (short)sg[i];
+    }
+    for (int i = nn; i < np; ++i) sinv[(size_t)q * np + i] = sfwd[(size_t)q * np + i] = (short)(nn - 1);
   }
+  // pairs of every expansion row (target), in pair order: the second M2L phase's sum order
+  std::vector<long long> row_off((size_t)rows + 1, 0);
+  for (int x : px) ++row_off[(size_t)x + 1];
+  for (long long r2 = 0; r2 < rows; ++r2) row_off[(size_t)r2 + 1] += row_off[(size_t)r2];
+  std::vector<int> row_pairs(px.size());
+  {
+    std::vector<long long> cur(row_off.begin(), row_off.end() - 1);
+    for (size_t q = 0; q < px.size(); ++q) row_pairs[(size_t)cur[(size_t)px[q]]++] = (int)q;
+  }
+  p->npairs = (long long)px.size();
   // near field CSR per occupied leaf
   std::vector<std::vector<unsigned>> nl(cells[d].size());
   for (const auto& pr : nearp) nl[pos[d][pr.first]].push_back(pr.second);
@@ -945,7 +983,9 @@ bbfmm_status bbfmm_dfmm_precompute(const bbfmm_tree* tree, double k, int32_t ord
   if ((e = upload(&p->d_op_off, op_off, &bytes)) != hipSuccess) return bad(e, "upload");
   if ((e = upload(&p->d_grp_end, grp_end, &bytes)) != hipSuccess) return bad(e, "upload");
   if ((e = upload(&p->d_blocks, blocks, &bytes)) != hipSuccess) return bad(e, "upload");
-  if ((e = upload(&p->d_pair_x, px, &bytes)) != hipSuccess) return bad(e, "upload");
+  if ((e = upload(&p->d_sig, sfwd, &bytes)) != hipSuccess) return bad(e, "upload");
+  if ((e = upload(&p->d_row_off, row_off, &bytes)) != hipSuccess) return bad(e, "upload");
+  if ((e = upload(&p->d_row_pairs, row_pairs, &bytes)) != hipSuccess) return bad(e, "upload");
   if ((e = upload(&p->d_pair_y, py, &bytes)) != hipSuccess) return bad(e, "upload");
   if ((e = upload(&p->d_pair_perm, pperm, &bytes)) != hipSuccess) return bad(e, "upload");
   if ((e = upload(&p->d_siginv, sinv, &bytes)) != hipSuccess) return bad(e, "upload");
@@ -955,6 +995,10 @@ bbfmm_status bbfmm_dfmm_precompute(const bbfmm_tree* tree, double k, int32_t ord
     if ((e = hipMalloc((void**)&p->W, (size_t)rows * nn * sizeof(double2))) != hipSuccess) return bad(e, "alloc");
     if ((e = hipMalloc((void**)&p->F, (size_t)rows * nn * sizeof(double2))) != hipSuccess) return bad(e, "alloc");
     bytes += 2 * rows * nn * (long long)sizeof(double2);
+  }
+  if (p->npairs > 0) {
+    if ((e = hipMalloc((void**)&p->P, (size_t)p->npairs * nn * sizeof(double2))) != hipSuccess) return bad(e, "alloc");
+    bytes += p->npairs * nn * (long long)sizeof(double2);
   }
   if ((e = hipMalloc((void**)&p->qs, (size_t)tree->n * sizeof(double2))) != hipSuccess) return bad(e, "alloc");
   bytes += tree->n * (long long)sizeof(double2);
@@ -1039,14 +1083,18 @@ bbfmm_status bbfmm_dfmm_apply(bbfmm_dfmm* p, const double* d_q, double* d_phi, v
       er = R::p2m(g, dlevel_of(p, d), p->qs, p->W, s);
       for (int l = d - 1; l >= top && er == hipSuccess; --l)
         er = R::m2m(g, dlevel_of(p, l), dlevel_of(p, l + 1), l, p->W, s);
-      if (er == hipSuccess) er = launch_fill_zero(reinterpret_cast<double*>(p->F), 2 * p->rows * p->nn, s);
       if (er == hipSuccess) er = dmark(p, s);
       if (er == hipSuccess) {
         DM2L a;
-        a.W = p->W; a.F = p->F; a.ops = p->d_ops; a.op_off = p->d_op_off; a.grp_end = p->d_grp_end;
-        a.blocks = p->d_blocks; a.pair_x = p->d_pair_x; a.pair_y = p->d_pair_y; a.pair_perm = p->d_pair_perm;
+        a.W = p->W; a.P = p->P; a.ops = p->d_ops; a.op_off = p->d_op_off; a.grp_end = p->d_grp_end;
+        a.blocks = p->d_blocks; a.pair_y = p->d_pair_y; a.pair_perm = p->d_pair_perm;
         a.siginv = p->d_siginv;
         er = R::m2l(a, p->nblocks, s);
+      }
+      if (er == hipSuccess) {
+        hipLaunchKernelGGL(dfmm_m2l_reduce_kernel, dim3((unsigned)p->rows), dim3(kPassThreads), 0, s, p->P,
+                           p->d_row_off, p->d_row_pairs, p->d_pair_perm, p->d_sig, p->nn, p->np, p->F);
+        er = hipGetLastError();
       }
       if (er == hipSuccess) er = dmark(p, s);
       for (int l = top; l < d && er == hipSuccess; ++l)
