@@ -275,11 +275,20 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
   constexpr bool SPLIT = PREC == 2;
   __shared__ T khi[KL::SIZE];
   __shared__ T klo[SPLIT ? KL::SIZE : 1];
-  // sigma tables in LDS when they fit; the row table then holds LDS row offsets
-  constexpr bool SIGLDS =
-      ((SPLIT ? 2 : 1) * KL::SIZE * (int)sizeof(T) + 2 * kNumPerms * NP * 2) <= 150 * 1024;
+  // sigma tables in LDS when they fit; the row table then holds LDS row offsets. Otherwise
+  // sigma^-1 (the B gathers' indices) alone when it fits, and the lanes' sigma(i) of the next
+  // transfer vector are loaded into registers beside its B operands (orders <= 7 outside the
+  // split mode; the others have no registers left), so no global load is waited for inside a
+  // transfer vector.
+  constexpr int KBYTES = (SPLIT ? 2 : 1) * KL::SIZE * (int)sizeof(T);
+  constexpr int TBYTES = kNumPerms * NP * 2;
+  constexpr int OTHER = kMaskWords * 4 + (NN + 1) * 2 + (AD ? kSrcTargets * kFarPerOctant * 4 : 4) +
+                        kFarPerOctant * 4;
+  constexpr bool SIGLDS = KBYTES + 2 * TBYTES <= 150 * 1024;
+  constexpr bool SISLDS = SIGLDS || KBYTES + TBYTES + OTHER <= 159 * 1024;
+  constexpr bool SIGPF = !SIGLDS && L <= 7 && !SPLIT;
   __shared__ short sgs[SIGLDS ? kNumPerms * NP : 1];
-  __shared__ short sis[SIGLDS ? kNumPerms * NP : 1];
+  __shared__ short sis[SISLDS ? kNumPerms * NP : 1];
   __shared__ unsigned amask[kMaskWords];
   __shared__ short roff_tab[NN + 1];       // LDS offset of each K_p row
   __shared__ int ssrc[AD ? kSrcTargets * kFarPerOctant : 1];
@@ -295,15 +304,15 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
   const Column col = column_of<AD>(a, bp, 16 * cw + j);
   const int set = bp.lv.set;
 
-  if (SIGLDS)
+  if (SISLDS)
     for (int x = tid; x < kNumPerms * NP; x += NT) {
-      sgs[x] = (short)KL::off(a.sig[x]);
+      if (SIGLDS) sgs[x] = (short)KL::off(a.sig[x]);
       sis[x] = a.siginv[x];
     }
   block_mask<AD>(a, bp, amask, ssrc, tid, NT);
   if (!AD) __syncthreads();
   const short* sgb = SIGLDS ? sgs : a.sig;
-  const short* sib = SIGLDS ? sis : a.siginv;
+  const short* sib = SISLDS ? sis : a.siginv;
 
   V acc[MBW];
   f64x4 acc64[MBW];
@@ -368,7 +377,9 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
       // loads in batches of SB issued back to back, then their LDS stores: a few memory
       // latencies per chunk rather than one per element
       constexpr int PER = ((NN + 1) * KC + NT - 1) / NT;
-      constexpr int SB = L >= 8 ? 4 : (sizeof(T) == 8 ? 8 : 16);   // order 8: register-bound
+      // order 7 in FP64: the whole share in one batch (one memory latency per chunk); order 8:
+      // register-bound
+      constexpr int SB = L >= 8 ? 4 : (L == 7 && PREC == 0 ? PER : (sizeof(T) == 8 ? 8 : 16));
 #pragma unroll 1
       for (int u0 = 0; u0 < PER; u0 += SB) {
         T th[SB], tl[SPLIT ? SB : 1];
@@ -399,13 +410,31 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
       __syncthreads();
       BT bv[KS];
       double bn[KS];
+      // sigma(i) of this lane's rows, loaded one transfer vector ahead (SIGPF)
+      int sgn[SIGPF ? MBW : 1];
+      auto load_sig = [&](int e) {
+        if (SIGPF) {
+          const short* sg = a.sig + (stab[e] >> 13) * NP;
+#pragma unroll
+          for (int m = 0; m < MBW; ++m) sgn[m] = sg[16 * (mb0 + m) + j];
+        }
+      };
       int e = e0;
       bool pres = load_b(e, ch, bn), pres_n = false;
+      load_sig(e);
 #pragma unroll
       for (int s2 = 0; s2 < KS; ++s2) bv[s2] = (BT)bn[s2];
       while (e < g1) {
         const int en = next_active(e + 1, g1);
-        if (en < g1) pres_n = load_b(en, ch, bn);
+        // sigma(i) of transfer vector e, before the next one's loads overwrite them
+        int sgc[SIGPF ? MBW : 1];
+        if (SIGPF)
+#pragma unroll
+          for (int m = 0; m < MBW; ++m) sgc[m] = sgn[m];
+        if (en < g1) {
+          pres_n = load_b(en, ch, bn);
+          load_sig(en);
+        }
         // a wave none of whose columns has this source skips its products (they are zero)
         if (__ballot(pres) == 0ull) {
 #pragma unroll
@@ -419,14 +448,17 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
         // k step 4 s2 then folds into the LDS reads' immediate offsets
         constexpr int NPK = (MBW + 1) / 2;
         static_assert(KL::SIZE < 32768, "row offsets fit 16 bits");
-        auto roff = [&](int i) -> unsigned {
+        // row block m of this wave: output row i = 16 (mb0 + m) + j
+        auto roff = [&](int m) -> unsigned {
+          if (SIGPF) return (unsigned)((int)roff_tab[sgc[m]] + kq);
+          const int i = 16 * (mb0 + m) + j;
           return (unsigned)((SIGLDS ? (int)sg[i] : (int)roff_tab[sg[i]]) + kq);
         };
         unsigned srow2[NPK];
 #pragma unroll
         for (int m2 = 0; m2 < NPK; ++m2) {
-          const unsigned lo = roff(16 * (mb0 + 2 * m2) + j);
-          const unsigned hi = (2 * m2 + 1 < MBW) ? roff(16 * (mb0 + 2 * m2 + 1) + j) : 0u;
+          const unsigned lo = roff(2 * m2);
+          const unsigned hi = (2 * m2 + 1 < MBW) ? roff(2 * m2 + 1) : 0u;
           srow2[m2] = lo | (hi << 16);
         }
         auto srow = [&](int m) -> int { return (int)((m & 1) ? (srow2[m >> 1] >> 16) : (srow2[m >> 1] & 0xffffu)); };
