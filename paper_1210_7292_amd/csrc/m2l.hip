@@ -272,6 +272,7 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
   constexpr int NCH = (NN + KC - 1) / KC;
   using KL = KLayout<L, KC, (int)sizeof(T)>;
   constexpr int KS = KC / 4;
+  constexpr int KS_LAST = (NN - (NCH - 1) * KC + 3) / 4;   // k steps of the last chunk holding k < l^3
   constexpr bool SPLIT = PREC == 2;
   __shared__ T khi[KL::SIZE];
   __shared__ T klo[SPLIT ? KL::SIZE : 1];
@@ -464,6 +465,8 @@ __global__ __launch_bounds__(kThreads * RS) void m2l_full_kernel(M2LArgs a) {
         auto srow = [&](int m) -> int { return (int)((m & 1) ? (srow2[m >> 1] >> 16) : (srow2[m >> 1] & 0xffffu)); };
 #pragma unroll
         for (int s2 = 0; s2 < KS; ++s2) {
+          // the last chunk's k steps beyond l^3 multiply zero columns: skipped
+          if (s2 >= KS_LAST && ch == NCH - 1) break;
           const int kl = 4 * s2;
           if (!SPLIT) {
             const T b = (T)bv[s2];
@@ -1068,7 +1071,8 @@ double m2l_issued_flops_per_t(int order, bool lowrank, int rank) {
   if (!lowrank) {
     const int kc = order <= 2 ? 8 : order >= 9 ? 16 : 32;
     const int nch = (nn + kc - 1) / kc;
-    return (double)(np / 16) * (nch * kc / 4) * mfma * 4;
+    const int ksteps = (nch - 1) * kc / 4 + (nn - (nch - 1) * kc + 3) / 4;   // the last chunk's padding is skipped
+    return (double)(np / 16) * ksteps * mfma * 4;
   }
   // per rank slice (32 ranks below order 7, 16 from order 7)
   const int sw = order <= 6 ? 32 : 16;
