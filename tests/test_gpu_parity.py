@@ -199,10 +199,14 @@ def test_aca_adjoint_and_gradient_match_oracle():
     assert rel(grad, O.fmm_grad_points(pts, q, g, order, depth, eps=eps, compressor="aca")) < 1e-11
 
 
-def test_passes_match_oracle():
-    say("passes")
-    pts, q = cube(3000, 2, 5)
-    order, depth = 4, 3
+# (order, right-hand sides): M2M and L2L with several right-hand sides per parent, where a
+# workgroup takes all of them at once (2 at order 4) or one or a few per pass (4 at orders 5 and
+# 7, 3 at order 6, 30 at order 4)
+@pytest.mark.parametrize("order,nrhs", [(4, 2), (5, 4), (6, 3), (7, 4), (4, 30)])
+def test_passes_match_oracle(order, nrhs):
+    say("passes", order, nrhs)
+    pts, q = cube(3000, nrhs, 5)
+    depth = 3
     tree = pk.Octree(dev(pts), depth)
     plan = pk.Plan(tree, "inv_r", order, 0.0)
     plan.apply(dev(q))
@@ -212,14 +216,14 @@ def test_passes_match_oracle():
     s = 1 << depth
     ijk = np.clip(np.floor(pts * s).astype(np.int64), 0, s - 1)
     for lev in range(2, depth + 1):
-        w = morton_to_oracle(host(plan.expansions(lev, 0, 2)), lev)
+        w = morton_to_oracle(host(plan.expansions(lev, 0, nrhs)), lev)
         assert rel(w, res.multipoles[lev]) < 1e-13, ("W", lev)
         c = ijk >> (depth - lev)
         held = np.zeros(8 ** lev, dtype=bool)
         held[c[:, 0] + (1 << lev) * c[:, 1] + (1 << (2 * lev)) * c[:, 2]] = True
-        f = morton_to_oracle(host(plan.expansions(lev, 2, 2)), lev)
+        f = morton_to_oracle(host(plan.expansions(lev, 2, nrhs)), lev)
         assert rel(f[held], res.locals[lev][held]) < 1e-12, ("F", lev)
-        fm = morton_to_oracle(host(plan.expansions(lev, 1, 2)), lev)
+        fm = morton_to_oracle(host(plan.expansions(lev, 1, nrhs)), lev)
         assert rel(fm, res.locals_m2l[lev]) < 1e-12, ("M2L", lev)
 
 
