@@ -135,6 +135,36 @@ constexpr int kM2MThreads = 256;
 template <int L> constexpr int m2m_nv() {
   return (2048 / (8 * L * L * L)) < 1 ? 1 : (2048 / (8 * L * L * L)) > 32 ? 32 : 2048 / (8 * L * L * L);
 }
+// Work items of the M2M / L2L grid. With nrhs <= NV an item is NV / nrhs whole parents (their
+// vectors are contiguous). With more right-hand sides than NV an item is NV right-hand sides of one
+// parent, read at a stride of nrhs; the items of one parent are then given to neighbouring
+// workgroups of one XCD (hardware sends workgroup b to XCD b % 8), so that their reads of the same
+// lines meet in that XCD's L2 instead of each fetching them from HBM.
+struct PassIter {
+  long long count, npar;   // items, parents
+  int nrhs, nv_max, pg, per_par;
+  __device__ PassIter(long long np, int nr, int NV) : npar(np), nrhs(nr), nv_max(NV) {
+    pg = nr <= NV ? NV / nr : 1;
+    per_par = nr <= NV ? 1 : (nr + NV - 1) / NV;
+    count = nr <= NV ? (npar + pg - 1) / pg : npar * per_par;
+  }
+  __device__ long long first() const {
+    if (per_par == 1 || gridDim.x % 8 != 0) return blockIdx.x;
+    return (long long)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  }
+  // first vector of item gi and its vector count
+  __device__ long long vectors(long long gi, int& nv) const {
+    if (per_par == 1) {
+      const long long P0 = gi * pg;
+      nv = (int)min((long long)pg, npar - P0) * nrhs;   // whole parents; the last item may hold fewer
+      return P0 * nrhs;
+    }
+    const long long P = gi / per_par;
+    const int w0 = (int)(gi - P * per_par) * nv_max;
+    nv = min(nv_max, nrhs - w0);
+    return P * nrhs + w0;
+  }
+};
 
 template <int L>
 __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(PassGeom g, int parent_level,
@@ -150,11 +180,10 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(PassGeom g, int parent
   // a block owns PG whole parents and takes their (parent, rhs) vectors NV at a time, so the
   // right-hand sides of a parent share one L2
   const long long npar = 1ll << (3 * parent_level);
-  const int PG = max(1, NV / nrhs);
-  for (long long P0 = (long long)blockIdx.x * PG; P0 < npar; P0 += (long long)gridDim.x * PG)
-  for (int w0 = 0; w0 < (int)min((long long)PG, npar - P0) * nrhs; w0 += NV) {
-    const int nv = min(NV, (int)min((long long)PG, npar - P0) * nrhs - w0);
-    const long long v0 = P0 * nrhs + w0;   // vector v = P * nrhs + r
+  PassIter it(npar, nrhs, NV);
+  for (long long gi = it.first(); gi < it.count; gi += gridDim.x) {
+    int nv;
+    const long long v0 = it.vectors(gi, nv);   // vectors v0 .. v0 + nv - 1, v = P * nrhs + r
     double t[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -229,11 +258,10 @@ __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(PassGeom g, int parent
   const int tid = threadIdx.x;
   for (int i = tid; i < 2 * L * L; i += kM2MThreads) sM[i] = g.m2m[i];
   const long long npar = 1ll << (3 * parent_level);
-  const int PG = max(1, NV / nrhs);
-  for (long long P0 = (long long)blockIdx.x * PG; P0 < npar; P0 += (long long)gridDim.x * PG)
-  for (int w0 = 0; w0 < (int)min((long long)PG, npar - P0) * nrhs; w0 += NV) {
-    const int nv = min(NV, (int)min((long long)PG, npar - P0) * nrhs - w0);
-    const long long v0 = P0 * nrhs + w0;
+  PassIter it(npar, nrhs, NV);
+  for (long long gi = it.first(); gi < it.count; gi += gridDim.x) {
+    int nv;
+    const long long v0 = it.vectors(gi, nv);
     // the children's current locals (the M2L result), in flight during the contractions
     double old[PER];
     long long addr[PER];
@@ -895,8 +923,10 @@ template <int L> struct P2MRun {
 };
 inline unsigned m2m_blocks(int pl, int nrhs, int nv) {
   const long long npar = 1ll << (3 * pl);
-  const int pg = std::max(1, nv / nrhs);
-  return (unsigned)std::min<long long>((npar + pg - 1) / pg, 1 << 20);
+  // the items of PassIter; with several items per parent the grid is a multiple of 8 (XCD remap)
+  const long long items = nrhs <= nv ? (npar + nv / nrhs - 1) / (nv / nrhs) : npar * ((nrhs + nv - 1) / nv);
+  const long long g = std::min<long long>(items, 1 << 20);
+  return (unsigned)(nrhs <= nv || g < 8 ? g : g / 8 * 8);
 }
 template <int L> struct M2MRun {
   static hipError_t run(const PassGeom& g, int pl, const double* Wc, double* Wp, int nrhs, hipStream_t s) {
