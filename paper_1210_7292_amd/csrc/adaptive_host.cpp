@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <numeric>
+#include <thread>
 
 namespace bbfmm {
 
@@ -69,6 +70,23 @@ bool touch(int la, const long long* a, int lb, const long long* b) {
   return true;
 }
 
+// Runs fn(part, begin, end) over [0, n) cut into contiguous parts, one thread each; the parts are
+// in index order, so per-part outputs concatenated in part order equal the serial output.
+template <typename Fn>
+void parallel_parts(long long n, int parts, Fn fn) {
+  std::vector<std::thread> th;
+  for (int t = 0; t < parts; ++t) {
+    const long long b = n * t / parts, e = n * (t + 1) / parts;
+    th.emplace_back([=, &fn]() { fn(t, b, e); });
+  }
+  for (auto& x : th) x.join();
+}
+
+int host_threads() {
+  const unsigned hw = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(hw, 16u));
+}
+
 }  // namespace
 
 void build_adaptive_topology(AdaptiveTopology& T, const std::vector<std::vector<unsigned long long>>& keys,
@@ -118,39 +136,95 @@ void build_adaptive_topology(AdaptiveTopology& T, const std::vector<std::vector<
   Finder F{T};
   // ---- V: the far-field table restricted to existing cells ----
   T.m2l_off.assign((size_t)T.nlevels * 8 + 1, 0);
+  const int nth = host_threads();
   {
-    std::vector<std::vector<int>> tgt(T.nlevels * 8);
-    std::vector<std::vector<int>> src(T.nlevels * 8);
-    for (int l = 2; l < T.nlevels; ++l) {
-      const long long side = 1LL << l;
-      for (int g = T.level_off[l]; g < T.level_off[l + 1]; ++g) {
+    // The V sources of a cell are the children of its parent's 27 neighbours at the far offsets of
+    // its octant: the neighbours are looked up once per parent, and each child found there is
+    // placed at its offset's entry (an inverse of the octant table), so no cell is searched for.
+    std::vector<int> inv(8 * 512, -1);
+    for (int o = 0; o < 8; ++o)
+      for (int k = 0; k < kFarPerOctant; ++k) inv[o * 512 + (octant_tab[o * kFarPerOctant + k] & 511)] = k;
+    // neighbours (27, self included) of every node that has children, -1 where absent
+    std::vector<int> nbr(27 * (size_t)nn, -1);
+    parallel_parts(nn, nth, [&](int, long long b, long long e) {
+      for (int g = (int)b; g < (int)e; ++g) {
+        if (T.child_begin[g] == T.child_end[g]) continue;
+        const int l = T.level[g];
+        const long long side = 1LL << l;
+        long long c[3];
+        coords(T.key[g], c);
+        for (int d = 0; d < 27; ++d) {
+          const long long n3[3] = {c[0] + d % 3 - 1, c[1] + (d / 3) % 3 - 1, c[2] + d / 9 - 1};
+          if (n3[0] < 0 || n3[1] < 0 || n3[2] < 0 || n3[0] >= side || n3[1] >= side || n3[2] >= side) continue;
+          nbr[27 * (size_t)g + d] = d == 13 ? g : F.find(l, morton(n3));
+        }
+      }
+    });
+    // parent of every node of level >= 1
+    std::vector<int> parent(nn, -1);
+    for (int g = 0; g < nn; ++g)
+      for (int ch = T.child_begin[g]; ch < T.child_end[g]; ++ch) parent[ch] = g;
+    // per part: targets and source rows per (level, octant), in node order
+    struct VPart {
+      std::vector<std::vector<int>> tgt, src;
+      long long pairs = 0;
+    };
+    std::vector<VPart> vp(nth);
+    const int g0 = T.nlevels > 2 ? T.level_off[2] : nn;
+    parallel_parts(nn - g0, nth, [&](int t, long long b, long long e) {
+      VPart& P = vp[t];
+      P.tgt.assign(T.nlevels * 8, {});
+      P.src.assign(T.nlevels * 8, {});
+      for (int g = g0 + (int)b; g < g0 + (int)e; ++g) {
+        const int l = T.level[g];
         long long c[3];
         coords(T.key[g], c);
         const int oct = (int)(T.key[g] & 7);
         int row[kFarPerOctant];
+        for (int k = 0; k < kFarPerOctant; ++k) row[k] = -1;
         bool any = false;
-        for (int e = 0; e < kFarPerOctant; ++e) {
-          const int ent = octant_tab[oct * kFarPerOctant + e];
-          const long long n3[3] = {c[0] + (ent & 7) - 3, c[1] + ((ent >> 3) & 7) - 3, c[2] + ((ent >> 6) & 7) - 3};
-          row[e] = -1;
-          if (n3[0] < 0 || n3[1] < 0 || n3[2] < 0 || n3[0] >= side || n3[1] >= side || n3[2] >= side) continue;
-          row[e] = F.find(l, morton(n3));
-          if (row[e] >= 0) {
+        const int pg = parent[g];
+        for (int d = 0; d < 27; ++d) {
+          const int np = nbr[27 * (size_t)pg + d];
+          if (np < 0) continue;
+          for (int ch = T.child_begin[np]; ch < T.child_end[np]; ++ch) {
+            long long cc[3];
+            coords(T.key[ch], cc);
+            const int ent = (int)(cc[0] - c[0] + 3) + 8 * (int)(cc[1] - c[1] + 3) + 64 * (int)(cc[2] - c[2] + 3);
+            const int k = inv[oct * 512 + ent];
+            if (k < 0) continue;   // a near neighbour (or the cell itself)
+            row[k] = ch;
             any = true;
-            ++T.v_pairs;
+            ++P.pairs;
           }
         }
         if (any) {
-          tgt[l * 8 + oct].push_back(g);
-          src[l * 8 + oct].insert(src[l * 8 + oct].end(), row, row + kFarPerOctant);
+          P.tgt[l * 8 + oct].push_back(g);
+          P.src[l * 8 + oct].insert(P.src[l * 8 + oct].end(), row, row + kFarPerOctant);
         }
       }
-    }
+    });
+    // offsets of every (level, octant, part) piece, then the pieces copied in parallel
+    std::vector<long long> base((size_t)T.nlevels * 8 * nth + 1, 0);
     for (int lo8 = 0; lo8 < T.nlevels * 8; ++lo8) {
-      T.m2l_off[lo8 + 1] = T.m2l_off[lo8] + (int)tgt[lo8].size();
-      T.m2l_tgt.insert(T.m2l_tgt.end(), tgt[lo8].begin(), tgt[lo8].end());
-      T.vsrc.insert(T.vsrc.end(), src[lo8].begin(), src[lo8].end());
+      int cnt = 0;
+      for (int t = 0; t < nth; ++t) {
+        base[(size_t)lo8 * nth + t + 1] = base[(size_t)lo8 * nth + t] + (long long)vp[t].tgt[lo8].size();
+        cnt += (int)vp[t].tgt[lo8].size();
+      }
+      T.m2l_off[lo8 + 1] = T.m2l_off[lo8] + cnt;
     }
+    const long long ntgt = base.back();
+    T.m2l_tgt.resize(ntgt);
+    T.vsrc.resize((size_t)ntgt * kFarPerOctant);
+    parallel_parts(nth, nth, [&](int t, long long, long long) {
+      for (int lo8 = 0; lo8 < T.nlevels * 8; ++lo8) {
+        const long long at = base[(size_t)lo8 * nth + t];
+        std::copy(vp[t].tgt[lo8].begin(), vp[t].tgt[lo8].end(), T.m2l_tgt.begin() + at);
+        std::copy(vp[t].src[lo8].begin(), vp[t].src[lo8].end(), T.vsrc.begin() + at * kFarPerOctant);
+      }
+    });
+    for (const VPart& P : vp) T.v_pairs += P.pairs;
   }
   // ---- U and W for every leaf ----
   T.leaf_pos.assign(nn, -1);
@@ -161,9 +235,16 @@ void build_adaptive_topology(AdaptiveTopology& T, const std::vector<std::vector<
     }
   T.u_off.assign(T.leaves.size() + 1, 0);
   T.w_off.assign(T.leaves.size() + 1, 0);
-  std::vector<std::vector<int>> xl(nn);
+  // per part: the U and W lists of its leaves (CSR counts per leaf, indices in leaf order)
+  struct UWPart {
+    std::vector<int> u_idx, w_idx;
+    long long u_pairs = 0;
+  };
+  std::vector<UWPart> uw(nth);
+  parallel_parts((long long)T.leaves.size(), nth, [&](int t, long long lb, long long le) {
+  UWPart& P = uw[t];
   std::vector<int> u, w, stack;
-  for (size_t lp = 0; lp < T.leaves.size(); ++lp) {
+  for (size_t lp = (size_t)lb; lp < (size_t)le; ++lp) {
     const int b = T.leaves[lp];
     const int l = T.level[b];
     long long c[3];
@@ -210,14 +291,27 @@ void build_adaptive_topology(AdaptiveTopology& T, const std::vector<std::vector<
             }
           }
         }
-    T.u_off[lp + 1] = T.u_off[lp] + (int)u.size();
-    T.u_idx.insert(T.u_idx.end(), u.begin(), u.end());
-    T.w_off[lp + 1] = T.w_off[lp] + (int)w.size();
-    T.w_idx.insert(T.w_idx.end(), w.begin(), w.end());
-    for (int cc : w) xl[cc].push_back(b);
-    for (int y : u) T.u_pairs += (long long)(T.end[b] - T.start[b]) * (T.end[y] - T.start[y]);
-    T.w_pairs += (long long)w.size();
+    T.u_off[lp + 1] = (int)u.size();   // counts; offsets after the join
+    P.u_idx.insert(P.u_idx.end(), u.begin(), u.end());
+    T.w_off[lp + 1] = (int)w.size();
+    P.w_idx.insert(P.w_idx.end(), w.begin(), w.end());
+    for (int y : u) P.u_pairs += (long long)(T.end[b] - T.start[b]) * (T.end[y] - T.start[y]);
   }
+  });
+  for (size_t lp = 0; lp < T.leaves.size(); ++lp) {
+    T.u_off[lp + 1] += T.u_off[lp];
+    T.w_off[lp + 1] += T.w_off[lp];
+  }
+  for (const UWPart& P : uw) {
+    T.u_idx.insert(T.u_idx.end(), P.u_idx.begin(), P.u_idx.end());
+    T.w_idx.insert(T.w_idx.end(), P.w_idx.begin(), P.w_idx.end());
+    T.u_pairs += P.u_pairs;
+  }
+  T.w_pairs = (long long)T.w_idx.size();
+  // X: the leaves whose W list holds each node, in leaf order
+  std::vector<std::vector<int>> xl(nn);
+  for (size_t lp = 0; lp < T.leaves.size(); ++lp)
+    for (int k = T.w_off[lp]; k < T.w_off[lp + 1]; ++k) xl[T.w_idx[k]].push_back(T.leaves[lp]);
   T.x_off.assign(1, 0);
   for (int g = 0; g < nn; ++g) {
     if (xl[g].empty()) continue;
