@@ -337,12 +337,32 @@ __global__ __launch_bounds__(256 * RS) void dfmm_m2l_kernel(DM2L a) {
       bv[s2] = (valid && k < NN) ? src[si[k]] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int x = tid; x < (NN + 1) * KC; x += NT) {
-      const int row = x / KC, cc = x - row * KC, k = ch * KC + cc;
-      const bool in = row < NN && k < NN;
-      const long long o = in ? (long long)row * NN + k : 0;
-      kre[row * LDK + cc] = in ? opr[o] : 0.0;
-      kim[row * LDK + cc] = in ? opi[o] : 0.0;
+    // the chunk's loads in batches of SB issued back to back, then their LDS stores (entries
+    // outside the operator are zeroed at the stores, so no load waits on another)
+    constexpr int PER = ((NN + 1) * KC + NT - 1) / NT;
+    constexpr int SB = L <= 5 ? 8 : (L == 6 ? 4 : 2);
+#pragma unroll 1
+    for (int u0 = 0; u0 < PER; u0 += SB) {
+      double tr[SB], ti[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int x = tid + (u0 + u) * NT;
+        const int row = x / KC, cc = x - row * KC, k = ch * KC + cc;
+        const bool in = x < (NN + 1) * KC && row < NN && k < NN;
+        const long long o = in ? (long long)row * NN + k : 0;
+        tr[u] = opr[o];
+        ti[u] = opi[o];
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int x = tid + (u0 + u) * NT;
+        if (x < (NN + 1) * KC) {
+          const int row = x / KC, cc = x - row * KC, k = ch * KC + cc;
+          const bool in = row < NN && k < NN;
+          kre[row * LDK + cc] = in ? tr[u] : 0.0;
+          kim[row * LDK + cc] = in ? ti[u] : 0.0;
+        }
+      }
     }
     __syncthreads();
 #pragma unroll
