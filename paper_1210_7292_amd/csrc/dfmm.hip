@@ -440,11 +440,17 @@ __global__ __launch_bounds__(kLeafThreads) void dfmm_leaf_kernel(DGeom g, DLevel
   constexpr int NN = L * L * L;
   __shared__ double stk[L * L];
   __shared__ double2 sf[kLeafConeBatch][NN];
+  __shared__ double2 snear[kLeafThreads];
   const int tid = threadIdx.x;
   for (int i = tid; i < L * L; i += kLeafThreads) stk[i] = g.tk[i];
   const int cell = blockIdx.x;
   const unsigned key = lv.cells[cell];
   const int ps = g.leaf_start[key], pe = g.leaf_start[key + 1];
+  // a leaf of fewer points than threads splits each point's near field over G threads, thread
+  // t taking point t mod n and every G-th source leaf from t / n; the G partial sums are added in
+  // a fixed order
+  const int npts = pe - ps;
+  const int G = npts >= kLeafThreads ? 1 : kLeafThreads / max(npts, 1);
   double c[3];
   cell_centre(g, g.depth, key, c);
   const double half = 0.5 * lv.w, inv_half = 1.0 / half;
@@ -473,6 +479,7 @@ __global__ __launch_bounds__(kLeafThreads) void dfmm_leaf_kernel(DGeom g, DLevel
         for (int sb = 0; sb < nb; ++sb) {
           const int s = s0 + sb;
           double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 1
           for (int a2 = 0; a2 < L; ++a2)
             for (int a1 = 0; a1 < L; ++a1) {
               const double w12 = by[a1] * bz[a2];
@@ -493,14 +500,18 @@ __global__ __launch_bounds__(kLeafThreads) void dfmm_leaf_kernel(DGeom g, DLevel
         }
       }
     }
-    if (act) {
-      // near field: the non-admissible leaves of this leaf (itself included), j != i
-      for (int e = near_off[cell]; e < near_off[cell + 1]; ++e) {
+    // near field: the non-admissible leaves of this leaf (itself included), j != i
+    const int ni = G == 1 ? i : ps + tid % max(npts, 1), gi = G == 1 ? 0 : tid / max(npts, 1);
+    const bool nact = G == 1 ? act : tid < G * npts;
+    double2 pn = make_double2(0.0, 0.0);
+    if (nact) {
+      const double nx = g.xs[ni], ny = g.ys[ni], nz = g.zs[ni];
+      for (int e = near_off[cell] + gi; e < near_off[cell + 1]; e += G) {
         const unsigned sk = near_src[e];
         const int js = g.leaf_start[sk], je = g.leaf_start[sk + 1];
         for (int jj = js; jj < je; ++jj) {
-          if (jj == i) continue;
-          const double dx = x - g.xs[jj], dy = y - g.ys[jj], dz = z - g.zs[jj];
+          if (jj == ni) continue;
+          const double dx = nx - g.xs[jj], dy = ny - g.ys[jj], dz = nz - g.zs[jj];
           const double r2 = dx * dx + dy * dy + dz * dz;
           double2 kv;
           if (r2 > 0.0) {
@@ -511,12 +522,24 @@ __global__ __launch_bounds__(kLeafThreads) void dfmm_leaf_kernel(DGeom g, DLevel
             kv = make_double2(0.0, g.k);   // coincident distinct points: the smooth part's limit
           }
           const double2 v = cmul(kv, qs[jj]);
-          phi.x += v.x;
-          phi.y += v.y;
+          pn.x += v.x;
+          pn.y += v.y;
         }
       }
-      out[g.perm[i]] = phi;
     }
+    if (G == 1) {
+      phi.x += pn.x;
+      phi.y += pn.y;
+    } else {
+      snear[tid] = pn;
+      __syncthreads();
+      if (act)
+        for (int gg = 0; gg < G; ++gg) {
+          phi.x += snear[tid + gg * npts].x;
+          phi.y += snear[tid + gg * npts].y;
+        }
+    }
+    if (act) out[g.perm[i]] = phi;
   }
 }
 
