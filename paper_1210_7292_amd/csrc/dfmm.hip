@@ -411,17 +411,44 @@ __global__ __launch_bounds__(kPassThreads) void dfmm_m2l_reduce_kernel(const dou
                                                                        const unsigned char* __restrict__ pair_perm,
                                                                        const short* __restrict__ sig, int nn, int np,
                                                                        double2* __restrict__ F) {
+  // the row's pairs (slot, permutation row) are read into LDS in batches, so the sum over a
+  // batch issues its loads without waiting on the pair lists; entries i + r * threads, r < RI, per
+  // thread (l^3 <= 343 <= RI * threads at the orders 2-7 the directional plan takes)
+  __shared__ int sq[kPassThreads];
+  __shared__ int sp[kPassThreads];
+  constexpr int RI = 3;
+  static_assert(7 * 7 * 7 <= RI * kPassThreads, "every entry of an order-7 row has a thread");
+  const int tid = threadIdx.x;
   const long long row = blockIdx.x;
   const long long q0 = row_off[row], q1 = row_off[row + 1];
-  for (int i = threadIdx.x; i < nn; i += kPassThreads) {
-    double2 acc = make_double2(0.0, 0.0);
-    for (long long e = q0; e < q1; ++e) {
-      const int q = row_pairs[e];
-      const double2 v = P[(long long)q * nn + sig[(int)pair_perm[q] * np + i]];
-      acc.x += v.x;
-      acc.y += v.y;
+  double2 acc[RI];
+#pragma unroll
+  for (int r = 0; r < RI; ++r) acc[r] = make_double2(0.0, 0.0);
+  for (long long b0 = q0; b0 < q1; b0 += kPassThreads) {
+    const int nb = (int)min((long long)kPassThreads, q1 - b0);
+    __syncthreads();
+    if (tid < nb) {
+      const int q = row_pairs[b0 + tid];
+      sq[tid] = q;
+      sp[tid] = (int)pair_perm[q] * np;
     }
-    F[row * nn + i] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int i = tid + r * kPassThreads;
+      if (i >= nn) continue;
+#pragma unroll 4
+      for (int e = 0; e < nb; ++e) {
+        const double2 v = P[(long long)sq[e] * nn + sig[sp[e] + i]];
+        acc[r].x += v.x;
+        acc[r].y += v.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RI; ++r) {
+    const int i = tid + r * kPassThreads;
+    if (i < nn) F[row * nn + i] = acc[r];
   }
 }
 
