@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kPassThreads) void dfmm_l2l_kernel(DGeom g, DLevel 
   }
 }
 
-// ---- M2L: per representative, a complex MFMA product over a tile of 64 pairs ---------------
+// ---- M2L: per representative, a complex MFMA product over a tile of 64 or 128 pairs -------
 struct DM2L {
   const double2* W;
   double2* P;                  // [pair][NN]: each pair's product K_p W_Y(sigma^-1), in K_p's rows
@@ -289,13 +289,17 @@ struct DM2L {
 
 template <int L> constexpr int dfmm_kc() { return L >= 7 ? 16 : 32; }
 template <int L> constexpr int dfmm_rs() { return L >= 6 ? 2 : 1; }
+// column waves of a workgroup: 16 pairs each; up to order 5 eight (128 pairs share each staged
+// operator chunk), above four (the row blocks are split over two waves instead)
+template <int L> constexpr int dfmm_cw() { return L <= 5 ? 8 : 4; }
+inline int dfmm_pairs_per_block(int order) { return order <= 5 ? 128 : 64; }
 
-// Wave w owns pair columns 16 (w % 4) .. +16 and row blocks (w / 4) MB/RS .. +MB/RS. Lane
+// Wave w owns pair columns 16 (w % CW) .. +16 and row blocks (w / CW) MB/RS .. +MB/RS. Lane
 // (j = l % 16, kq = l / 16) supplies A = K_p[16 m + j][k] and B = W_Y[sigma^-1(k)] of its
 // column; the FP64 MFMA returns row kq + 4 v of the block in element v.
-template <int L, int RS>
-__global__ __launch_bounds__(256 * RS) void dfmm_m2l_kernel(DM2L a) {
-  constexpr int NT = 256 * RS;
+template <int L, int RS, int CW>
+__global__ __launch_bounds__(64 * CW * RS) void dfmm_m2l_kernel(DM2L a) {
+  constexpr int NT = 64 * CW * RS;
   constexpr int NN = L * L * L;
   constexpr int NP = (NN + 15) / 16 * 16;
   constexpr int MB = NP / 16;
@@ -310,7 +314,7 @@ __global__ __launch_bounds__(256 * RS) void dfmm_m2l_kernel(DM2L a) {
   __shared__ short ssi[kNumPerms * NP];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int j = lane % 16, kq = lane / 16;
-  const int cw = wave % 4, mb0 = (wave / 4) * MBW;
+  const int cw = wave % CW, mb0 = (wave / CW) * MBW;
   for (int x = tid; x < kNumPerms * NP; x += NT) ssi[x] = a.siginv[x];
   const int2 bi = a.blocks[blockIdx.x];
   const int grp = bi.x;
@@ -593,8 +597,9 @@ template <int L> struct DRun {
   }
   static hipError_t m2l(const DM2L& a, int nblocks, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
-    constexpr int RS = dfmm_rs<L>();
-    hipLaunchKernelGGL((dfmm_m2l_kernel<L, RS>), dim3(nblocks), dim3(256 * RS), 0, s, a);
+    constexpr int RS = dfmm_rs<L>(), CW = dfmm_cw<L>();
+    static_assert(16 * CW == (L <= 5 ? 128 : 64), "tiles of the host's block list");
+    hipLaunchKernelGGL((dfmm_m2l_kernel<L, RS, CW>), dim3(nblocks), dim3(64 * CW * RS), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t leaf(const DGeom& g, const DLevel& lv, const double2* F, const double2* qs, const int* noff,
@@ -975,7 +980,7 @@ bbfmm_status bbfmm_dfmm_precompute(const bbfmm_tree* tree, double k, int32_t ord
     pperm.insert(pperm.end(), G.perm.begin(), G.perm.end());
     const long long p1 = (long long)px.size();
     grp_end.push_back(p1);
-    for (long long q0 = p0; q0 < p1; q0 += 64) blocks.push_back(make_int2((int)g, (int)q0));
+    for (long long q0 = p0; q0 < p1; q0 += dfmm_pairs_per_block(order)) blocks.push_back(make_int2((int)g, (int)q0));
   }
   if ((long long)px.size() > 0x7fffffffLL) return fail(BBFMM_EUNSUPPORTED, "too many M2L pairs");
   p->ngroups = (int)groups.size();
