@@ -243,3 +243,161 @@ def fmm_apply(points, q, order, max_pts, kind="inv_r", c=0.0, max_depth=MAX_DEPT
             kmat[idx[:, None] == jdx[None, :]] = 0.0
             phi[idx] += kmat @ q[jdx]
     return phi, tree
+
+
+def _leaves_adjacent(tree: AdaptiveTree, k: int) -> List[int]:
+    """U(k) of `lists` for one leaf, without scanning every cell: a leaf no finer than k that
+    touches k is a colleague of k's ancestor at its level; a finer one lies below a non-leaf
+    colleague of k, along cells that all touch k. Ascending cell order, as `lists`."""
+    cells = tree.cells
+    c = cells[k]
+    out = set()
+    a = k
+    while a >= 0:
+        for y in colleagues(tree, a):
+            if cells[y].leaf and adjacent(cells[y], c):
+                out.add(y)
+        a = cells[a].parent
+    stack = [y for y in colleagues(tree, k) if y != k and not cells[y].leaf]
+    while stack:
+        y = stack.pop()
+        for ch in cells[y].children:
+            if adjacent(cells[ch], c):
+                if cells[ch].leaf:
+                    out.add(ch)
+                else:
+                    stack.append(ch)
+    return sorted(out)
+
+
+def _w_list(tree: AdaptiveTree, k: int) -> List[int]:
+    """W(k) of `lists` for one leaf (the same descent, the same order)."""
+    cells = tree.cells
+    c = cells[k]
+    w = []
+    stack = [y for y in colleagues(tree, k) if y != k and not cells[y].leaf]
+    while stack:
+        y = stack.pop()
+        for ch in cells[y].children:
+            if adjacent(cells[ch], c):
+                if not cells[ch].leaf:
+                    stack.append(ch)
+            else:
+                w.append(ch)
+    return w
+
+
+def _v_list(tree: AdaptiveTree, k: int) -> List[int]:
+    """V(k) of `lists` (the same order)."""
+    cells = tree.cells
+    c = cells[k]
+    if c.parent < 0:
+        return []
+    return [ch for pc in colleagues(tree, c.parent) for ch in cells[pc].children if not adjacent(cells[ch], c)]
+
+
+def _x_list(tree: AdaptiveTree, k: int) -> List[int]:
+    """X(k) of `lists`: the leaves b with k in W(b). Such a b is a colleague of k's ancestor C at
+    b's level, other than C, coarser than k, touching parent(k) (so the descent from C reaches
+    parent(k)) and not touching k. Ascending order of b, as `lists`."""
+    cells = tree.cells
+    c = cells[k]
+    if c.parent < 0:
+        return []
+    par = cells[c.parent]
+    out = set()
+    a = c.parent
+    while a >= 0:
+        for y in colleagues(tree, a):
+            if y != a and cells[y].leaf and adjacent(cells[y], par) and not adjacent(cells[y], c):
+                out.add(y)
+        a = cells[a].parent
+    return sorted(out)
+
+
+def fmm_apply_sampled(points, q, order, max_pts, targets, kind="inv_r", c=0.0, max_depth=MAX_DEPTH,
+                      lo=None, width=None, tree: Optional[AdaptiveTree] = None, batch: int = 64,
+                      chunk: int = 1 << 16):
+    """phi of `fmm_apply` (full rank) at the selected targets only, (len(targets), nrhs), for
+    point sets too large for the full sweep.
+
+    The passes of `fmm_apply` evaluated only where the targets need them. M2M (Eq. m2m_bbfmm) and
+    L2L (Eq. l2l_bbfmm) re-interpolate at a finer or coarser cell's Chebyshev nodes, and an order-l
+    interpolant reproduces the degree-(l-1) polynomials it is applied to, so both chains are exact
+    up to rounding: a cell's multipole is its points' P2M at its own level, and a target receives
+    the local expansion of every cell on its leaf's ancestor chain evaluated at the target in that
+    cell's basis. Per chain cell A: M2L over V(A) with K_t formed per t at A's width, P2L over
+    X(A); at the target: those locals, M2P over W(leaf) and the near field over U(leaf), j != i.
+    The lists are those of `lists`, built per cell. Work goes level by level and in batches of
+    chain cells, so only a batch's source multipoles are held."""
+    points = np.ascontiguousarray(points, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    if q.ndim == 1:
+        q = q[:, None]
+    targets = np.asarray(targets, dtype=np.int64)
+    tree = build(points, max_pts, max_depth, lo, width) if tree is None else tree
+    cells = tree.cells
+    nn, nrhs = order ** 3, q.shape[1]
+
+    def local_coords(k, idx):
+        cc = cells[k]
+        return (points[idx] - tree.center(cc)[None, :]) / (0.5 * tree.cell_width(cc))
+
+    def nodes(k):
+        cc = cells[k]
+        return O.cell_nodes(tree.center(cc), tree.cell_width(cc), order)
+
+    def multipole(k):
+        idx = cells[k].points
+        m = np.zeros((nn, nrhs))
+        for s0 in range(0, idx.size, chunk):
+            part = idx[s0:s0 + chunk]
+            m += O.tensor_basis(local_coords(k, part), order).T @ q[part]
+        return m
+
+    leaf = tree.leaf_of_point[targets]
+    # ancestor chains (leaf included) and the targets below each chain cell
+    below: Dict[int, List[int]] = {}
+    for ti, b in enumerate(leaf):
+        a = int(b)
+        while a >= 0:
+            below.setdefault(a, []).append(ti)
+            a = cells[a].parent
+    phi = np.zeros((targets.size, nrhs))
+    by_level: Dict[int, List[int]] = {}
+    for a in sorted(below):
+        by_level.setdefault(cells[a].level, []).append(a)
+    for lev in sorted(by_level):
+        ops: Dict[Tuple[int, int, int], np.ndarray] = {}
+        chain = by_level[lev]
+        for b0 in range(0, len(chain), batch):
+            part = chain[b0:b0 + batch]
+            vl = {a: _v_list(tree, a) for a in part}
+            mult = {y: multipole(y) for y in sorted({y for a in part for y in vl[a]})}
+            for a in part:
+                ca = cells[a]
+                wa = tree.cell_width(ca)
+                loc = np.zeros((nn, nrhs))
+                for y in vl[a]:                                                  # M2L over V
+                    t = tuple(int(ca.ijk[r] - cells[y].ijk[r]) for r in range(3))
+                    if t not in ops:
+                        ops[t] = O.m2l_operator(np.asarray(t), wa, order, kind, c)
+                    loc += ops[t] @ mult[y]
+                xs = None
+                for bx in _x_list(tree, a):                                      # P2L over X
+                    xs = nodes(a) if xs is None else xs
+                    idx = cells[bx].points
+                    loc += O.kernel(kind, xs[:, None, :], points[idx][None, :, :], c) @ q[idx]
+                tis = np.asarray(below[a])
+                phi[tis] += np.einsum("nb,br->nr", O.tensor_basis(local_coords(a, targets[tis]), order), loc)
+            del mult
+    for ti, (i, b) in enumerate(zip(targets, leaf)):
+        x = points[i][None, :]
+        for y in _w_list(tree, int(b)):                                          # M2P over W
+            phi[ti] += (O.kernel(kind, x[:, None, :], nodes(y)[None, :, :], c) @ multipole(y))[0]
+        for u in _leaves_adjacent(tree, int(b)):                                 # near field
+            jdx = cells[u].points
+            jdx = jdx[jdx != i]
+            if jdx.size:
+                phi[ti] += (O.kernel(kind, x[:, None, :], points[jdx][None, :, :], c) @ q[jdx])[0]
+    return phi, tree

@@ -88,3 +88,35 @@ def test_inverse_r_error_small_and_falls_with_order():
     errs = [O.rel_l2(A.fmm_apply(pts, q, order, 24)[0], ref) for order in (3, 5, 7)]
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 1e-5
+
+
+def test_per_cell_lists_equal_the_full_lists():
+    """The list builders of the sampled evaluation (one cell at a time, from colleague
+    relations) give the lists of `lists` exactly, in the same order, on a tree with W and X
+    lists."""
+    pts, _ = clustered(3000, 6)
+    tree = A.build(pts, 12)
+    U, V, W, X = A.lists(tree)
+    assert sum(len(v) for v in W.values()) > 0 and sum(len(v) for v in X.values()) > 0
+    for k, c in enumerate(tree.cells):
+        if c.parent >= 0:
+            assert A._v_list(tree, k) == V[k], ("V", k)
+        assert A._x_list(tree, k) == sorted(X.get(k, [])), ("X", k)
+        if c.leaf:
+            assert A._leaves_adjacent(tree, k) == U[k], ("U", k)
+            assert A._w_list(tree, k) == W[k], ("W", k)
+
+
+@pytest.mark.parametrize("kind", ["inv_r", "r2"])
+def test_sampled_evaluation_equals_the_full_sweep(kind):
+    """The sampled-target evaluation (multipoles by P2M at each cell's own level, ancestor
+    locals evaluated at the target) equals the full sweep's M2M / L2L chains at the targets:
+    they differ only by rounding, since both chains re-interpolate polynomials exactly; for the
+    polynomial kernel |x-y|^2 both reproduce the direct sum."""
+    pts, q = clustered(3000, 7)
+    tg = np.random.default_rng(8).choice(3000, 150, replace=False)
+    full, tree = A.fmm_apply(pts, q, 4, 12, kind)
+    samp, _ = A.fmm_apply_sampled(pts, q, 4, 12, tg, kind, tree=tree)
+    assert O.rel_l2(samp, full[tg]) < 1e-13
+    if kind == "r2":
+        assert O.rel_l2(samp, O.brute_force(pts, q, kind, targets=tg)) < 1e-12
