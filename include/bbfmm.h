@@ -313,8 +313,10 @@ const char* bbfmm_version(void);
  *  - the M2L uses K(xbar_a, ybar_b) itself, so K_t = P_t K_p(t) P_t^T with the symmetries of
  *    Sec. 4.2.1 for every t of the (larger) high-frequency lists; the pairs of a level are
  *    grouped by representative p(t) = sorted |t| (Table size_T_all's |T_sym|) and each group is
- *    one complex FP64 MFMA product, its columns added into the targets' locals with atomics
- *    (results agree with any other summation order to rounding, not bitwise).
+ *    one complex FP64 MFMA product; every pair's product goes to a slot of its own and each
+ *    target's locals are the sum of its pairs' slots in a fixed order, so a plan's result is the
+ *    same bit for bit on every call. The plan holds far_pairs x l^3 complex slots (about 4.9 GB
+ *    for 2.45M pairs at order 5; `device_bytes` counts them).
  * The kernel at r = 0 between distinct points contributes ik (the limit of its smooth part);
  * i = j is excluded.
  * --------------------------------------------------------------------------------------- */
