@@ -348,12 +348,18 @@ def fmm_apply_sampled(points, q, order, max_pts, targets, kind="inv_r", c=0.0, m
         return O.cell_nodes(tree.center(cc), tree.cell_width(cc), order)
 
     def multipole(k):
+        # P2M, sum_j S(x_j, xbar_a) q_j with S the product of the three 1-D Lagrange bases,
+        # contracted as (B1 B2)^T (B0 q): index a0 + l a1 + l^2 a2 as `tensor_basis`
         idx = cells[k].points
-        m = np.zeros((nn, nrhs))
+        m = np.zeros((order * order, order * nrhs))
         for s0 in range(0, idx.size, chunk):
             part = idx[s0:s0 + chunk]
-            m += O.tensor_basis(local_coords(k, part), order).T @ q[part]
-        return m
+            u = local_coords(k, part)
+            b0, b1, b2 = (O.lagrange_basis(u[:, r], order) for r in range(3))
+            b12 = (b2[:, :, None] * b1[:, None, :]).reshape(part.size, order * order)
+            b0q = (b0[:, :, None] * q[part][:, None, :]).reshape(part.size, order * nrhs)
+            m += b12.T @ b0q
+        return m.reshape(nn, nrhs)
 
     leaf = tree.leaf_of_point[targets]
     # ancestor chains (leaf included) and the targets below each chain cell
@@ -374,15 +380,23 @@ def fmm_apply_sampled(points, q, order, max_pts, targets, kind="inv_r", c=0.0, m
             part = chain[b0:b0 + batch]
             vl = {a: _v_list(tree, a) for a in part}
             mult = {y: multipole(y) for y in sorted({y for a in part for y in vl[a]})}
+            # M2L over V, the batch's pairs grouped by t: one product K_t [w_y1 w_y2 ...] per t
+            by_t: Dict[Tuple[int, int, int], List[Tuple[int, int]]] = {}
+            for a in part:
+                for y in vl[a]:
+                    t = tuple(int(cells[a].ijk[r] - cells[y].ijk[r]) for r in range(3))
+                    by_t.setdefault(t, []).append((a, y))
+            locs = {a: np.zeros((nn, nrhs)) for a in part}
+            wl = tree.cell_width(cells[part[0]])
+            for t, prs in by_t.items():
+                if t not in ops:
+                    ops[t] = O.m2l_operator(np.asarray(t), wl, order, kind, c)
+                prod = ops[t] @ np.concatenate([mult[y] for _, y in prs], axis=1)
+                for n, (a, _) in enumerate(prs):
+                    locs[a] += prod[:, n * nrhs:(n + 1) * nrhs]
             for a in part:
                 ca = cells[a]
-                wa = tree.cell_width(ca)
-                loc = np.zeros((nn, nrhs))
-                for y in vl[a]:                                                  # M2L over V
-                    t = tuple(int(ca.ijk[r] - cells[y].ijk[r]) for r in range(3))
-                    if t not in ops:
-                        ops[t] = O.m2l_operator(np.asarray(t), wa, order, kind, c)
-                    loc += ops[t] @ mult[y]
+                loc = locs[a]
                 xs = None
                 for bx in _x_list(tree, a):                                      # P2L over X
                     xs = nodes(a) if xs is None else xs
