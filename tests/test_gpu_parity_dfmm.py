@@ -49,6 +49,9 @@ CASES = [
     ("lf_cube_p4_d3", "cube", 1500, 3.0, 4, 3),           # every level low-frequency
     ("hf_cube_p5_d3", "cube", 800, 12.0, 5, 3),           # a full cube at kw = 3, 1.5
     ("near_only_d1", "cube", 300, 10.0, 4, 1),            # no far field
+    ("hf_sphere_p2_d4", "sphere", 1000, 20.0, 2, 4),      # the smallest order
+    ("hf_sphere_p6_d4", "sphere", 1200, 20.0, 6, 4),      # tiles of 64 pairs, row blocks over 2 waves
+    ("hf_cube_p7_d3", "cube", 700, 12.0, 7, 3),           # the largest order: chunks of 16 columns
 ]
 
 
