@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <exception>
 #include <numeric>
 #include <thread>
 
@@ -71,15 +72,25 @@ bool touch(int la, const long long* a, int lb, const long long* b) {
 }
 
 // Runs fn(part, begin, end) over [0, n) cut into contiguous parts, one thread each; the parts are
-// in index order, so per-part outputs concatenated in part order equal the serial output.
+// in index order, so per-part outputs concatenated in part order equal the serial output. An
+// exception thrown in a part (std::bad_alloc) is rethrown here after every thread has joined.
 template <typename Fn>
 void parallel_parts(long long n, int parts, Fn fn) {
   std::vector<std::thread> th;
+  std::vector<std::exception_ptr> err(parts);
   for (int t = 0; t < parts; ++t) {
     const long long b = n * t / parts, e = n * (t + 1) / parts;
-    th.emplace_back([=, &fn]() { fn(t, b, e); });
+    th.emplace_back([=, &fn, &err]() {
+      try {
+        fn(t, b, e);
+      } catch (...) {
+        err[t] = std::current_exception();
+      }
+    });
   }
   for (auto& x : th) x.join();
+  for (auto& x : err)
+    if (x) std::rethrow_exception(x);
 }
 
 int host_threads() {

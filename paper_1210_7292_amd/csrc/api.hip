@@ -587,7 +587,12 @@ bbfmm_status build_adaptive(std::unique_ptr<bbfmm_tree>& t, const double* d_poin
   cleanup();
   std::vector<int> grp;
   const std::vector<int> tab = octant_tables(&grp);
-  build_adaptive_topology(t->topo, hkeys, hstart, hend, max_pts, t->lo, t->width, tab.data());
+  try {
+    build_adaptive_topology(t->topo, hkeys, hstart, hend, max_pts, t->lo, t->width, tab.data());
+  } catch (const std::bad_alloc&) {
+    free_tree_arrays(t.get());
+    return fail(BBFMM_ENOMEM, "adaptive tree lists: host memory exhausted");
+  }
   t->depth = t->topo.nlevels - 1;
   if ((e = upload_topology(t.get(), &bytes)) != hipSuccess) {
     free_tree_arrays(t.get());
@@ -1524,7 +1529,11 @@ bbfmm_status bbfmm_host_adaptive_tree(const double* points, int64_t n, int32_t m
   t->max_leaf_points = max_leaf_points;
   std::vector<int> grp;
   const std::vector<int> tab = octant_tables(&grp);
-  host_adaptive_build(points, n, max_leaf_points, t->lo, t->width, tab.data(), t->topo, t->host_perm);
+  try {
+    host_adaptive_build(points, n, max_leaf_points, t->lo, t->width, tab.data(), t->topo, t->host_perm);
+  } catch (const std::bad_alloc&) {
+    return fail(BBFMM_ENOMEM, "host adaptive tree: host memory exhausted");
+  }
   t->depth = t->topo.nlevels - 1;
   *out = t.release();
   return BBFMM_OK;
