@@ -754,8 +754,7 @@ void bbfmm_tree_destroy(bbfmm_tree* t) {
   delete t;
 }
 
-bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts* opts,
-                                  void* stream, bbfmm_plan** out) {
+static bbfmm_status bbfmm_precompute_m2l_body(const bbfmm_tree* tree, const bbfmm_plan_opts* opts, void* stream, bbfmm_plan** out) {
   if (!out) return fail(BBFMM_EINVAL, "out is null");
   *out = nullptr;
   if (!tree || !opts) return fail(BBFMM_EINVAL, "null tree or options");
@@ -1044,6 +1043,18 @@ bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts*
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = p.release();
   return BBFMM_OK;
+}
+
+// Host allocations of the precompute that fail (std::bad_alloc) return BBFMM_ENOMEM rather than
+// crossing the C ABI; device allocations report their own errors.
+bbfmm_status bbfmm_precompute_m2l(const bbfmm_tree* tree, const bbfmm_plan_opts* opts,
+                                  void* stream, bbfmm_plan** out) {
+  try {
+    return bbfmm_precompute_m2l_body(tree, opts, stream, out);
+  } catch (const std::bad_alloc&) {
+    if (out) *out = nullptr;
+    return fail(BBFMM_ENOMEM, "operator precompute: host memory exhausted");
+  }
 }
 
 void bbfmm_plan_destroy(bbfmm_plan* p) {

@@ -796,8 +796,7 @@ hipError_t upload(T** d, const std::vector<T>& h, long long* bytes) {
 
 extern "C" {
 
-bbfmm_status bbfmm_dfmm_precompute(const bbfmm_tree* tree, double k, int32_t order, void* stream,
-                                   bbfmm_dfmm** out) {
+static bbfmm_status bbfmm_dfmm_precompute_body(const bbfmm_tree* tree, double k, int32_t order, void* stream, bbfmm_dfmm** out) {
   if (!out) return fail(BBFMM_EINVAL, "out is null");
   *out = nullptr;
   if (!tree) return fail(BBFMM_EINVAL, "tree is null");
@@ -1081,6 +1080,18 @@ bbfmm_status bbfmm_dfmm_precompute(const bbfmm_tree* tree, double k, int32_t ord
   p->precompute_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = p.release();
   return BBFMM_OK;
+}
+
+// Host allocations of the precompute that fail (std::bad_alloc) return BBFMM_ENOMEM rather than
+// crossing the C ABI; device allocations report their own errors.
+bbfmm_status bbfmm_dfmm_precompute(const bbfmm_tree* tree, double k, int32_t order, void* stream,
+                                   bbfmm_dfmm** out) {
+  try {
+    return bbfmm_dfmm_precompute_body(tree, k, order, stream, out);
+  } catch (const std::bad_alloc&) {
+    if (out) *out = nullptr;
+    return fail(BBFMM_ENOMEM, "dFMM lists and operators: host memory exhausted");
+  }
 }
 
 bbfmm_status bbfmm_dfmm_stats_of(const bbfmm_dfmm* p, bbfmm_dfmm_stats* out) {
