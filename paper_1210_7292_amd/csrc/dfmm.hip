@@ -288,11 +288,12 @@ struct DM2L {
 };
 
 template <int L> constexpr int dfmm_kc() { return L >= 7 ? 16 : 32; }
-template <int L> constexpr int dfmm_rs() { return L >= 6 ? 2 : 1; }
-// column waves of a workgroup: 16 pairs each; up to order 5 eight (128 pairs share each staged
-// operator chunk), above four (the row blocks are split over two waves instead)
-template <int L> constexpr int dfmm_cw() { return L <= 5 ? 8 : 4; }
-inline int dfmm_pairs_per_block(int order) { return order <= 5 ? 128 : 64; }
+// row groups and column waves (16 pairs each) of a workgroup: up to order 5 one row group and
+// eight column waves (128 pairs share each staged operator chunk); order 6 two and four; order 7
+// four and two (rows padded to 384 so the real and imaginary accumulators of 6 row blocks fit)
+template <int L> constexpr int dfmm_rs() { return L >= 7 ? 4 : (L == 6 ? 2 : 1); }
+template <int L> constexpr int dfmm_cw() { return L <= 5 ? 8 : (L == 6 ? 4 : 2); }
+constexpr int dfmm_pairs_per_block(int order) { return order <= 5 ? 128 : (order == 6 ? 64 : 32); }
 
 // Wave w owns pair columns 16 (w % CW) .. +16 and row blocks (w / CW) MB/RS .. +MB/RS. Lane
 // (j = l % 16, kq = l / 16) supplies A = K_p[16 m + j][k] and B = W_Y[sigma^-1(k)] of its
@@ -301,9 +302,8 @@ template <int L, int RS, int CW>
 __global__ __launch_bounds__(64 * CW * RS) void dfmm_m2l_kernel(DM2L a) {
   constexpr int NT = 64 * CW * RS;
   constexpr int NN = L * L * L;
-  constexpr int NP = (NN + 15) / 16 * 16;
-  constexpr int MB = NP / 16;
-  static_assert(MB % RS == 0, "row blocks split evenly");
+  constexpr int NP = (NN + 15) / 16 * 16;          // rows of the sigma tables
+  constexpr int MB = (NP / 16 + RS - 1) / RS * RS;  // row blocks, padded to split evenly
   constexpr int MBW = MB / RS;
   constexpr int KC = dfmm_kc<L>();
   constexpr int LDK = KC + 1;
@@ -598,7 +598,7 @@ template <int L> struct DRun {
   static hipError_t m2l(const DM2L& a, int nblocks, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
     constexpr int RS = dfmm_rs<L>(), CW = dfmm_cw<L>();
-    static_assert(16 * CW == (L <= 5 ? 128 : 64), "tiles of the host's block list");
+    static_assert(16 * CW == dfmm_pairs_per_block(L), "tiles of the host's block list");
     hipLaunchKernelGGL((dfmm_m2l_kernel<L, RS, CW>), dim3(nblocks), dim3(64 * CW * RS), 0, s, a);
     return hipGetLastError();
   }
