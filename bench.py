@@ -277,23 +277,38 @@ def run_helmholtz(args):
     print(json.dumps(line))
 
 
+# the paper's three point sets for the dFMM (Sec. 5): random points on a sphere, an oblate and a
+# prolate spheroid, bounding boxes 64 x 64 x 64, 6.4 x 64 x 64 and 6.4 x 6.4 x 64 at k = 1, with
+# their point counts and levels; here scaled into the unit cube with k = 64 (the same k w per
+# level): semi-axes 0.45 x (box / 64)
+DFMM_GEOMETRIES = {
+    "sphere": ((0.45, 0.45, 0.45), 168_931, 6),
+    "oblate": ((0.045, 0.45, 0.45), 125_931, 6),
+    "prolate": ((0.045, 0.045, 0.45), 119_698, 7),
+}
+
+
 def run_dfmm(args):
-    """Directional FMM of e^{ikr}/r (high-frequency regime) on points on a sphere: the paper's
-    sphere set-up (random points on a sphere surface in a bounding cube 64 wavelengths/2pi wide,
-    k = 1, 6 levels), here N points on a sphere of radius 0.45 in the unit cube with k = 64
-    (the same k w per level), order `--dfmm-order`. Prints one JSON line: points/s of one complex
-    apply, M2L GFLOP/s (8 l^6 flops per far pair) against the FP64 MFMA peak, the per-level list
-    sizes (|T|, |T_sym|, cones) and the error against the direct sum."""
+    """Directional FMM of e^{ikr}/r (high-frequency regime) on points on a surface: the paper's
+    set-ups (random points on a sphere or spheroid surface in a bounding box up to 64
+    wavelengths/2pi wide, k = 1), here in the unit cube with k = 64 (the same k w per level),
+    order `--dfmm-order`; the points are normalised Gaussian draws scaled by the semi-axes. Prints
+    one JSON line: points/s of one complex apply, M2L GFLOP/s (8 l^6 flops per far pair) against
+    the FP64 MFMA peak, the per-level list sizes (|T|, |T_sym|, cones) and the error against the
+    direct sum."""
     import numpy as np
     import torch
 
     import paper_1210_7292_amd as pk
 
     dev = torch.device("cuda:0")
-    n, k, order, depth = args.dfmm_n, float(args.dfmm), args.dfmm_order, args.dfmm_depth
+    axes, n_paper, depth_paper = DFMM_GEOMETRIES[args.dfmm_geometry]
+    n = args.dfmm_n if args.dfmm_n is not None else n_paper
+    depth = args.dfmm_depth if args.dfmm_depth is not None else depth_paper
+    k, order = float(args.dfmm), args.dfmm_order
     rng = np.random.default_rng(1210729200 + 40)
     g = rng.standard_normal((n, 3))
-    pts_h = 0.5 + 0.45 * g / np.linalg.norm(g, axis=1, keepdims=True)
+    pts_h = 0.5 + np.asarray(axes)[None, :] * g / np.linalg.norm(g, axis=1, keepdims=True)
     q_h = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
     tg = rng.choice(n, 256, replace=False)
     pts = torch.from_numpy(pts_h).to(dev)
@@ -340,9 +355,9 @@ def run_dfmm(args):
         "value": n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"sphere{n}_helmholtz_k{k:g}_p{order}_d{depth}", "n_points": n,
+        "config": {"workload": f"{args.dfmm_geometry}{n}_helmholtz_k{k:g}_p{order}_d{depth}", "n_points": n,
                    "kernel": "e^{ikr}/r", "wavenumber": k, "order": order, "depth": depth,
-                   "geometry": "random points on a sphere of radius 0.45 (unit cube root)"},
+                   "geometry": f"random points on a {args.dfmm_geometry} of semi-axes {axes} (unit cube root)"},
         "m2l_ms": m2l_ms, "m2l_gflops": achieved * 1e3,
         "roofline": {"bound": "mfma", "kernel": "dfmm_m2l", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s",
                      "frac": achieved / 78.6, "traffic": None},
@@ -382,9 +397,11 @@ def main():
                          "workload's points")
     ap.add_argument("--dfmm", type=float, default=None, metavar="K",
                     help="instead: the directional FMM of e^{ikr}/r with wavenumber K on points on a sphere")
-    ap.add_argument("--dfmm-n", type=int, default=168_931, help="dFMM points (default: the paper's sphere count)")
+    ap.add_argument("--dfmm-geometry", default="sphere", choices=tuple(DFMM_GEOMETRIES),
+                    help="the paper's dFMM point sets: sphere, oblate or prolate spheroid")
+    ap.add_argument("--dfmm-n", type=int, default=None, help="dFMM points (default: the paper's count for the geometry)")
     ap.add_argument("--dfmm-order", type=int, default=5)
-    ap.add_argument("--dfmm-depth", type=int, default=6)
+    ap.add_argument("--dfmm-depth", type=int, default=None, help="default: the paper's levels for the geometry")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

@@ -36,10 +36,13 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def sphere(n, seed, radius=0.45):
+def sphere(n, seed, radius=0.45, axes=None):
+    """Points on a sphere of the given radius (or a spheroid of the given semi-axes) centred in
+    the unit cube."""
     rng = np.random.default_rng(seed)
     g = rng.standard_normal((n, 3))
-    return 0.5 + radius * g / np.linalg.norm(g, axis=1, keepdims=True), rng
+    scale = radius if axes is None else np.asarray(axes)[None, :]
+    return 0.5 + scale * g / np.linalg.norm(g, axis=1, keepdims=True), rng
 
 
 CASES = [
@@ -52,6 +55,8 @@ CASES = [
     ("hf_sphere_p2_d4", "sphere", 1000, 20.0, 2, 4),      # the smallest order
     ("hf_sphere_p6_d4", "sphere", 1200, 20.0, 6, 4),      # tiles of 64 pairs, row blocks over 2 waves
     ("hf_cube_p7_d3", "cube", 700, 12.0, 7, 3),           # the largest order: chunks of 16 columns
+    ("hf_oblate_p4_d4", "oblate", 1200, 20.0, 4, 4),      # the paper's oblate spheroid (10:1)
+    ("hf_prolate_p3_d5", "prolate", 1200, 20.0, 3, 5),    # and prolate one
 ]
 
 
@@ -60,6 +65,8 @@ def test_dfmm_apply_matches_oracle(name, geom, n, k, order, depth):
     say("dfmm", name)
     if geom == "sphere":
         pts, rng = sphere(n, 51)
+    elif geom in ("oblate", "prolate"):
+        pts, rng = sphere(n, 54, axes=(0.045, 0.45, 0.45) if geom == "oblate" else (0.045, 0.045, 0.45))
     else:
         rng = np.random.default_rng(52)
         pts = rng.random((n, 3))
