@@ -49,7 +49,7 @@ PassGeom geom_of(const bbfmm_plan* pl) {
   g.n = t->n; g.depth = t->depth;
   for (int r = 0; r < 3; ++r) g.lo[r] = t->lo[r];
   g.width = t->width;
-  g.tk = pl->d_tk; g.m2m = pl->d_m2m;
+  g.tk = pl->d_tk; g.m2m = pl->d_m2m; g.h_m2m = pl->h_m2m.data();
   g.order = pl->order; g.kernel = pl->kernel; g.c = pl->c;
   return g;
 }
@@ -959,6 +959,7 @@ static bbfmm_status bbfmm_precompute_m2l_body(const bbfmm_tree* tree, const bbfm
   if (e == hipSuccess) e = up((void**)&p->d_siginv, siginv.data(), siginv.size() * sizeof(short));
   if (e == hipSuccess) e = up((void**)&p->d_tk, tk.data(), tk.size() * sizeof(double));
   if (e == hipSuccess) e = up((void**)&p->d_m2m, m2m.data(), m2m.size() * sizeof(double));
+  p->h_m2m = m2m;
   const std::vector<double> zeros((size_t)nn * kMaxRhs, 0.0);
   if (e == hipSuccess) e = up((void**)&p->d_zeros, zeros.data(), zeros.size() * sizeof(double));
   if (e == hipSuccess && p->variant != BBFMM_VARIANT_BLOCKED) {

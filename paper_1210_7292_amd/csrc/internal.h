@@ -216,6 +216,7 @@ struct PassGeom {
   long long n; int depth; double lo[3]; double width;
   const double* tk;      // T_k(xhat_m) [k][m], order x order
   const double* m2m;     // [2][order][order]: S(child node b' of octant bit s, parent node B)
+  const double* h_m2m;   // host copy of m2m (passed by value to the M2M / L2L kernels)
   int order; int kernel; double c;
 };
 hipError_t launch_gather_rows(const double* in, const int* perm, long long n, int nrhs,
@@ -329,6 +330,7 @@ struct bbfmm_plan {
   long long* d_op_off = nullptr; int* d_op_rank = nullptr;
   int* d_tab = nullptr; int* d_grp = nullptr; short* d_sig = nullptr; short* d_siginv = nullptr;
   double* d_tk = nullptr; double* d_m2m = nullptr;
+  std::vector<double> h_m2m;
   double* d_zeros = nullptr;
   std::vector<int> h_tab, h_grp;
   // work buffers

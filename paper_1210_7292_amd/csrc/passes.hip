@@ -166,17 +166,23 @@ struct PassIter {
   }
 };
 
+// The 2 l^2 entries of the interpolation from a child's nodes to its parent's, passed by value:
+// the contractions index them with compile-time offsets, so they come from the kernel-argument
+// segment through scalar registers and the LDS serves only the expansions.
+template <int L> struct M2MMat { double m[2 * L * L]; };   // [bit][child node b][parent node B]
+
 template <int L>
-__global__ __launch_bounds__(kM2MThreads) void m2m_kernel(PassGeom g, int parent_level,
+__global__ __launch_bounds__(kM2MThreads) void m2m_kernel(M2MMat<L> S, int parent_level,
                                                           const double* __restrict__ Wc,
                                                           double* __restrict__ Wp, int nrhs) {
-  constexpr int NN = L * L * L, NV = m2m_nv<L>(), TOT = NV * 8 * NN;
+  constexpr int NN = L * L * L, LL = L * L, NV = m2m_nv<L>(), TOT = NV * 8 * NN;
   constexpr int PER = (TOT + kM2MThreads - 1) / kM2MThreads;
-  __shared__ double sM[2 * L * L];   // [bit][child node b][parent node B]
-  __shared__ double X[TOT];          // children [v][c][b]; later the y stage [v][cz][..]
-  __shared__ double T[NV * 4 * NN];  // x stage [v][cy + 2 cz][B0 + L b1 + L^2 b2]
-  const int tid = threadIdx.x;
-  for (int i = tid; i < 2 * L * L; i += kM2MThreads) sM[i] = g.m2m[i];
+  constexpr int RX = (NV * 4 * LL + kM2MThreads - 1) / kM2MThreads;   // lines per thread, x stage
+  constexpr int RY = (NV * 2 * LL + kM2MThreads - 1) / kM2MThreads;   // y stage
+  constexpr int RZ = (NV * LL + kM2MThreads - 1) / kM2MThreads;       // z stage
+  // children [v][c][b]; each stage reads its lines into registers, then overwrites the array
+  // in place: the x stage as [v][cy + 2 cz][B0 + L b1 + L^2 b2], the y stage as [v][cz][..]
+  __shared__ double X[TOT];
   // a block owns PG whole parents and takes their (parent, rhs) vectors NV at a time, so the
   // right-hand sides of a parent share one L2
   const long long npar = 1ll << (3 * parent_level);
@@ -184,14 +190,24 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(PassGeom g, int parent
   for (long long gi = it.first(); gi < it.count; gi += gridDim.x) {
     int nv;
     const long long v0 = it.vectors(gi, nv);   // vectors v0 .. v0 + nv - 1, v = P * nrhs + r
+    // An offset that is zero but depends on the item: through it the matrix entries are loaded
+    // where they are used, and the per-thread indices are computed per item, instead of all being
+    // hoisted out of the loop (which runs about once per workgroup) into registers.
+    const int z = (int)(gi >> 48), tid = threadIdx.x + z;
+    const double* Sm = S.m + z;
+    // vector v0 + vl is right-hand side (r0 + vl) % nrhs of parent P0 + (r0 + vl) / nrhs
+    const long long P0 = v0 / nrhs;
+    const int r0 = (int)(v0 - P0 * nrhs);
+    const double* Wc0 = Wc + P0 * 8 * NN * nrhs;
+    double* Wp0 = Wp + P0 * NN * nrhs;
     double t[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int idx = tid + u * kM2MThreads;
       const int vl = idx / (8 * NN), rest = idx - vl * 8 * NN;
-      const long long v = v0 + vl, P = v / nrhs;
-      const int r = (int)(v - P * nrhs);
-      t[u] = (idx < TOT && vl < nv) ? Wc[(P * 8 * NN + rest) * nrhs + r] : 0.0;
+      const int q = r0 + vl, dp = q / nrhs;
+      const unsigned o = (unsigned)((dp * 8 * NN + rest) * nrhs + (q - dp * nrhs));
+      t[u] = (idx < TOT && vl < nv) ? Wc0[o] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -200,124 +216,236 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(PassGeom g, int parent
       if (idx < TOT) X[idx] = t[u];
     }
     __syncthreads();
-    for (int idx = tid; idx < NV * 4 * NN; idx += kM2MThreads) {
-      const int v = idx / (4 * NN), rem = idx - v * 4 * NN, cyz = rem / NN, beta = rem - cyz * NN;
-      const int B0 = beta % L, rest = beta / L;
-      double a = 0.0;
+    // x: a line (v, cy + 2 cz, b1 + L b2) holds children cx = 0, 1 along b0 and gives L nodes B0
+    {
+      double in[RX][2 * L];
 #pragma unroll
-      for (int cx = 0; cx < 2; ++cx) {
-        const double* src = X + (v * 8 + cx + 2 * cyz) * NN + L * rest;
-        const double* M = sM + cx * L * L;
+      for (int k = 0; k < RX; ++k) {
+        // lanes past the last line read line 0 (always present) and discard it
+        const int ln = tid + k * kM2MThreads < nv * 4 * LL ? tid + k * kM2MThreads : 0;
+        const int v = ln / (4 * LL), rem = ln - v * 4 * LL, cyz = rem / LL, rest = rem - cyz * LL;
+        const double* src = X + (v * 8 + 2 * cyz) * NN + L * rest;
 #pragma unroll
-        for (int b0 = 0; b0 < L; ++b0) a += M[b0 * L + B0] * src[b0];
+        for (int b0 = 0; b0 < L; ++b0) { in[k][b0] = src[b0]; in[k][L + b0] = src[NN + b0]; }
       }
-      T[idx] = a;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < RX; ++k) {
+        const int ln = tid + k * kM2MThreads;
+        if (ln >= nv * 4 * LL) continue;
+        const int v = ln / (4 * LL), rem = ln - v * 4 * LL, cyz = rem / LL, rest = rem - cyz * LL;
+        double* dst = X + (v * 4 + cyz) * NN + L * rest;
+        double a[L];
+#pragma unroll
+        for (int B0 = 0; B0 < L; ++B0) a[B0] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 2 * L; ++j)   // j = cx L + b0: one row of the matrix at a time
+#pragma unroll
+          for (int B0 = 0; B0 < L; ++B0) a[B0] += Sm[j * L + B0] * in[k][j];
+#pragma unroll
+        for (int B0 = 0; B0 < L; ++B0) dst[B0] = a[B0];
+      }
     }
     __syncthreads();
-    for (int idx = tid; idx < NV * 2 * NN; idx += kM2MThreads) {
-      const int v = idx / (2 * NN), rem = idx - v * 2 * NN, cz = rem / NN, beta = rem - cz * NN;
-      const int B0 = beta % L, B1 = (beta / L) % L, b2 = beta / (L * L);
-      double a = 0.0;
+    // y: a line (v, cz, B0, b2) holds cy = 0, 1 along b1 and gives L nodes B1
+    {
+      double in[RY][2 * L];
 #pragma unroll
-      for (int cy = 0; cy < 2; ++cy) {
-        const double* src = T + (v * 4 + cy + 2 * cz) * NN + B0 + L * L * b2;
-        const double* M = sM + cy * L * L;
+      for (int k = 0; k < RY; ++k) {
+        // lanes past the last line read line 0 (always present) and discard it
+        const int ln = tid + k * kM2MThreads < nv * 2 * LL ? tid + k * kM2MThreads : 0;
+        const int v = ln / (2 * LL), rem = ln - v * 2 * LL, cz = rem / LL, r2 = rem - cz * LL;
+        const int B0 = r2 % L, b2 = r2 / L;
+        const double* src = X + (v * 4 + 2 * cz) * NN + B0 + LL * b2;
 #pragma unroll
-        for (int b1 = 0; b1 < L; ++b1) a += M[b1 * L + B1] * src[L * b1];
+        for (int b1 = 0; b1 < L; ++b1) { in[k][b1] = src[L * b1]; in[k][L + b1] = src[NN + L * b1]; }
       }
-      X[idx] = a;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < RY; ++k) {
+        const int ln = tid + k * kM2MThreads;
+        if (ln >= nv * 2 * LL) continue;
+        const int v = ln / (2 * LL), rem = ln - v * 2 * LL, cz = rem / LL, r2 = rem - cz * LL;
+        const int B0 = r2 % L, b2 = r2 / L;
+        double* dst = X + (v * 2 + cz) * NN + B0 + LL * b2;
+        double a[L];
+#pragma unroll
+        for (int B1 = 0; B1 < L; ++B1) a[B1] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 2 * L; ++j)   // j = cy L + b1
+#pragma unroll
+          for (int B1 = 0; B1 < L; ++B1) a[B1] += Sm[j * L + B1] * in[k][j];
+#pragma unroll
+        for (int B1 = 0; B1 < L; ++B1) dst[L * B1] = a[B1];
+      }
     }
     __syncthreads();
-    for (int idx = tid; idx < nv * NN; idx += kM2MThreads) {
-      const int v = idx / NN, beta = idx - v * NN;
-      const int B0 = beta % L, B1 = (beta / L) % L, B2 = beta / (L * L);
-      double a = 0.0;
+    // z: a line (v, B0 + L B1) holds cz = 0, 1 along b2 and gives the parent's L nodes B2
 #pragma unroll
-      for (int cz = 0; cz < 2; ++cz) {
-        const double* src = X + (v * 2 + cz) * NN + B0 + L * B1;
-        const double* M = sM + cz * L * L;
+    for (int k = 0; k < RZ; ++k) {
+      const int ln = tid + k * kM2MThreads;
+      if (ln >= nv * LL) continue;
+      const int v = ln / LL, r2 = ln - v * LL;
+      const double* src = X + v * 2 * NN + r2;
+      double in[2 * L];
 #pragma unroll
-        for (int b2 = 0; b2 < L; ++b2) a += M[b2 * L + B2] * src[L * L * b2];
-      }
-      const long long vv = v0 + v, P = vv / nrhs;
-      Wp[(P * NN + beta) * nrhs + (vv - P * nrhs)] = a;
+      for (int b2 = 0; b2 < L; ++b2) { in[b2] = src[LL * b2]; in[L + b2] = src[NN + LL * b2]; }
+      const int q = r0 + v, dp = q / nrhs;
+      const unsigned o = (unsigned)((dp * NN + r2) * nrhs + (q - dp * nrhs));
+      double a[L];
+#pragma unroll
+      for (int B2 = 0; B2 < L; ++B2) a[B2] = 0.0;
+#pragma unroll
+      for (int j = 0; j < 2 * L; ++j)   // j = cz L + b2
+#pragma unroll
+        for (int B2 = 0; B2 < L; ++B2) a[B2] += Sm[j * L + B2] * in[j];
+#pragma unroll
+      for (int B2 = 0; B2 < L; ++B2) Wp0[o + (unsigned)(LL * B2 * nrhs)] = a[B2];
     }
   }
 }
 
 template <int L>
-__global__ __launch_bounds__(kM2MThreads) void l2l_kernel(PassGeom g, int parent_level,
+__global__ __launch_bounds__(kM2MThreads) void l2l_kernel(M2MMat<L> S, int parent_level,
                                                           const double* __restrict__ Fp,
                                                           double* __restrict__ Fc, int nrhs) {
-  constexpr int NN = L * L * L, NV = m2m_nv<L>(), TOT = NV * 8 * NN;
+  constexpr int NN = L * L * L, LL = L * L, NV = m2m_nv<L>(), TOT = NV * 8 * NN;
   constexpr int PER = (TOT + kM2MThreads - 1) / kM2MThreads;
-  __shared__ double sM[2 * L * L];
-  __shared__ double A[NV * NN];        // parents [v][B]
-  __shared__ double T2[NV * 2 * NN];   // z stage [v][cz][B0 + L B1 + L^2 b2]
-  __shared__ double T1[NV * 4 * NN];   // y stage [v][cy + 2 cz][B0 + L b1 + L^2 b2]
-  const int tid = threadIdx.x;
-  for (int i = tid; i < 2 * L * L; i += kM2MThreads) sM[i] = g.m2m[i];
+  constexpr int RZ = (NV * LL + kM2MThreads - 1) / kM2MThreads;       // lines per thread, z stage
+  constexpr int RY = (NV * 2 * LL + kM2MThreads - 1) / kM2MThreads;   // y stage
+  constexpr int RX = (NV * 4 * LL + kM2MThreads - 1) / kM2MThreads;   // x stage
+  // parents [v][B] at the front; each stage reads its lines into registers, then overwrites the
+  // array in place: z as [v][cz][B0 + L B1 + L^2 b2], y as [v][cy + 2 cz][..], x as [v][c][b]
+  __shared__ double X[TOT];
   const long long npar = 1ll << (3 * parent_level);
   PassIter it(npar, nrhs, NV);
   for (long long gi = it.first(); gi < it.count; gi += gridDim.x) {
     int nv;
     const long long v0 = it.vectors(gi, nv);
-    // the children's current locals (the M2L result), in flight during the contractions
+    const int z = (int)(gi >> 48), tid = threadIdx.x + z;   // zero; keeps loads and indices per item
+    const double* Sm = S.m + z;
+    // the children's current locals (the M2L result), in flight during the contractions; their
+    // offsets from the first vector's children are small
+    // vector v0 + vl is right-hand side (r0 + vl) % nrhs of parent P0 + (r0 + vl) / nrhs
+    const long long P0 = v0 / nrhs;
+    const int r0 = (int)(v0 - P0 * nrhs);
+    double* Fc0 = Fc + P0 * 8 * NN * nrhs;
+    const double* Fp0 = Fp + P0 * NN * nrhs;
     double old[PER];
-    long long addr[PER];
+    unsigned off[PER];   // ~0u: no child element
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int idx = tid + u * kM2MThreads;
       const int vl = idx / (8 * NN), rest = idx - vl * 8 * NN;
-      const long long v = v0 + vl, P = v / nrhs;
-      addr[u] = (idx < TOT && vl < nv) ? (P * 8 * NN + rest) * nrhs + (v - P * nrhs) : -1;
-      old[u] = addr[u] >= 0 ? Fc[addr[u]] : 0.0;
+      const int q = r0 + vl, dp = q / nrhs;
+      off[u] = (idx < TOT && vl < nv) ? (unsigned)((dp * 8 * NN + rest) * nrhs + (q - dp * nrhs)) : ~0u;
+      old[u] = off[u] != ~0u ? Fc0[off[u]] : 0.0;
     }
     __syncthreads();
     for (int idx = tid; idx < nv * NN; idx += kM2MThreads) {
       const int v = idx / NN, beta = idx - v * NN;
-      const long long vv = v0 + v, P = vv / nrhs;
-      A[idx] = Fp[(P * NN + beta) * nrhs + (vv - P * nrhs)];
+      const int q = r0 + v, dp = q / nrhs;
+      X[idx] = Fp0[(unsigned)((dp * NN + beta) * nrhs + (q - dp * nrhs))];
     }
     __syncthreads();
-    for (int idx = tid; idx < NV * 2 * NN; idx += kM2MThreads) {
-      const int v = idx / (2 * NN), rem = idx - v * 2 * NN, cz = rem / NN, beta = rem - cz * NN;
-      const int B0 = beta % L, B1 = (beta / L) % L, b2 = beta / (L * L);
-      const double* src = A + v * NN + B0 + L * B1;
-      const double* M = sM + cz * L * L + b2 * L;
-      double a = 0.0;
+    // z: a line (v, B0 + L B1) holds the parent's L nodes B2 and gives cz = 0, 1 along b2
+    {
+      double in[RZ][L];
 #pragma unroll
-      for (int B2 = 0; B2 < L; ++B2) a += M[B2] * src[L * L * B2];
-      T2[idx] = a;
+      for (int k = 0; k < RZ; ++k) {
+        // lanes past the last line read line 0 (always present) and discard it
+        const int ln = tid + k * kM2MThreads < nv * LL ? tid + k * kM2MThreads : 0;
+        const int v = ln / LL, r2 = ln - v * LL;
+        const double* src = X + v * NN + r2;
+#pragma unroll
+        for (int B2 = 0; B2 < L; ++B2) in[k][B2] = src[LL * B2];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < RZ; ++k) {
+        const int ln = tid + k * kM2MThreads;
+        if (ln >= nv * LL) continue;
+        const int v = ln / LL, r2 = ln - v * LL;
+        double* dst = X + v * 2 * NN + r2;
+#pragma unroll
+        for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+          for (int b2 = 0; b2 < L; ++b2) {
+            double a = 0.0;
+#pragma unroll
+            for (int B2 = 0; B2 < L; ++B2) a += Sm[(cz * L + b2) * L + B2] * in[k][B2];
+            dst[cz * NN + LL * b2] = a;
+          }
+      }
     }
     __syncthreads();
-    for (int idx = tid; idx < NV * 4 * NN; idx += kM2MThreads) {
-      const int v = idx / (4 * NN), rem = idx - v * 4 * NN, cyz = rem / NN, beta = rem - cyz * NN;
-      const int cy = cyz & 1, cz = cyz >> 1;
-      const int B0 = beta % L, b1 = (beta / L) % L, b2 = beta / (L * L);
-      const double* src = T2 + (v * 2 + cz) * NN + B0 + L * L * b2;
-      const double* M = sM + cy * L * L + b1 * L;
-      double a = 0.0;
+    // y: a line (v, cz, B0, b2) holds L nodes B1 and gives cy = 0, 1 along b1
+    {
+      double in[RY][L];
 #pragma unroll
-      for (int B1 = 0; B1 < L; ++B1) a += M[B1] * src[L * B1];
-      T1[idx] = a;
+      for (int k = 0; k < RY; ++k) {
+        // lanes past the last line read line 0 (always present) and discard it
+        const int ln = tid + k * kM2MThreads < nv * 2 * LL ? tid + k * kM2MThreads : 0;
+        const int v = ln / (2 * LL), rem = ln - v * 2 * LL, cz = rem / LL, r2 = rem - cz * LL;
+        const int B0 = r2 % L, b2 = r2 / L;
+        const double* src = X + (v * 2 + cz) * NN + B0 + LL * b2;
+#pragma unroll
+        for (int B1 = 0; B1 < L; ++B1) in[k][B1] = src[L * B1];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < RY; ++k) {
+        const int ln = tid + k * kM2MThreads;
+        if (ln >= nv * 2 * LL) continue;
+        const int v = ln / (2 * LL), rem = ln - v * 2 * LL, cz = rem / LL, r2 = rem - cz * LL;
+        const int B0 = r2 % L, b2 = r2 / L;
+        double* dst = X + (v * 4 + 2 * cz) * NN + B0 + LL * b2;
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+          for (int b1 = 0; b1 < L; ++b1) {
+            double a = 0.0;
+#pragma unroll
+            for (int B1 = 0; B1 < L; ++B1) a += Sm[(cy * L + b1) * L + B1] * in[k][B1];
+            dst[cy * NN + L * b1] = a;
+          }
+      }
+    }
+    __syncthreads();
+    // x: a line (v, cy + 2 cz, b1 + L b2) holds L nodes B0 and gives cx = 0, 1 along b0
+    {
+      double in[RX][L];
+#pragma unroll
+      for (int k = 0; k < RX; ++k) {
+        // lanes past the last line read line 0 (always present) and discard it
+        const int ln = tid + k * kM2MThreads < nv * 4 * LL ? tid + k * kM2MThreads : 0;
+        const int v = ln / (4 * LL), rem = ln - v * 4 * LL, cyz = rem / LL, rest = rem - cyz * LL;
+        const double* src = X + (v * 4 + cyz) * NN + L * rest;
+#pragma unroll
+        for (int B0 = 0; B0 < L; ++B0) in[k][B0] = src[B0];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < RX; ++k) {
+        const int ln = tid + k * kM2MThreads;
+        if (ln >= nv * 4 * LL) continue;
+        const int v = ln / (4 * LL), rem = ln - v * 4 * LL, cyz = rem / LL, rest = rem - cyz * LL;
+        double* dst = X + (v * 8 + 2 * cyz) * NN + L * rest;
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx)
+#pragma unroll
+          for (int b0 = 0; b0 < L; ++b0) {
+            double a = 0.0;
+#pragma unroll
+            for (int B0 = 0; B0 < L; ++B0) a += Sm[(cx * L + b0) * L + B0] * in[k][B0];
+            dst[cx * NN + b0] = a;
+          }
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int idx = tid + u * kM2MThreads;
-      if (addr[u] < 0) continue;
-      const int v = idx / (8 * NN), rem = idx - v * 8 * NN, c = rem / NN, beta = rem - c * NN;
-      const int cx = c & 1, cyz = c >> 1;
-      const int b0 = beta % L, rest = beta / L;
-      const double* src = T1 + (v * 4 + cyz) * NN + L * rest;
-      const double* M = sM + cx * L * L + b0 * L;
-      double a = 0.0;
-#pragma unroll
-      for (int B0 = 0; B0 < L; ++B0) a += M[B0] * src[B0];
-      Fc[addr[u]] = old[u] + a;
-    }
-    __syncthreads();
+    for (int u = 0; u < PER; ++u)
+      if (off[u] != ~0u) Fc0[off[u]] = old[u] + X[tid + u * kM2MThreads];
   }
 }
 
@@ -928,17 +1056,24 @@ inline unsigned m2m_blocks(int pl, int nrhs, int nv) {
   const long long g = std::min<long long>(items, 1 << 20);
   return (unsigned)(nrhs <= nv || g < 8 ? g : g / 8 * 8);
 }
+template <int L> M2MMat<L> m2m_mat(const PassGeom& g) {
+  M2MMat<L> S;
+  for (int i = 0; i < 2 * L * L; ++i) S.m[i] = g.h_m2m[i];
+  return S;
+}
 template <int L> struct M2MRun {
   static hipError_t run(const PassGeom& g, int pl, const double* Wc, double* Wp, int nrhs, hipStream_t s) {
     const unsigned blocks = m2m_blocks(pl, nrhs, m2m_nv<L>());
-    hipLaunchKernelGGL((m2m_kernel<L>), dim3(blocks), dim3(kM2MThreads), 0, s, g, pl, Wc, Wp, nrhs);
+    const M2MMat<L> S = m2m_mat<L>(g);
+    hipLaunchKernelGGL((m2m_kernel<L>), dim3(blocks), dim3(kM2MThreads), 0, s, S, pl, Wc, Wp, nrhs);
     return hipGetLastError();
   }
 };
 template <int L> struct L2LRun {
   static hipError_t run(const PassGeom& g, int pl, const double* Fp, double* Fc, int nrhs, hipStream_t s) {
     const unsigned blocks = m2m_blocks(pl, nrhs, m2m_nv<L>());
-    hipLaunchKernelGGL((l2l_kernel<L>), dim3(blocks), dim3(kM2MThreads), 0, s, g, pl, Fp, Fc, nrhs);
+    const M2MMat<L> S = m2m_mat<L>(g);
+    hipLaunchKernelGGL((l2l_kernel<L>), dim3(blocks), dim3(kM2MThreads), 0, s, S, pl, Fp, Fc, nrhs);
     return hipGetLastError();
   }
 };
