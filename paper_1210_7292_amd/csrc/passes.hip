@@ -171,15 +171,19 @@ struct PassIter {
 // segment through scalar registers and the LDS serves only the expansions.
 template <int L> struct M2MMat { double m[2 * L * L]; };   // [bit][child node b][parent node B]
 
-template <int L>
-__global__ __launch_bounds__(kM2MThreads) void m2m_kernel(M2MMat<L> S, int parent_level,
+// PAIR: every work item is two adjacent right-hand sides of one parent (nrhs even), read and written
+// as 16-byte pairs by a workgroup of 512 threads; otherwise NV = m2m_nv<L>() vectors of 256 threads.
+template <int L, int NV, bool PAIR>
+__global__ __launch_bounds__(PAIR ? 2 * kM2MThreads : kM2MThreads) void m2m_kernel(M2MMat<L> S, int parent_level,
                                                           const double* __restrict__ Wc,
                                                           double* __restrict__ Wp, int nrhs) {
-  constexpr int NN = L * L * L, LL = L * L, NV = m2m_nv<L>(), TOT = NV * 8 * NN;
-  constexpr int PER = (TOT + kM2MThreads - 1) / kM2MThreads;
-  constexpr int RX = (NV * 4 * LL + kM2MThreads - 1) / kM2MThreads;   // lines per thread, x stage
-  constexpr int RY = (NV * 2 * LL + kM2MThreads - 1) / kM2MThreads;   // y stage
-  constexpr int RZ = (NV * LL + kM2MThreads - 1) / kM2MThreads;       // z stage
+  constexpr int NN = L * L * L, LL = L * L, TOT = NV * 8 * NN;
+  constexpr int NT = PAIR ? 2 * kM2MThreads : kM2MThreads;   // threads
+  static_assert(!PAIR || NV == 2, "pairs of right-hand sides");
+  constexpr int PER = (TOT + NT - 1) / NT;
+  constexpr int RX = (NV * 4 * LL + NT - 1) / NT;   // lines per thread, x stage
+  constexpr int RY = (NV * 2 * LL + NT - 1) / NT;   // y stage
+  constexpr int RZ = (NV * LL + NT - 1) / NT;       // z stage
   // children [v][c][b]; each stage reads its lines into registers, then overwrites the array
   // in place: the x stage as [v][cy + 2 cz][B0 + L b1 + L^2 b2], the y stage as [v][cz][..]
   __shared__ double X[TOT];
@@ -200,20 +204,37 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(M2MMat<L> S, int paren
     const int r0 = (int)(v0 - P0 * nrhs);
     const double* Wc0 = Wc + P0 * 8 * NN * nrhs;
     double* Wp0 = Wp + P0 * NN * nrhs;
-    double t[PER];
+    if constexpr (PAIR) {
+      constexpr int PE = (8 * NN + NT - 1) / NT;
+      double2 t[PE];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int idx = tid + u * kM2MThreads;
-      const int vl = idx / (8 * NN), rest = idx - vl * 8 * NN;
-      const int q = r0 + vl, dp = q / nrhs;
-      const unsigned o = (unsigned)((dp * 8 * NN + rest) * nrhs + (q - dp * nrhs));
-      t[u] = (idx < TOT && vl < nv) ? Wc0[o] : 0.0;
-    }
-    __syncthreads();
+      for (int u = 0; u < PE; ++u) {
+        const int e = tid + u * NT;
+        t[u] = e < 8 * NN ? *reinterpret_cast<const double2*>(Wc0 + (unsigned)(e * nrhs + r0))
+                          : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int idx = tid + u * kM2MThreads;
-      if (idx < TOT) X[idx] = t[u];
+      for (int u = 0; u < PE; ++u) {
+        const int e = tid + u * NT;
+        if (e < 8 * NN) { X[e] = t[u].x; X[8 * NN + e] = t[u].y; }
+      }
+    } else {
+      double t[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * NT;
+        const int vl = idx / (8 * NN), rest = idx - vl * 8 * NN;
+        const int q = r0 + vl, dp = q / nrhs;
+        const unsigned o = (unsigned)((dp * 8 * NN + rest) * nrhs + (q - dp * nrhs));
+        t[u] = (idx < TOT && vl < nv) ? Wc0[o] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * NT;
+        if (idx < TOT) X[idx] = t[u];
+      }
     }
     __syncthreads();
     // x: a line (v, cy + 2 cz, b1 + L b2) holds children cx = 0, 1 along b0 and gives L nodes B0
@@ -222,7 +243,7 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(M2MMat<L> S, int paren
 #pragma unroll
       for (int k = 0; k < RX; ++k) {
         // lanes past the last line read line 0 (always present) and discard it
-        const int ln = tid + k * kM2MThreads < nv * 4 * LL ? tid + k * kM2MThreads : 0;
+        const int ln = tid + k * NT < nv * 4 * LL ? tid + k * NT : 0;
         const int v = ln / (4 * LL), rem = ln - v * 4 * LL, cyz = rem / LL, rest = rem - cyz * LL;
         const double* src = X + (v * 8 + 2 * cyz) * NN + L * rest;
 #pragma unroll
@@ -231,7 +252,7 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(M2MMat<L> S, int paren
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < RX; ++k) {
-        const int ln = tid + k * kM2MThreads;
+        const int ln = tid + k * NT;
         if (ln >= nv * 4 * LL) continue;
         const int v = ln / (4 * LL), rem = ln - v * 4 * LL, cyz = rem / LL, rest = rem - cyz * LL;
         double* dst = X + (v * 4 + cyz) * NN + L * rest;
@@ -253,7 +274,7 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(M2MMat<L> S, int paren
 #pragma unroll
       for (int k = 0; k < RY; ++k) {
         // lanes past the last line read line 0 (always present) and discard it
-        const int ln = tid + k * kM2MThreads < nv * 2 * LL ? tid + k * kM2MThreads : 0;
+        const int ln = tid + k * NT < nv * 2 * LL ? tid + k * NT : 0;
         const int v = ln / (2 * LL), rem = ln - v * 2 * LL, cz = rem / LL, r2 = rem - cz * LL;
         const int B0 = r2 % L, b2 = r2 / L;
         const double* src = X + (v * 4 + 2 * cz) * NN + B0 + LL * b2;
@@ -263,7 +284,7 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(M2MMat<L> S, int paren
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < RY; ++k) {
-        const int ln = tid + k * kM2MThreads;
+        const int ln = tid + k * NT;
         if (ln >= nv * 2 * LL) continue;
         const int v = ln / (2 * LL), rem = ln - v * 2 * LL, cz = rem / LL, r2 = rem - cz * LL;
         const int B0 = r2 % L, b2 = r2 / L;
@@ -283,7 +304,7 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(M2MMat<L> S, int paren
     // z: a line (v, B0 + L B1) holds cz = 0, 1 along b2 and gives the parent's L nodes B2
 #pragma unroll
     for (int k = 0; k < RZ; ++k) {
-      const int ln = tid + k * kM2MThreads;
+      const int ln = tid + k * NT;
       if (ln >= nv * LL) continue;
       const int v = ln / LL, r2 = ln - v * LL;
       const double* src = X + v * 2 * NN + r2;
@@ -305,15 +326,17 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(M2MMat<L> S, int paren
   }
 }
 
-template <int L>
-__global__ __launch_bounds__(kM2MThreads) void l2l_kernel(M2MMat<L> S, int parent_level,
+template <int L, int NV, bool PAIR>
+__global__ __launch_bounds__(PAIR ? 2 * kM2MThreads : kM2MThreads) void l2l_kernel(M2MMat<L> S, int parent_level,
                                                           const double* __restrict__ Fp,
                                                           double* __restrict__ Fc, int nrhs) {
-  constexpr int NN = L * L * L, LL = L * L, NV = m2m_nv<L>(), TOT = NV * 8 * NN;
-  constexpr int PER = (TOT + kM2MThreads - 1) / kM2MThreads;
-  constexpr int RZ = (NV * LL + kM2MThreads - 1) / kM2MThreads;       // lines per thread, z stage
-  constexpr int RY = (NV * 2 * LL + kM2MThreads - 1) / kM2MThreads;   // y stage
-  constexpr int RX = (NV * 4 * LL + kM2MThreads - 1) / kM2MThreads;   // x stage
+  constexpr int NN = L * L * L, LL = L * L, TOT = NV * 8 * NN;
+  constexpr int NT = PAIR ? 2 * kM2MThreads : kM2MThreads;   // threads
+  static_assert(!PAIR || NV == 2, "pairs of right-hand sides");
+  constexpr int PER = (TOT + NT - 1) / NT;
+  constexpr int RZ = (NV * LL + NT - 1) / NT;       // lines per thread, z stage
+  constexpr int RY = (NV * 2 * LL + NT - 1) / NT;   // y stage
+  constexpr int RX = (NV * 4 * LL + NT - 1) / NT;   // x stage
   // parents [v][B] at the front; each stage reads its lines into registers, then overwrites the
   // array in place: z as [v][cz][B0 + L B1 + L^2 b2], y as [v][cy + 2 cz][..], x as [v][c][b]
   __shared__ double X[TOT];
@@ -331,18 +354,29 @@ __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(M2MMat<L> S, int paren
     const int r0 = (int)(v0 - P0 * nrhs);
     double* Fc0 = Fc + P0 * 8 * NN * nrhs;
     const double* Fp0 = Fp + P0 * NN * nrhs;
-    double old[PER];
-    unsigned off[PER];   // ~0u: no child element
+    constexpr int PE = PAIR ? (8 * NN + NT - 1) / NT : 1;
+    double2 old2[PE];   // PAIR: the two right-hand sides of child element e = tid + u NT
+    double old[PAIR ? 1 : PER];
+    unsigned off[PAIR ? 1 : PER];   // ~0u: no child element
+    if constexpr (PAIR) {
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int idx = tid + u * kM2MThreads;
-      const int vl = idx / (8 * NN), rest = idx - vl * 8 * NN;
-      const int q = r0 + vl, dp = q / nrhs;
-      off[u] = (idx < TOT && vl < nv) ? (unsigned)((dp * 8 * NN + rest) * nrhs + (q - dp * nrhs)) : ~0u;
-      old[u] = off[u] != ~0u ? Fc0[off[u]] : 0.0;
+      for (int u = 0; u < PE; ++u) {
+        const int e = tid + u * NT;
+        old2[u] = e < 8 * NN ? *reinterpret_cast<const double2*>(Fc0 + (unsigned)(e * nrhs + r0))
+                             : make_double2(0.0, 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * NT;
+        const int vl = idx / (8 * NN), rest = idx - vl * 8 * NN;
+        const int q = r0 + vl, dp = q / nrhs;
+        off[u] = (idx < TOT && vl < nv) ? (unsigned)((dp * 8 * NN + rest) * nrhs + (q - dp * nrhs)) : ~0u;
+        old[u] = off[u] != ~0u ? Fc0[off[u]] : 0.0;
+      }
     }
     __syncthreads();
-    for (int idx = tid; idx < nv * NN; idx += kM2MThreads) {
+    for (int idx = tid; idx < nv * NN; idx += NT) {
       const int v = idx / NN, beta = idx - v * NN;
       const int q = r0 + v, dp = q / nrhs;
       X[idx] = Fp0[(unsigned)((dp * NN + beta) * nrhs + (q - dp * nrhs))];
@@ -354,7 +388,7 @@ __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(M2MMat<L> S, int paren
 #pragma unroll
       for (int k = 0; k < RZ; ++k) {
         // lanes past the last line read line 0 (always present) and discard it
-        const int ln = tid + k * kM2MThreads < nv * LL ? tid + k * kM2MThreads : 0;
+        const int ln = tid + k * NT < nv * LL ? tid + k * NT : 0;
         const int v = ln / LL, r2 = ln - v * LL;
         const double* src = X + v * NN + r2;
 #pragma unroll
@@ -363,7 +397,7 @@ __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(M2MMat<L> S, int paren
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < RZ; ++k) {
-        const int ln = tid + k * kM2MThreads;
+        const int ln = tid + k * NT;
         if (ln >= nv * LL) continue;
         const int v = ln / LL, r2 = ln - v * LL;
         double* dst = X + v * 2 * NN + r2;
@@ -385,7 +419,7 @@ __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(M2MMat<L> S, int paren
 #pragma unroll
       for (int k = 0; k < RY; ++k) {
         // lanes past the last line read line 0 (always present) and discard it
-        const int ln = tid + k * kM2MThreads < nv * 2 * LL ? tid + k * kM2MThreads : 0;
+        const int ln = tid + k * NT < nv * 2 * LL ? tid + k * NT : 0;
         const int v = ln / (2 * LL), rem = ln - v * 2 * LL, cz = rem / LL, r2 = rem - cz * LL;
         const int B0 = r2 % L, b2 = r2 / L;
         const double* src = X + (v * 2 + cz) * NN + B0 + LL * b2;
@@ -395,7 +429,7 @@ __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(M2MMat<L> S, int paren
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < RY; ++k) {
-        const int ln = tid + k * kM2MThreads;
+        const int ln = tid + k * NT;
         if (ln >= nv * 2 * LL) continue;
         const int v = ln / (2 * LL), rem = ln - v * 2 * LL, cz = rem / LL, r2 = rem - cz * LL;
         const int B0 = r2 % L, b2 = r2 / L;
@@ -418,7 +452,7 @@ __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(M2MMat<L> S, int paren
 #pragma unroll
       for (int k = 0; k < RX; ++k) {
         // lanes past the last line read line 0 (always present) and discard it
-        const int ln = tid + k * kM2MThreads < nv * 4 * LL ? tid + k * kM2MThreads : 0;
+        const int ln = tid + k * NT < nv * 4 * LL ? tid + k * NT : 0;
         const int v = ln / (4 * LL), rem = ln - v * 4 * LL, cyz = rem / LL, rest = rem - cyz * LL;
         const double* src = X + (v * 4 + cyz) * NN + L * rest;
 #pragma unroll
@@ -427,7 +461,7 @@ __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(M2MMat<L> S, int paren
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < RX; ++k) {
-        const int ln = tid + k * kM2MThreads;
+        const int ln = tid + k * NT;
         if (ln >= nv * 4 * LL) continue;
         const int v = ln / (4 * LL), rem = ln - v * 4 * LL, cyz = rem / LL, rest = rem - cyz * LL;
         double* dst = X + (v * 8 + 2 * cyz) * NN + L * rest;
@@ -443,9 +477,19 @@ __global__ __launch_bounds__(kM2MThreads) void l2l_kernel(M2MMat<L> S, int paren
       }
     }
     __syncthreads();
+    if constexpr (PAIR) {
 #pragma unroll
-    for (int u = 0; u < PER; ++u)
-      if (off[u] != ~0u) Fc0[off[u]] = old[u] + X[tid + u * kM2MThreads];
+      for (int u = 0; u < PE; ++u) {
+        const int e = tid + u * NT;
+        if (e >= 8 * NN) continue;
+        const double2 f = make_double2(old2[u].x + X[e], old2[u].y + X[8 * NN + e]);
+        *reinterpret_cast<double2*>(Fc0 + (unsigned)(e * nrhs + r0)) = f;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < PER; ++u)
+        if (off[u] != ~0u) Fc0[off[u]] = old[u] + X[tid + u * NT];
+    }
   }
 }
 
@@ -1063,17 +1107,33 @@ template <int L> M2MMat<L> m2m_mat(const PassGeom& g) {
 }
 template <int L> struct M2MRun {
   static hipError_t run(const PassGeom& g, int pl, const double* Wc, double* Wp, int nrhs, hipStream_t s) {
-    const unsigned blocks = m2m_blocks(pl, nrhs, m2m_nv<L>());
     const M2MMat<L> S = m2m_mat<L>(g);
-    hipLaunchKernelGGL((m2m_kernel<L>), dim3(blocks), dim3(kM2MThreads), 0, s, S, pl, Wc, Wp, nrhs);
+    if constexpr (L == 7) {
+      if (nrhs % 2 == 0) {   // pairs of right-hand sides: 16-byte accesses
+        hipLaunchKernelGGL((m2m_kernel<L, 2, true>), dim3(m2m_blocks(pl, nrhs, 2)), dim3(2 * kM2MThreads), 0, s,
+                           S, pl, Wc, Wp, nrhs);
+        return hipGetLastError();
+      }
+    }
+    const unsigned blocks = m2m_blocks(pl, nrhs, m2m_nv<L>());
+    hipLaunchKernelGGL((m2m_kernel<L, m2m_nv<L>(), false>), dim3(blocks), dim3(kM2MThreads), 0, s, S, pl, Wc, Wp,
+                       nrhs);
     return hipGetLastError();
   }
 };
 template <int L> struct L2LRun {
   static hipError_t run(const PassGeom& g, int pl, const double* Fp, double* Fc, int nrhs, hipStream_t s) {
-    const unsigned blocks = m2m_blocks(pl, nrhs, m2m_nv<L>());
     const M2MMat<L> S = m2m_mat<L>(g);
-    hipLaunchKernelGGL((l2l_kernel<L>), dim3(blocks), dim3(kM2MThreads), 0, s, S, pl, Fp, Fc, nrhs);
+    if constexpr (L == 7) {
+      if (nrhs % 2 == 0) {
+        hipLaunchKernelGGL((l2l_kernel<L, 2, true>), dim3(m2m_blocks(pl, nrhs, 2)), dim3(2 * kM2MThreads), 0, s,
+                           S, pl, Fp, Fc, nrhs);
+        return hipGetLastError();
+      }
+    }
+    const unsigned blocks = m2m_blocks(pl, nrhs, m2m_nv<L>());
+    hipLaunchKernelGGL((l2l_kernel<L, m2m_nv<L>(), false>), dim3(blocks), dim3(kM2MThreads), 0, s, S, pl, Fp, Fc,
+                       nrhs);
     return hipGetLastError();
   }
 };

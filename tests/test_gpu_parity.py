@@ -200,9 +200,10 @@ def test_aca_adjoint_and_gradient_match_oracle():
 
 
 # (order, right-hand sides): M2M and L2L with several right-hand sides per parent, where a
-# workgroup takes all of them at once (2 at order 4) or one or a few per pass (4 at orders 5 and
-# 7, 3 at order 6, 30 at order 4)
-@pytest.mark.parametrize("order,nrhs", [(4, 2), (5, 4), (6, 3), (7, 4), (4, 30)])
+# workgroup takes all of them at once (2 at order 4) or one or a few per pass (4 at order 5, 3 at
+# order 6, 30 at order 4); at order 7 an even count goes in pairs of right-hand sides (2, 4) and
+# an odd one singly (3)
+@pytest.mark.parametrize("order,nrhs", [(4, 2), (5, 4), (6, 3), (7, 4), (7, 2), (7, 3), (4, 30)])
 def test_passes_match_oracle(order, nrhs):
     say("passes", order, nrhs)
     pts, q = cube(3000, nrhs, 5)
