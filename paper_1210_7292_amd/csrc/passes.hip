@@ -55,6 +55,7 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(PassGeom g, const doub
   constexpr int NN = L * L * L, LL = L * L, PASS = kP2MThreads * kP2MUnits;
   __shared__ double stk[L * L];
   __shared__ double sb[kP2MBatch][3][L];
+  static_assert(kP2MBatch * 3 >= kP2MThreads && kP2MThreads % RC == 0, "P2M output stage");
   __shared__ double sq[kP2MBatch * RC];
   __shared__ int sls[PASS + 1];   // the group's leaf starts (G <= PASS)
   const int tid = threadIdx.x;
@@ -113,12 +114,33 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(PassGeom g, const doub
           }
         }
       }
+      if (RC <= 2 && rc == nrhs) {
+        // All right-hand sides in this launch: the outputs of the units u0 + v PASS/kP2MUnits + t,
+        // t < 256, are one contiguous range of W. They go through LDS (the basis table, idle until
+        // the next pass) so that the stores are coalesced. With 4 or more right-hand sides the
+        // direct stores already write 32-byte pieces, and the staging costs more than it saves.
+        double* stage = &sb[0][0][0];   // kP2MBatch 3 L >= L kP2MThreads doubles
+        const int valid = ng * LL * RC;
 #pragma unroll
-      for (int v = 0; v < kP2MUnits; ++v) {
-        if (!ok[v]) continue;
-        double* Wl = W + ((long long)(leaf0 + lg[v]) * NN + L * (a1[v] + L * a2[v])) * nrhs + r0 + rr[v];
+        for (int v = 0; v < kP2MUnits; ++v) {
+          const int h0 = u0 + v * kP2MThreads, nval = min(kP2MThreads, valid - h0);
+          __syncthreads();
+          if (ok[v]) {
 #pragma unroll
-        for (int a0 = 0; a0 < L; ++a0) Wl[(long long)a0 * nrhs] = acc[v][a0];
+            for (int a0 = 0; a0 < L; ++a0) stage[L * (tid - rr[v]) + RC * a0 + rr[v]] = acc[v][a0];
+          }
+          __syncthreads();
+          double* Wh = W + ((long long)leaf0 * NN * RC + (long long)L * h0);
+          for (int i = tid; i < L * nval; i += kP2MThreads) Wh[i] = stage[i];
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < kP2MUnits; ++v) {
+          if (!ok[v]) continue;
+          double* Wl = W + ((long long)(leaf0 + lg[v]) * NN + L * (a1[v] + L * a2[v])) * nrhs + r0 + rr[v];
+#pragma unroll
+          for (int a0 = 0; a0 < L; ++a0) Wl[(long long)a0 * nrhs] = acc[v][a0];
+        }
       }
     }
   }
