@@ -83,134 +83,196 @@ __global__ __launch_bounds__(64 * kAdP2MWaves) void ad_p2m_kernel(AdaptiveGeom g
 constexpr int kAdM2MThreads = 128;
 constexpr int kAdM2MBuf = 2048;    // doubles per LDS stage buffer
 
+// The 2 l^2 interpolation entries, passed by value so that the contractions take them from
+// scalar registers ([octant bit][child node b][parent node B]).
+template <int L> struct AdM2MMat { double m[2 * L * L]; };
+
+// Each 1-D contraction is register-blocked: a thread takes one line of l nodes along the axis (for
+// one right-hand side) into registers and produces the line's l outputs, so every LDS value is
+// read once per stage. The x lines of the first two buffers are padded by rc values, so that the
+// lanes of a wave, which read or write l values at a stride of rc, spread over the banks.
 template <int L, int RC>
-__global__ __launch_bounds__(kAdM2MThreads) void ad_m2m_kernel(AdaptiveGeom g, int node_begin, int node_end,
-                                                               double* __restrict__ W, int nrhs) {
-  constexpr int NN = L * L * L;
-  constexpr int OUT = (NN * RC + kAdM2MThreads - 1) / kAdM2MThreads;
-  __shared__ double sM[2 * L * L];
-  __shared__ double bufA[NN * RC], bufB[NN * RC], bufC[NN * RC];
-  for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) sM[i] = g.m2m[i];
-  __syncthreads();
+__global__ __launch_bounds__(kAdM2MThreads) void ad_m2m_kernel(AdaptiveGeom g, AdM2MMat<L> S, int node_begin,
+                                                               int node_end, double* __restrict__ W, int nrhs) {
+  constexpr int NN = L * L * L, LL = L * L, T = kAdM2MThreads;
+  constexpr int RL = (LL * RC + T - 1) / T;   // lines per thread and stage
+  __shared__ double bufA[(NN + LL) * RC], bufB[(NN + LL) * RC], bufC[NN * RC];
   for (int P = node_begin + blockIdx.x; P < node_end; P += gridDim.x) {
     const int cb = g.child_begin[P], ce = g.child_end[P];
     if (cb == ce) continue;                       // a leaf: its multipole comes from P2M
     for (int r0 = 0; r0 < nrhs; r0 += RC) {
       const int rc = min(RC, nrhs - r0);
-      const int tot = NN * rc;
-      double acc[OUT];
+      const int tot = NN * rc, lines = LL * rc;
+      double acc[RL][L];   // z-stage line (B0 + L B1, rr): the parent's L nodes B2
 #pragma unroll
-      for (int u = 0; u < OUT; ++u) acc[u] = 0.0;
+      for (int k = 0; k < RL; ++k)
+#pragma unroll
+        for (int j = 0; j < L; ++j) acc[k][j] = 0.0;
       for (int ch = cb; ch < ce; ++ch) {
         const int o = g.oct[ch];
-        const int cx = o & 1, cy = (o >> 1) & 1, cz = (o >> 2) & 1;
         const double* src = W + (long long)ch * NN * nrhs;
         __syncthreads();
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        for (int idx = threadIdx.x; idx < tot; idx += T) {
           const int beta = idx / rc, rr = idx - beta * rc;
-          bufA[idx] = src[beta * nrhs + r0 + rr];
+          bufA[idx + (beta / L) * rc] = src[beta * nrhs + r0 + rr];
         }
         __syncthreads();
-        const double* M0 = sM + cx * L * L;   // [b'][B]
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          const int B0 = beta % L, rest = beta / L;
-          double s = 0.0;
+        // x: line (rest = b1 + L b2, rr) -> B0
+        const double* M0 = S.m + (o & 1) * LL;
 #pragma unroll
-          for (int b0 = 0; b0 < L; ++b0) s += M0[b0 * L + B0] * bufA[(b0 + L * rest) * rc + rr];
-          bufB[idx] = s;
-        }
-        __syncthreads();
-        const double* M1 = sM + cy * L * L;
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          const int B0 = beta % L, B1 = (beta / L) % L, b2 = beta / (L * L);
-          double s = 0.0;
+        for (int k = 0; k < RL; ++k) {
+          const int ln = threadIdx.x + k * T;
+          if (ln >= lines) continue;
+          const int rest = ln / rc, rr = ln - rest * rc;
+          const double* in = bufA + rest * (L + 1) * rc + rr;
+          double a[L];
 #pragma unroll
-          for (int b1 = 0; b1 < L; ++b1) s += M1[b1 * L + B1] * bufB[(B0 + L * b1 + L * L * b2) * rc + rr];
-          bufC[idx] = s;
-        }
-        __syncthreads();
-        const double* M2 = sM + cz * L * L;
+          for (int j = 0; j < L; ++j) a[j] = 0.0;
 #pragma unroll
-        for (int u = 0; u < OUT; ++u) {
-          const int idx = threadIdx.x + u * kAdM2MThreads;
-          if (idx < tot) {
-            const int beta = idx / rc, rr = idx - beta * rc;
-            const int B0 = beta % L, B1 = (beta / L) % L, B2 = beta / (L * L);
-            double s = 0.0;
+          for (int b0 = 0; b0 < L; ++b0) {
+            const double x = in[b0 * rc];
 #pragma unroll
-            for (int b2 = 0; b2 < L; ++b2) s += M2[b2 * L + B2] * bufC[(B0 + L * B1 + L * L * b2) * rc + rr];
-            acc[u] += s;
+            for (int B0 = 0; B0 < L; ++B0) a[B0] += M0[b0 * L + B0] * x;
           }
+#pragma unroll
+          for (int B0 = 0; B0 < L; ++B0) bufB[(rest * (L + 1) + B0) * rc + rr] = a[B0];
+        }
+        __syncthreads();
+        // y: line (B0, b2, rr) -> B1
+        const double* M1 = S.m + ((o >> 1) & 1) * LL;
+#pragma unroll
+        for (int k = 0; k < RL; ++k) {
+          const int ln = threadIdx.x + k * T;
+          if (ln >= lines) continue;
+          const int q = ln / rc, rr = ln - q * rc, B0 = q % L, b2 = q / L;
+          const double* in = bufB + (B0 + (LL + L) * b2) * rc + rr;
+          double a[L];
+#pragma unroll
+          for (int j = 0; j < L; ++j) a[j] = 0.0;
+#pragma unroll
+          for (int b1 = 0; b1 < L; ++b1) {
+            const double x = in[(L + 1) * b1 * rc];
+#pragma unroll
+            for (int B1 = 0; B1 < L; ++B1) a[B1] += M1[b1 * L + B1] * x;
+          }
+#pragma unroll
+          for (int B1 = 0; B1 < L; ++B1) bufC[(B0 + L * B1 + LL * b2) * rc + rr] = a[B1];
+        }
+        __syncthreads();
+        // z: line (B0 + L B1, rr) -> B2, summed over the children in registers
+        const double* M2 = S.m + ((o >> 2) & 1) * LL;
+#pragma unroll
+        for (int k = 0; k < RL; ++k) {
+          const int ln = threadIdx.x + k * T;
+          if (ln >= lines) continue;
+          const int q = ln / rc, rr = ln - q * rc;
+          const double* in = bufC + q * rc + rr;
+          double a[L];
+#pragma unroll
+          for (int j = 0; j < L; ++j) a[j] = 0.0;
+#pragma unroll
+          for (int b2 = 0; b2 < L; ++b2) {
+            const double x = in[LL * b2 * rc];
+#pragma unroll
+            for (int B2 = 0; B2 < L; ++B2) a[B2] += M2[b2 * L + B2] * x;
+          }
+#pragma unroll
+          for (int B2 = 0; B2 < L; ++B2) acc[k][B2] += a[B2];
         }
       }
-      double* dst = W + (long long)P * NN * nrhs;
+      double* dst = W + (long long)P * NN * nrhs + r0;
 #pragma unroll
-      for (int u = 0; u < OUT; ++u) {
-        const int idx = threadIdx.x + u * kAdM2MThreads;
-        if (idx < tot) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          dst[beta * nrhs + r0 + rr] = acc[u];
-        }
+      for (int k = 0; k < RL; ++k) {
+        const int ln = threadIdx.x + k * T;
+        if (ln >= lines) continue;
+        const int q = ln / rc, rr = ln - q * rc;
+#pragma unroll
+        for (int B2 = 0; B2 < L; ++B2) dst[(q + LL * B2) * nrhs + rr] = acc[k][B2];
       }
     }
   }
 }
 
 template <int L, int RC>
-__global__ __launch_bounds__(kAdM2MThreads) void ad_l2l_kernel(AdaptiveGeom g, int node_begin, int node_end,
-                                                               double* __restrict__ F, int nrhs) {
-  constexpr int NN = L * L * L;
-  __shared__ double sM[2 * L * L];
-  __shared__ double bufA[NN * RC], bufB[NN * RC], bufC[NN * RC];
-  for (int i = threadIdx.x; i < 2 * L * L; i += blockDim.x) sM[i] = g.m2m[i];
-  __syncthreads();
+__global__ __launch_bounds__(kAdM2MThreads) void ad_l2l_kernel(AdaptiveGeom g, AdM2MMat<L> S, int node_begin,
+                                                               int node_end, double* __restrict__ F, int nrhs) {
+  constexpr int NN = L * L * L, LL = L * L, T = kAdM2MThreads;
+  constexpr int RL = (LL * RC + T - 1) / T;
+  __shared__ double bufA[(NN + LL) * RC], bufB[(NN + LL) * RC], bufC[NN * RC];
   for (int P = node_begin + blockIdx.x; P < node_end; P += gridDim.x) {
     const int cb = g.child_begin[P], ce = g.child_end[P];
     if (cb == ce) continue;
     for (int r0 = 0; r0 < nrhs; r0 += RC) {
       const int rc = min(RC, nrhs - r0);
-      const int tot = NN * rc;
+      const int tot = NN * rc, lines = LL * rc;
       const double* src = F + (long long)P * NN * nrhs;
       __syncthreads();
-      for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+      for (int idx = threadIdx.x; idx < tot; idx += T) {
         const int beta = idx / rc, rr = idx - beta * rc;
-        bufA[idx] = src[beta * nrhs + r0 + rr];
+        bufA[idx + (beta / L) * rc] = src[beta * nrhs + r0 + rr];
       }
       for (int ch = cb; ch < ce; ++ch) {
         const int o = g.oct[ch];
-        const int cx = o & 1, cy = (o >> 1) & 1, cz = (o >> 2) & 1;
         __syncthreads();
-        const double* M0 = sM + cx * L * L;
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          const int b0 = beta % L, rest = beta / L;
-          double s = 0.0;
+        // x: parent line (rest = B1 + L B2, rr) over B0 -> the child's b0
+        const double* M0 = S.m + (o & 1) * LL;
 #pragma unroll
-          for (int B0 = 0; B0 < L; ++B0) s += M0[b0 * L + B0] * bufA[(B0 + L * rest) * rc + rr];
-          bufB[idx] = s;
+        for (int k = 0; k < RL; ++k) {
+          const int ln = threadIdx.x + k * T;
+          if (ln >= lines) continue;
+          const int rest = ln / rc, rr = ln - rest * rc;
+          const double* in = bufA + rest * (L + 1) * rc + rr;
+          double x[L];
+#pragma unroll
+          for (int B0 = 0; B0 < L; ++B0) x[B0] = in[B0 * rc];
+#pragma unroll
+          for (int b0 = 0; b0 < L; ++b0) {
+            double s = 0.0;
+#pragma unroll
+            for (int B0 = 0; B0 < L; ++B0) s += M0[b0 * L + B0] * x[B0];
+            bufB[(rest * (L + 1) + b0) * rc + rr] = s;
+          }
         }
         __syncthreads();
-        const double* M1 = sM + cy * L * L;
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          const int b0 = beta % L, b1 = (beta / L) % L, B2 = beta / (L * L);
-          double s = 0.0;
+        // y: line (b0, B2, rr) over B1 -> b1
+        const double* M1 = S.m + ((o >> 1) & 1) * LL;
 #pragma unroll
-          for (int B1 = 0; B1 < L; ++B1) s += M1[b1 * L + B1] * bufB[(b0 + L * B1 + L * L * B2) * rc + rr];
-          bufC[idx] = s;
+        for (int k = 0; k < RL; ++k) {
+          const int ln = threadIdx.x + k * T;
+          if (ln >= lines) continue;
+          const int q = ln / rc, rr = ln - q * rc, b0 = q % L, B2 = q / L;
+          const double* in = bufB + (b0 + (LL + L) * B2) * rc + rr;
+          double x[L];
+#pragma unroll
+          for (int B1 = 0; B1 < L; ++B1) x[B1] = in[(L + 1) * B1 * rc];
+#pragma unroll
+          for (int b1 = 0; b1 < L; ++b1) {
+            double s = 0.0;
+#pragma unroll
+            for (int B1 = 0; B1 < L; ++B1) s += M1[b1 * L + B1] * x[B1];
+            bufC[(b0 + L * b1 + LL * B2) * rc + rr] = s;
+          }
         }
         __syncthreads();
-        const double* M2 = sM + cz * L * L;
-        double* dst = F + (long long)ch * NN * nrhs;
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-          const int beta = idx / rc, rr = idx - beta * rc;
-          const int b0 = beta % L, b1 = (beta / L) % L, b2 = beta / (L * L);
-          double s = 0.0;
+        // z: line (b0 + L b1, rr) over B2 -> b2, added into the child's locals
+        const double* M2 = S.m + ((o >> 2) & 1) * LL;
+        double* dst = F + (long long)ch * NN * nrhs + r0;
 #pragma unroll
-          for (int B2 = 0; B2 < L; ++B2) s += M2[b2 * L + B2] * bufC[(b0 + L * b1 + L * L * B2) * rc + rr];
-          dst[beta * nrhs + r0 + rr] += s;
+        for (int k = 0; k < RL; ++k) {
+          const int ln = threadIdx.x + k * T;
+          if (ln >= lines) continue;
+          const int q = ln / rc, rr = ln - q * rc;
+          const double* in = bufC + q * rc + rr;
+          double x[L];
+#pragma unroll
+          for (int B2 = 0; B2 < L; ++B2) x[B2] = in[LL * B2 * rc];
+#pragma unroll
+          for (int b2 = 0; b2 < L; ++b2) {
+            double s = 0.0;
+#pragma unroll
+            for (int B2 = 0; B2 < L; ++B2) s += M2[b2 * L + B2] * x[B2];
+            dst[(q + LL * b2) * nrhs + rr] += s;
+          }
         }
       }
     }
@@ -501,11 +563,16 @@ template <int L> struct AdP2M {
   }
 };
 
+template <int L> AdM2MMat<L> ad_m2m_mat(const AdaptiveGeom& g) {
+  AdM2MMat<L> S;
+  for (int i = 0; i < 2 * L * L; ++i) S.m[i] = g.h_m2m[i];
+  return S;
+}
 template <int L> struct AdM2M {
   template <int RC>
   static void go(const AdaptiveGeom& g, int b, int e, double* W, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL((ad_m2m_kernel<L, RC>), dim3(grid_of(e - b, 1 << 20)), dim3(kAdM2MThreads), 0, s, g, b,
-                       e, W, nrhs);
+    hipLaunchKernelGGL((ad_m2m_kernel<L, RC>), dim3(grid_of(e - b, 1 << 20)), dim3(kAdM2MThreads), 0, s, g,
+                       ad_m2m_mat<L>(g), b, e, W, nrhs);
   }
   static hipError_t run(const AdaptiveGeom& g, int b, int e, double* W, int nrhs, hipStream_t s) {
     if (e <= b) return hipSuccess;
@@ -524,8 +591,8 @@ template <int L> struct AdM2M {
 template <int L> struct AdL2L {
   template <int RC>
   static void go(const AdaptiveGeom& g, int b, int e, double* F, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL((ad_l2l_kernel<L, RC>), dim3(grid_of(e - b, 1 << 20)), dim3(kAdM2MThreads), 0, s, g, b,
-                       e, F, nrhs);
+    hipLaunchKernelGGL((ad_l2l_kernel<L, RC>), dim3(grid_of(e - b, 1 << 20)), dim3(kAdM2MThreads), 0, s, g,
+                       ad_m2m_mat<L>(g), b, e, F, nrhs);
   }
   static hipError_t run(const AdaptiveGeom& g, int b, int e, double* F, int nrhs, hipStream_t s) {
     if (e <= b) return hipSuccess;

@@ -197,7 +197,7 @@ AdaptiveGeom ageom_of(const bbfmm_plan* pl) {
   g.n = t->n;
   g.start = t->d_start; g.end = t->d_end; g.cen = t->d_cen;
   g.child_begin = t->d_child_begin; g.child_end = t->d_child_end; g.oct = t->d_oct;
-  g.tk = pl->d_tk; g.m2m = pl->d_m2m;
+  g.tk = pl->d_tk; g.m2m = pl->d_m2m; g.h_m2m = pl->h_m2m.data();
   g.order = pl->order; g.kernel = pl->kernel; g.c = pl->c;
   return g;
 }

@@ -250,6 +250,7 @@ struct AdaptiveGeom {
   const int* child_begin; const int* child_end;
   const unsigned char* oct;                                // octant of each node in its parent
   const double* tk; const double* m2m;
+  const double* h_m2m;   // host copy of m2m (passed by value to the M2M / L2L kernels)
   int order; int kernel; double c;
 };
 // Kernel fill (not a memset, so that the call may sit in a captured graph).
