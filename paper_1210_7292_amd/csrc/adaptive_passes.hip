@@ -16,32 +16,46 @@ namespace bbfmm {
 namespace {
 
 // ---- P2M over the leaf list: one wave per leaf -------------------------------------------
+// Separable: a lane owns units (a1, a2, r) of the leaf and accumulates their L outputs a0, so a
+// point's S(y, a1) S(z, a2) q[r] is formed once per unit and its L basis values S(x, a0) once per
+// lane. kAdP2MUnits units per lane per pass; the basis values of a batch of the leaf's points
+// are computed once per pass into the wave's LDS.
 constexpr int kAdP2MWaves = 4;
 constexpr int kAdP2MBatch = 16;
-constexpr int kAdP2MOut = 8;
+constexpr int kAdP2MUnits = 4;
 
 template <int L>
 __global__ __launch_bounds__(64 * kAdP2MWaves) void ad_p2m_kernel(AdaptiveGeom g, const int* __restrict__ leaves,
                                                                   int nleaves, const double* __restrict__ qs,
                                                                   int nrhs, double* __restrict__ W) {
-  constexpr int NN = L * L * L;
+  constexpr int NN = L * L * L, LL = L * L, K = kAdP2MUnits;
   __shared__ double sb[kAdP2MWaves][kAdP2MBatch][3][L];
   __shared__ double stk[L * L];
   for (int i = threadIdx.x; i < L * L; i += blockDim.x) stk[i] = g.tk[i];
   __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int nout = NN * nrhs;
+  const int units = LL * nrhs;
   for (int li = blockIdx.x * kAdP2MWaves + wave; li < nleaves; li += gridDim.x * kAdP2MWaves) {
     const int node = leaves[li];
     const int s = g.start[node], e = g.end[node];
-    double* Wl = W + (long long)node * nout;
+    double* Wl = W + (long long)node * NN * nrhs;
     const double* cp = g.cen + 4LL * node;
     const double c[3] = {cp[0], cp[1], cp[2]};
     const double inv_half = 1.0 / cp[3];
-    for (int o0 = 0; o0 < nout; o0 += 64 * kAdP2MOut) {
-      double acc[kAdP2MOut];
+    for (int w0 = 0; w0 < units; w0 += 64 * K) {
+      int a1[K], a2[K], rr[K];
+      bool ok[K];
+      double acc[K][L];
 #pragma unroll
-      for (int u = 0; u < kAdP2MOut; ++u) acc[u] = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const int w = w0 + lane + 64 * k, m = w / nrhs;
+        ok[k] = w < units;
+        rr[k] = w - m * nrhs;
+        a1[k] = m % L;
+        a2[k] = ok[k] ? m / L : 0;
+#pragma unroll
+        for (int a0 = 0; a0 < L; ++a0) acc[k][a0] = 0.0;
+      }
       for (int b0 = s; b0 < e; b0 += kAdP2MBatch) {
         const int nb = min(kAdP2MBatch, e - b0);
         if (lane < nb * 3) {
@@ -53,17 +67,17 @@ __global__ __launch_bounds__(64 * kAdP2MWaves) void ad_p2m_kernel(AdaptiveGeom g
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        for (int jj = 0; jj < nb; ++jj) {
+          double s0[L];
 #pragma unroll
-        for (int u = 0; u < kAdP2MOut; ++u) {
-          const int o = o0 + lane + 64 * u;
-          if (o < nout) {
-            const int beta = o / nrhs, r = o - beta * nrhs;
-            const int a0 = beta % L, a1 = (beta / L) % L, a2 = beta / (L * L);
-            double t = 0.0;
-            for (int jj = 0; jj < nb; ++jj)
-              t += sb[wave][jj][0][a0] * sb[wave][jj][1][a1] * sb[wave][jj][2][a2] *
-                   qs[(long long)(b0 + jj) * nrhs + r];
-            acc[u] += t;
+          for (int a0 = 0; a0 < L; ++a0) s0[a0] = sb[wave][jj][0][a0];
+          const double* qj = qs + (long long)(b0 + jj) * nrhs;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            if (!ok[k]) continue;
+            const double wq = sb[wave][jj][1][a1[k]] * sb[wave][jj][2][a2[k]] * qj[rr[k]];
+#pragma unroll
+            for (int a0 = 0; a0 < L; ++a0) acc[k][a0] += wq * s0[a0];
           }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -71,9 +85,11 @@ __global__ __launch_bounds__(64 * kAdP2MWaves) void ad_p2m_kernel(AdaptiveGeom g
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       }
 #pragma unroll
-      for (int u = 0; u < kAdP2MOut; ++u) {
-        const int o = o0 + lane + 64 * u;
-        if (o < nout) Wl[o] = acc[u];
+      for (int k = 0; k < K; ++k) {
+        if (!ok[k]) continue;
+        double* dst = Wl + (long long)L * (a1[k] + L * a2[k]) * nrhs + rr[k];
+#pragma unroll
+        for (int a0 = 0; a0 < L; ++a0) dst[(long long)a0 * nrhs] = acc[k][a0];
       }
     }
   }
