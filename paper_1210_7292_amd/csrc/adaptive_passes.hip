@@ -432,7 +432,8 @@ __global__ __launch_bounds__(kAdL2PThreads) void ad_l2p_kernel(AdaptiveGeom g, c
   }
 }
 
-// ---- M2P over the W list: one block per leaf, threads over its points ----------------------
+// ---- M2P over the W list: one block per leaf, threads over its points and, in small leaves, -----
+// ---- also over the interpolation points of each W entry ------------------------------------
 constexpr int kAdM2PThreads = 128;
 constexpr int kAdM2PChunk = 128;     // interpolation points staged per step
 
@@ -445,16 +446,23 @@ __global__ __launch_bounds__(kAdM2PThreads) void ad_m2p_kernel(AdaptiveGeom g, c
   constexpr int NN = L * L * L;
   __shared__ double sy[kAdM2PChunk][3];
   __shared__ double sw[kAdM2PChunk][RC];
+  __shared__ double sred[kAdM2PThreads][RC];   // per-thread partial sums
   const int lp = blockIdx.x;
   const int w0 = w_off[lp], w1 = w_off[lp + 1];
   if (w0 == w1) return;
   const int tid = threadIdx.x;
   const int b = leaves[lp];
   const int s = g.start[b], e = g.end[b];
+  if (e <= s) return;
   const double c2 = kernel_param<KIND>(g.c);
-  for (int i0 = s; i0 < e; i0 += kAdM2PThreads) {
-    const int i = i0 + tid;
-    const bool vi = i < e;
+  // A leaf of fewer points than threads: G groups of P threads (one per point), group grp takes
+  // every G-th interpolation point of a chunk, and the groups' partial sums are added in group
+  // order (the same result on every run).
+  const int P = min(e - s, kAdM2PThreads), G = kAdM2PThreads / P;
+  const int grp = tid / P, p = tid - grp * P;
+  for (int i0 = s; i0 < e; i0 += P) {
+    const int i = i0 + p;
+    const bool vi = grp < G && i < e;
     const double xi = vi ? g.xs[i] : 0.0, yi = vi ? g.ys[i] : 0.0, zi = vi ? g.zs[i] : 0.0;
     double acc[RC];
 #pragma unroll
@@ -477,7 +485,7 @@ __global__ __launch_bounds__(kAdM2PThreads) void ad_m2p_kernel(AdaptiveGeom g, c
         }
         __syncthreads();
         if (vi) {
-          for (int bb = 0; bb < nb; ++bb) {
+          for (int bb = grp; bb < nb; bb += G) {
             const double dx = xi - sy[bb][0], dy = yi - sy[bb][1], dz = zi - sy[bb][2];
             const double kv = kern<KIND>(dx * dx + dy * dy + dz * dz, c2);
 #pragma unroll
@@ -486,11 +494,18 @@ __global__ __launch_bounds__(kAdM2PThreads) void ad_m2p_kernel(AdaptiveGeom g, c
         }
       }
     }
-    if (vi) {
 #pragma unroll
-      for (int r = 0; r < RC; ++r)
-        if (r0 + r < nrhs) phis[(long long)i * nrhs + r0 + r] += acc[r];
+    for (int r = 0; r < RC; ++r) sred[tid][r] = acc[r];
+    __syncthreads();
+    if (grp == 0 && i < e) {
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+        double t = sred[p][r];
+        for (int q = 1; q < G; ++q) t += sred[q * P + p][r];
+        if (r0 + r < nrhs) phis[(long long)i * nrhs + r0 + r] += t;
+      }
     }
+    __syncthreads();
   }
 }
 
